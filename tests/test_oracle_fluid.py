@@ -1,0 +1,301 @@
+"""Pins of the CPU oracle's fluid part against facts the paper and the
+mathematics fix (no GPU). Each test names the passage or result it checks."""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _lat(oracle_mod):
+    return oracle_mod.lattice()
+
+
+def test_lattice_is_d3q19(oracle_mod):
+    """Velocity set and weights are the D3Q19 constants (golden fixture);
+    2nd and 4th order isotropy: sum w c_a c_b = cs2 d_ab,
+    sum w c_a c_b c_c c_d = cs2^2 (d_ab d_cd + d_ac d_bd + d_ad d_bc)."""
+    g = json.load(open(os.path.join(GOLD, "d3q19_lattice.json")))
+    c, w = _lat(oracle_mod)
+    assert len({tuple(v) for v in c}) == 19
+    sp = (c ** 2).sum(1)
+    for cl in g["classes"]:
+        sel = sp == cl["speed2"]
+        assert sel.sum() == cl["count"]
+        assert np.all(w[sel] == cl["weight"][0] / cl["weight"][1])
+    cs2 = g["cs2"][0] / g["cs2"][1]
+    assert abs(w.sum() - 1) < 1e-15
+    assert np.allclose(np.einsum("i,ia->a", w, c), 0, atol=1e-16)
+    assert np.allclose(np.einsum("i,ia,ib->ab", w, c, c), cs2 * np.eye(3), atol=1e-16)
+    d = np.eye(3)
+    t4 = np.einsum("i,ia,ib,ic,id->abcd", w, c, c, c, c)
+    iso = cs2 ** 2 * (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d) + np.einsum("ad,bc->abcd", d, d))
+    assert np.allclose(t4, iso, atol=1e-16)
+    assert int((c[1:, 0] ** 2).sum()) == g["sum_c_cx_cx_over_moving_links"]
+
+
+def test_feq_moments(oracle_mod):
+    """Closed form: the equilibrium's moments are rho, rho u, rho cs2 I + rho u u."""
+    c, _ = _lat(oracle_mod)
+    rng = np.random.default_rng(7)
+    for _ in range(50):
+        rho = rng.uniform(0.01, 2.0)
+        u = rng.uniform(-0.1, 0.1, 3)
+        f = oracle_mod.feq(rho, u)
+        assert abs(f.sum() - rho) <= 1e-15 * rho * 4
+        assert np.allclose(f @ c, rho * u, atol=4e-16 * rho, rtol=0)
+        P = np.einsum("i,ia,ib->ab", f, c, c)
+        assert np.allclose(P, rho / 3 * np.eye(3) + rho * np.outer(u, u), atol=4e-16 * rho, rtol=0)
+
+
+def test_streaming_moves_one_population(oracle_mod):
+    """Eq. (1) without collision: a lone population moves by c_i per step and
+    is back after L steps on a periodic L^3 lattice (bitwise)."""
+    Lx = 5
+    o = oracle_mod.Oracle((Lx, Lx, Lx), 1.0, 0.0)
+    o.init_fields(np.zeros(Lx ** 3), np.zeros(Lx ** 3))
+    c, _ = _lat(oracle_mod)
+    for i in range(19):
+        for comp in (0, 1):
+            f = np.zeros((19, Lx ** 3))
+            x0, y0, z0 = 1, 2, 3
+            n0 = x0 + Lx * (y0 + Lx * z0)
+            f[i, n0] = 0.123
+            o.set_pops(comp, f)
+            o.set_pops(1 - comp, np.zeros((19, Lx ** 3)))
+            o.stream_only()
+            g = o.get_pops(comp)
+            x1, y1, z1 = (x0 + c[i, 0]) % Lx, (y0 + c[i, 1]) % Lx, (z0 + c[i, 2]) % Lx
+            n1 = x1 + Lx * (y1 + Lx * z1)
+            assert g[i, n1] == 0.123 and np.count_nonzero(g) == 1
+            for _ in range(Lx - 1):
+                o.stream_only()
+            assert np.array_equal(o.get_pops(comp), f)
+
+
+def _random_system(oracle_mod, dims, g, seed, tau=1.0, psi_kind=0, u_amp=0.0):
+    o = oracle_mod.Oracle(dims, tau, g, psi_kind)
+    N = int(np.prod(dims))
+    rng = np.random.default_rng(seed)
+    ra = 0.7 + 0.05 * rng.uniform(-1, 1, N)
+    rb = 0.6 + 0.05 * rng.uniform(-1, 1, N)
+    u = u_amp * rng.uniform(-1, 1, (N, 3)) if u_amp else None
+    o.init_fields(ra, rb, u)
+    return o
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.8, 1.7])
+def test_collision_conserves_mass_and_adds_force(oracle_mod, tau):
+    """Eq. (2) with the force of Eq. (3): BGK keeps rho^c at every node, and the
+    node momentum summed over components changes by exactly F^A + F^B."""
+    c, _ = _lat(oracle_mod)
+    o = _random_system(oracle_mod, (6, 5, 7), 0.08, 1, tau=tau, u_amp=0.02)
+    pre = [o.get_pops(k) for k in (0, 1)]
+    o.stage("densities")
+    o.stage("shell")
+    FA, FB = o.sc_force()
+    o.stage("collide")
+    post = [o.get_pops(k) for k in (0, 1)]
+    for k in (0, 1):
+        assert np.allclose(post[k].sum(0), pre[k].sum(0), rtol=0, atol=2e-15)
+    dj = sum(c.T @ (post[k] - pre[k]) for k in (0, 1)).T
+    assert np.allclose(dj, FA + FB, rtol=0, atol=2e-15)
+    assert np.abs(FA + FB).max() > 1e-4
+
+
+def test_collision_tau_one_gives_equilibrium_moments(oracle_mod):
+    """tau = 1: post-collision populations are an equilibrium, so per component
+    the 2nd moment equals rho cs2 I + j j / rho built from their own 0th/1st."""
+    c, _ = _lat(oracle_mod)
+    o = _random_system(oracle_mod, (5, 6, 4), 0.08, 2, u_amp=0.02)
+    o.stage("densities")
+    o.stage("shell")
+    o.stage("collide")
+    for k in (0, 1):
+        f = o.get_pops(k)
+        r = f.sum(0)
+        j = (c.T @ f).T
+        P = np.einsum("in,ia,ib->nab", f, c, c)
+        want = r[:, None, None] / 3 * np.eye(3) + np.einsum("na,nb->nab", j, j) / r[:, None, None]
+        assert np.allclose(P, want, rtol=0, atol=4e-15)
+
+
+def test_sc_force_linear_field_closed_form(oracle_mod):
+    """Eq. (3) over all 18 neighbours: for Psi^B linear in x (no wrap), the
+    neighbour sum is (sum_i c_i c_i) grad Psi^B = 10 grad Psi^B, so
+    F^A = -10 g Psi^A grad Psi^B. Checked for both Psi choices."""
+    dims = (7, 7, 7)
+    N = 343
+    z, y, x = np.meshgrid(np.arange(7), np.arange(7), np.arange(7), indexing="ij")
+    x, y, z = x.ravel(), y.ravel(), z.ravel()
+    grad = np.array([0.011, -0.007, 0.004])
+    g = 0.09
+    for kind in (0, 1):
+        psiB = 0.3 + grad[0] * x + grad[1] * y + grad[2] * z
+        rb = psiB if kind == 0 else -np.log(1.0 - psiB)
+        ra = 0.5 + 0.01 * np.sin(x + 2 * y)
+        o = oracle_mod.Oracle(dims, 1.0, g, kind)
+        o.init_fields(ra, rb)
+        o.stage("densities")
+        o.stage("shell")
+        ri, _ = o.rho_internal()
+        FA, _ = o.sc_force()
+        inner = (x >= 1) & (x <= 5) & (y >= 1) & (y <= 5) & (z >= 1) & (z <= 5)
+        psiA = ri if kind == 0 else 1 - np.exp(-ri)
+        want = -10 * g * psiA[inner, None] * grad[None, :]
+        assert np.allclose(FA[inner], want, rtol=1e-12, atol=1e-17)
+
+
+def test_sc_force_sums_to_zero(oracle_mod):
+    """Pairwise antisymmetry of Eq. (3) on a periodic lattice: the total force
+    summed over nodes AND components vanishes (each component alone does not)."""
+    for kind in (0, 1):
+        o = _random_system(oracle_mod, (8, 6, 5), 0.08, 3 + kind, psi_kind=kind)
+        o.stage("densities")
+        o.stage("shell")
+        FA, FB = o.sc_force()
+        tot = (FA + FB).sum(0)
+        scale = np.abs(FA).sum() + np.abs(FB).sum()
+        assert np.abs(tot).max() <= 1e-13 * scale
+        assert np.abs(FA.sum(0)).max() > 1e-6 * scale
+
+
+def test_mass_and_momentum_conserved_1000_steps(oracle_mod):
+    """No particles: per-component mass and the total momentum are invariants
+    of Eqs. (1)-(3) (the force sums to zero)."""
+    o = _random_system(oracle_mod, (10, 9, 8), 0.08, 5, u_amp=0.01)
+    s0 = o.stats()
+    o.step(1000)
+    s1 = o.stats()
+    assert abs(s1[0] - s0[0]) <= 1e-13 * s0[0]
+    assert abs(s1[1] - s0[1]) <= 1e-13 * s0[1]
+    assert np.abs(s1[2:5] - s0[2:5]).max() <= 1e-12 * (s0[0] + s0[1]) * 0.01
+    assert s1[7] == 0
+
+
+def test_uniform_state_stays_uniform(oracle_mod):
+    """With no noise, F = 0 and the state does not change."""
+    dims = (6, 6, 6)
+    o = oracle_mod.Oracle(dims, 1.0, 0.08)
+    o.init_fields(np.full(216, 0.7), np.full(216, 0.3))
+    f0 = o.get_pops(0)
+    o.step(50)
+    ra, rb, u, _ = o.read_fields()
+    assert np.abs(ra - 0.7).max() < 1e-14 and np.abs(rb - 0.3).max() < 1e-14
+    assert np.abs(u).max() < 1e-15
+    assert np.abs(o.get_pops(0) - f0).max() < 1e-15
+
+
+def _mode_amplitude(o, Lx):
+    ra, rb, _, _ = o.read_fields()
+    phi = (ra - rb).reshape(-1, Lx)  # rows along x
+    x = np.arange(Lx)
+    return (phi * np.sin(2 * np.pi * x / Lx)).sum() / phi.shape[0]
+
+
+def _wave_ratio(oracle_mod, kind, tau, g, steps=800, Lx=32):
+    x = np.tile(np.arange(Lx), 9)
+    d = 1e-4 * np.sin(2 * np.pi * x / Lx)
+    o = oracle_mod.Oracle((Lx, 3, 3), tau, g, kind)
+    o.init_fields(0.7 + d, 0.7 - d)
+    a0 = _mode_amplitude(o, Lx)
+    o.step(steps)
+    return _mode_amplitude(o, Lx) / a0
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("tau", [0.8, 1.0, 1.5])
+def test_demixing_threshold(oracle_mod, kind, tau):
+    """Linear stability of a 50/50 mixture under Eq. (3) (unweighted
+    18-neighbour sum, sum_i c_ix^2 = 10) with the force entering BGK, Eq. (2),
+    as a velocity shift tau F / rho. Per step the relative momentum of a
+    component relaxes to a drift tau F_rel, while ideal-gas pressure drives
+    interdiffusion with D = cs2 (tau - 1/2). A long concentration wave
+    therefore grows iff 10 g Psi Psi' tau > cs2 (tau - 1/2) (derived). Checked
+    at +-10 % around that g for three tau; with Eq. (3) as printed a positive g
+    demixes, and reversing its sign speeds the mixing up."""
+    rho0 = 0.7
+    pp = rho0 if kind == 0 else (1 - math.exp(-rho0)) * math.exp(-rho0)
+    gc = (tau - 0.5) / (30.0 * pp * tau)
+    below = _wave_ratio(oracle_mod, kind, tau, 0.9 * gc)
+    above = _wave_ratio(oracle_mod, kind, tau, 1.1 * gc)
+    free = _wave_ratio(oracle_mod, kind, tau, 0.0)
+    flipped = _wave_ratio(oracle_mod, kind, tau, -1.1 * gc)
+    assert below < 0.95 and above > 1.05, (below, above)
+    assert flipped < free < below, (flipped, free, below)
+
+
+@pytest.mark.parametrize("tau", [0.8, 1.0, 1.5])
+def test_interdiffusion_rate(oracle_mod, tau):
+    """g = 0: a concentration wave of wavenumber k decays at the BGK
+    diffusivity D = cs2 (tau - 1/2) (textbook), using the lattice wavenumber
+    k^2 -> 2 (1 - cos k) of the discrete Laplacian."""
+    Lx, steps = 32, 400
+    k2 = 2 * (1 - math.cos(2 * math.pi / Lx))
+    r = _wave_ratio(oracle_mod, 0, tau, 0.0, steps=steps, Lx=Lx)
+    D = -math.log(r) / (k2 * steps)
+    assert abs(D / ((tau - 0.5) / 3) - 1) < 0.02, D
+
+
+def test_paper_bijel_parameters_phase_separate(oracle_mod):
+    """Sec. 4: g_br = 0.08 is chosen 'to obtain a phase separation' of a random
+    1:1 mixture (golden fixture). The order-parameter variance must grow by
+    orders of magnitude within a few hundred steps."""
+    p = json.load(open(os.path.join(GOLD, "paper_parameters.json")))["bijel"]
+    dims = (16, 16, 16)
+    o = _random_system(oracle_mod, dims, p["g_br"], 11)
+    ra, rb, _, _ = o.read_fields()
+    v0 = np.var(ra - rb)
+    o.step(400)
+    ra, rb, _, _ = o.read_fields()
+    assert np.var(ra - rb) > 30 * v0
+
+
+def _channel(oracle_mod, nz, tau, g=0.0, top_u=None, accel=None):
+    nx = ny = 3
+    dims = (nx, ny, nz)
+    N = nx * ny * nz
+    o = oracle_mod.Oracle(dims, tau, g)
+    z = np.repeat(np.arange(nz), nx * ny)
+    mask = (z == 0) | (z == nz - 1)
+    wu = np.zeros((N, 3))
+    if top_u is not None:
+        wu[z == nz - 1, 0] = top_u
+    o.set_walls(mask, wu)
+    o.init_fields(np.full(N, 0.6), np.full(N, 0.4))
+    if accel is not None:
+        o.set_accel([accel, 0.0, 0.0])
+    return o, z
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.7])
+def test_couette_is_linear_with_halfway_walls(oracle_mod, tau):
+    """Moving bounce-back, Eq. (4), with a wall of velocity U: steady Couette
+    flow is exactly linear with the walls half-way between wall and fluid
+    nodes (textbook property of half-way bounce-back)."""
+    nz, U = 10, 0.01
+    o, z = _channel(oracle_mod, nz, tau, top_u=U)
+    o.step(6000)
+    _, _, u, own = o.read_fields()
+    zs = np.arange(1, nz - 1)
+    prof = np.array([u[(z == k), 0].mean() for k in zs])
+    want = U * (zs - 0.5) / (nz - 2)
+    assert np.abs(prof - want).max() <= 1e-10 * U * 10
+    assert np.abs(u[:, 2]).max() < 1e-14
+
+
+def test_poiseuille_curvature(oracle_mod):
+    """Body force a between static walls: the steady barycentric profile is a
+    parabola of second difference -a/nu, nu = (tau - 1/2)/3."""
+    nz, a, tau = 12, 1e-6, 0.9
+    o, z = _channel(oracle_mod, nz, tau, accel=a)
+    o.step(8000)
+    _, _, u, _ = o.read_fields()
+    prof = np.array([u[(z == k), 0].mean() for k in range(1, nz - 1)])
+    nu = (tau - 0.5) / 3
+    d2 = prof[2:] - 2 * prof[1:-1] + prof[:-2]
+    assert np.abs(d2 / (-a / nu) - 1).max() <= 1e-6
