@@ -1,0 +1,158 @@
+/*
+ * lbe.h -- C ABI of the MI355X (gfx950) two-component Shan-Chen D3Q19 lattice
+ * Boltzmann library with moving rigid ellipsoids.
+ *
+ * Method: F. Guenther, F. Janoschek, S. Frijters, J. Harting, "Lattice
+ * Boltzmann simulations of anisotropic particles at liquid interfaces",
+ * arXiv:1109.3277, Sec. 2: LB equation (1) with the BGK operator (2), the
+ * Shan-Chen inter-component force (3), moving bounce-back (4) and the particle
+ * force (5), shell densities with particle colour (10), particles evolved by
+ * Newton's equations.
+ *
+ * Conventions for every call:
+ *  - Return 0 on success or a negative LB_E* code; lb_last_error() then holds
+ *    a message. A failed call leaves the handle usable unless it says otherwise.
+ *  - Pointers named dev_* are device memory; all others are host memory owned
+ *    by the caller, copied in or out before the call returns.
+ *  - Fields are indexed [z][y][x], x fastest, N = nx*ny*nz nodes; node (x,y,z)
+ *    sits at position (x,y,z) (0-based; the paper counts from 1).
+ *  - Quaternions are (w, x, y, z), body -> space, normalised on input. The body
+ *    z axis is the ellipsoid's symmetry axis (radius R_par); the other two
+ *    radii are R_perp.
+ *  - A handle is not thread-safe; all device work of a handle is ordered on
+ *    the stream given at creation. Calls that return host data synchronise
+ *    that stream.
+ *  - The library never allocates device memory: the caller passes a device
+ *    workspace of at least lb_workspace_bytes() bytes that must outlive the
+ *    handle.
+ */
+#ifndef LBE_H
+#define LBE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB_OK 0
+#define LB_EINVAL (-1)     /* bad argument: dims < 3, tau <= 1/2, non-finite value, NULL where required */
+#define LB_ENOMEM (-2)     /* workspace too small, or particle capacity exceeded */
+#define LB_EHIP (-3)       /* a HIP runtime error; the message holds hipGetErrorString */
+#define LB_EUNSTABLE (-4)  /* NaN or negative density found during lb_step */
+#define LB_ESTATE (-5)     /* call-order violation (e.g. lb_step before lb_init_fields) */
+#define LB_EGEOM (-6)      /* particle radius <= 0, or bounding radius >= min(nx,ny,nz)/2 */
+
+/* Storage / arithmetic forms of the populations. FP64 stores and computes in
+ * double. FP32 stores and computes in float. FP16_DEV / BF16_DEV store the
+ * deviation f_i - w_i rho_ref^c (rho_ref^c = the component's initial mean
+ * density) in IEEE half / bfloat16 and compute in float. Particle state,
+ * force / torque sums and mass reductions are double in every form. */
+typedef enum { LB_FP64 = 0, LB_FP32 = 1, LB_FP16_DEV = 2, LB_BF16_DEV = 3 } lb_precision;
+
+/* Problem parameters (Sec. 2 and Sec. 4 of the paper):
+ *  tau       BGK relaxation time of both components, Eq. (2); > 1/2.
+ *  g_br      cross-component coupling g_AB = g_BA of Eq. (3); > 0 demixes.
+ *  psi_kind  effective mass of Eq. (3): 0 -> Psi = rho, 1 -> Psi = 1 - exp(-rho).
+ *  max_particles  particle capacity reserved in the workspace. */
+typedef struct {
+    int32_t nx, ny, nz;
+    double tau;
+    double g_br;
+    int32_t psi_kind;
+    int32_t precision; /* lb_precision */
+    int32_t max_particles;
+} lb_params;
+
+typedef struct lb_handle lb_handle;
+
+/* Bytes of device workspace lb_create needs for these parameters (0 if the
+ * parameters are invalid). */
+size_t lb_workspace_bytes(const lb_params* prm);
+
+/* Create a handle over a caller-owned device workspace (dev_ws, ws_bytes) and
+ * a HIP stream (hipStream_t passed as void*, NULL = default stream). The
+ * workspace is carved, never freed by the library. *out is NULL on failure. */
+int lb_create(const lb_params* prm, void* dev_ws, size_t ws_bytes, void* hip_stream, lb_handle** out);
+
+/* Release host-side state. Does not free the workspace. NULL is a no-op. */
+void lb_destroy(lb_handle* h);
+
+/* Initial fields (Sec. 2; populations start at the equilibrium of Eq. (2)):
+ * f_i^c = f_i^eq(rho^c, u) on every fluid node. rho_a, rho_b: N doubles each
+ * (component A = red, B = blue). u: 3N doubles (x,y,z per node) or NULL for
+ * rest. Must precede lb_add_ellipsoids and lb_step. */
+int lb_init_fields(lb_handle* h, const double* rho_a, const double* rho_b, const double* u);
+
+/* Add n rigid ellipsoids (Sec. 2: particles discretised on the lattice,
+ * coupled by Eq. (4)-(5); colour Delta rho after Eq. (10)). radii: n x 2
+ * (R_par, R_perp); pos: n x 3 (wrapped into the box); quat: n x 4; delta_rho:
+ * n (may be NULL -> 0); density: n (may be NULL -> 1). Nodes whose body-frame
+ * offset d satisfies (d_x^2+d_y^2)/R_perp^2 + d_z^2/R_par^2 <= 1 become solid
+ * (smallest particle index wins on overlaps) and the fluid on them is removed.
+ * Velocities start at zero. Requires lb_init_fields first. */
+int lb_add_ellipsoids(lb_handle* h, int32_t n, const double* radii, const double* pos, const double* quat,
+                      const double* delta_rho, const double* density);
+
+/* Advance nsteps >= 0 full time steps (densities, shell fill, Shan-Chen force,
+ * BGK collision, streaming with moving bounce-back and particle force/torque,
+ * rigid-body update, re-rasterisation with kill/fill). Work is enqueued on
+ * the handle's stream; the call then waits for it to check the health flag and
+ * returns LB_EUNSTABLE if a NaN or negative density appeared. */
+int lb_step(lb_handle* h, int32_t nsteps);
+
+/* Same as lb_step but does not wait: no health check; the stream is left
+ * running (for timing and graph capture by the caller). */
+int lb_step_async(lb_handle* h, int32_t nsteps);
+
+/* Read densities rho_a, rho_b (N each), barycentric velocity u = (j^A+j^B) /
+ * (rho^A+rho^B) (3N) and the owner map (N int32: -1 fluid, -2 wall, p >= 0
+ * particle index). Solid nodes read 0 density and velocity. Any output may be
+ * NULL. Synchronises the stream. */
+int lb_read_fields(lb_handle* h, double* rho_a, double* rho_b, double* u, int32_t* owner);
+
+/* Number of particles on the handle (or a negative error code). */
+int lb_num_particles(const lb_handle* h);
+
+/* Particle state, n x 3 (quat n x 4); force / torque are the totals applied in
+ * the last rigid-body update (bounce-back sums of Eq. (5) plus kill/fill
+ * impulses). Any output may be NULL. Synchronises the stream. */
+int lb_read_particles(lb_handle* h, double* pos, double* quat, double* vel, double* omega, double* force,
+                      double* torque);
+
+/* Diagnostics, FP64, deterministic order: out[0..7] = {mass A, mass B,
+ * momentum x, y, z over fluid nodes, mass removed by particles (killed minus
+ * filled, cumulative), number of fluid nodes, health (1 = NaN or negative
+ * density present)}. Synchronises the stream. */
+int lb_stats(lb_handle* h, double out[8]);
+
+/* Uniform body acceleration a (3 doubles) added to every fluid node's force
+ * (test and channel-flow use; default 0). */
+int lb_set_body_accel(lb_handle* h, const double a[3]);
+
+/* Checkpoint: lb_state_bytes() bytes of host memory hold the populations,
+ * owner map, particle state and counters; lb_load_state restores them into a
+ * handle created with the same parameters. */
+size_t lb_state_bytes(const lb_handle* h);
+int lb_save_state(lb_handle* h, void* host_buf, size_t bytes);
+int lb_load_state(lb_handle* h, const void* host_buf, size_t bytes);
+
+/* Per-phase timing with HIP events recorded on the handle's stream around
+ * every kernel launch of lb_step (phases: 0 densities, 1 shell fill, 2 fused
+ * force/collide/stream, 3 rigid bodies, 4 raster (clear + rasterise), 5 kill /
+ * fill). lb_profile_enable(h, 1) starts a fresh record, 0 stops recording.
+ * lb_profile_read waits for the recorded events and writes, per phase, the
+ * summed milliseconds and the number of launches (arrays of LB_NPHASES). */
+#define LB_NPHASES 6
+int lb_profile_enable(lb_handle* h, int on);
+int lb_profile_read(lb_handle* h, double* ms, int64_t* launches);
+
+/* Message of the last failed call on h (or of the last failed lb_create when
+ * h is NULL); valid until the next call on the same handle. */
+const char* lb_last_error(const lb_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBE_H */

@@ -77,6 +77,8 @@ def lib():
         L.orc_lattice.argtypes = [ip, ip, ip, dp]
         L.orc_feq.argtypes = [C.c_double, dp, dp]
         L.orc_read_owner.argtypes = [P, ip]
+        L.orc_num_threads.restype = C.c_int
+        L.orc_num_threads.argtypes = []
         _lib = L
     return _lib
 
@@ -94,6 +96,10 @@ def _f64(a, n=None):
     if n is not None:
         assert a.size == n, (a.size, n)
     return a
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def lattice():

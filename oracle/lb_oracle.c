@@ -51,6 +51,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define NQ 19
 #define OWN_FLUID (-1)
@@ -107,6 +110,7 @@ typedef struct {
     double link_mass;      /* sum of the bounce-back C terms, last step */
     double kill_mass, fill_mass; /* last step */
     int inited;
+    int any_wall;          /* a static wall node exists */
 } orc_t;
 
 /* ---------------------------------------------------------------- helpers */
@@ -118,12 +122,24 @@ static int wrapi(int a, int n) {
     a %= n;
     return a < 0 ? a + n : a;
 }
+static int wrap1(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+/* neighbour of node (x, y, z) along c_i, periodic */
+static long nb3(const orc_t *s, int x, int y, int z, int i) {
+    return nidx(s, wrap1(x + CX[i], s->nx), wrap1(y + CY[i], s->ny), wrap1(z + CZ[i], s->nz));
+}
 static long nbr(const orc_t *s, long n, int i) {
     int x = (int)(n % s->nx);
     int y = (int)((n / s->nx) % s->ny);
     int z = (int)(n / ((long)s->nx * s->ny));
-    return nidx(s, wrapi(x + CX[i], s->nx), wrapi(y + CY[i], s->ny), wrapi(z + CZ[i], s->nz));
+    return nb3(s, x, y, z, i);
 }
+/* node loops: z-slabs in parallel, each thread walking y then x */
+#define FOR_NODES(s) \
+    _Pragma("omp parallel for schedule(static)") \
+    for (int z = 0; z < (s)->nz; z++) \
+        for (int y = 0; y < (s)->ny; y++) \
+            for (int x = 0; x < (s)->nx; x++)
+#define NODE(s) nidx((s), x, y, z)
 static void coords(const orc_t *s, long n, int *x, int *y, int *z) {
     *x = (int)(n % s->nx);
     *y = (int)((n / s->nx) % s->ny);
@@ -286,6 +302,7 @@ void orc_set_walls(orc_t *s, const unsigned char *mask, const double *wall_u) {
     if (!s->wall_u) s->wall_u = (double *)calloc((size_t)3 * s->N, sizeof(double));
     for (long n = 0; n < s->N; n++) {
         s->wall[n] = mask[n] ? 1 : 0;
+        if (s->wall[n]) s->any_wall = 1;
         for (int k = 0; k < 3; k++) s->wall_u[3 * n + k] = wall_u ? wall_u[3 * n + k] : 0.0;
         if (s->wall[n]) {
             s->owner[n] = OWN_WALL;
@@ -393,10 +410,9 @@ int orc_add_ellipsoids(orc_t *s, int n, const double *radii, const double *pos, 
 /* ---------------------------------------------------------------- S1 */
 void orc_stage_densities(orc_t *s) {
     long N = s->N;
-#pragma omp parallel for schedule(static)
-    for (int z = 0; z < s->nz; z++)
-        for (long n = (long)z * s->nx * s->ny; n < (long)(z + 1) * s->nx * s->ny; n++)
-            for (int c = 0; c < 2; c++) {
+    FOR_NODES(s) {
+        long n = NODE(s);
+        for (int c = 0; c < 2; c++) {
                 double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
                 if (s->owner[n] == OWN_FLUID) {
                     for (int i = 0; i < NQ; i++) {
@@ -411,7 +427,8 @@ void orc_stage_densities(orc_t *s) {
                 s->jm[c][3 * n] = jx;
                 s->jm[c][3 * n + 1] = jy;
                 s->jm[c][3 * n + 2] = jz;
-            }
+        }
+    }
 }
 
 /* ---------------------------------------------------------------- S2 */
@@ -420,14 +437,13 @@ void orc_stage_densities(orc_t *s) {
  * added to A (Delta rho > 0) or its magnitude to B (Delta rho < 0). Walls have
  * colour 0. Solid nodes without fluid neighbours get 0 (never read). */
 void orc_stage_shell(orc_t *s) {
-#pragma omp parallel for schedule(static)
-    for (int z = 0; z < s->nz; z++)
-        for (long n = (long)z * s->nx * s->ny; n < (long)(z + 1) * s->nx * s->ny; n++) {
+    FOR_NODES(s) {
+            long n = NODE(s);
             if (s->owner[n] == OWN_FLUID) continue;
             double sum[2] = {0.0, 0.0};
             int k = 0;
             for (int i = 1; i < NQ; i++) {
-                long m = nbr(s, n, i);
+                long m = nb3(s, x, y, z, i);
                 if (s->owner[m] != OWN_FLUID) continue;
                 sum[0] += s->rho[0][m];
                 sum[1] += s->rho[1][m];
@@ -450,13 +466,12 @@ void orc_stage_shell(orc_t *s) {
 /* Shan-Chen force per node, Eq. (3), both components (valid after S1, S2).
  * Fluid nodes only; solid nodes get 0. Exposed for the invariance checks. */
 void orc_sc_force(const orc_t *s, double *FA, double *FB) {
-#pragma omp parallel for schedule(static)
-    for (int z = 0; z < s->nz; z++)
-        for (long n = (long)z * s->nx * s->ny; n < (long)(z + 1) * s->nx * s->ny; n++) {
+    FOR_NODES(s) {
+            long n = NODE(s);
             double SA[3] = {0, 0, 0}, SB[3] = {0, 0, 0};
             if (s->owner[n] == OWN_FLUID) {
                 for (int i = 1; i < NQ; i++) {
-                    long m = nbr(s, n, i);
+                    long m = nb3(s, x, y, z, i);
                     double pa = psi(s, s->rho[0][m]), pb = psi(s, s->rho[1][m]);
                     SA[0] += pa * CX[i];
                     SA[1] += pa * CY[i];
@@ -483,13 +498,12 @@ void orc_sc_force(const orc_t *s, double *FA, double *FB) {
  * F^c / rho^c is formed as -g (Psi^c/rho^c) sum_i Psi^cbar(x+c_i) c_i. */
 void orc_stage_collide(orc_t *s) {
     long N = s->N;
-#pragma omp parallel for schedule(static)
-    for (int z = 0; z < s->nz; z++)
-        for (long n = (long)z * s->nx * s->ny; n < (long)(z + 1) * s->nx * s->ny; n++) {
+    FOR_NODES(s) {
+            long n = NODE(s);
             if (s->owner[n] != OWN_FLUID) continue;
             double S[2][3] = {{0, 0, 0}, {0, 0, 0}};
             for (int i = 1; i < NQ; i++) {
-                long m = nbr(s, n, i);
+                long m = nb3(s, x, y, z, i);
                 for (int c = 0; c < 2; c++) {
                     double p = psi(s, s->rho[c][m]);
                     S[c][0] += p * CX[i];
@@ -550,15 +564,19 @@ static double link_C(const orc_t *s, long n, int i, int c, long m, double r[3]) 
  * Eq. (5), written with the reflected population of Eq. (4) as f*_i (R11). */
 void orc_stage_stream(orc_t *s) {
     long N = s->N;
-    for (int c = 0; c < 2; c++) memset(s->fn[c], 0, sizeof(double) * NQ * (size_t)N);
-#pragma omp parallel for schedule(static)
-    for (int z = 0; z < s->nz; z++)
-        for (long n = (long)z * s->nx * s->ny; n < (long)(z + 1) * s->nx * s->ny; n++) {
-            if (s->owner[n] != OWN_FLUID) continue;
+    /* Every population of a fluid node is written below (by a push from its
+     * fluid neighbour or by bounce-back); solid nodes hold none. */
+    FOR_NODES(s) {
+            long n = NODE(s);
+            if (s->owner[n] != OWN_FLUID) {
+                for (int c = 0; c < 2; c++)
+                    for (int i = 0; i < NQ; i++) s->fn[c][i * N + n] = 0.0;
+                continue;
+            }
             for (int c = 0; c < 2; c++) {
                 s->fn[c][n] = s->f[c][n];
                 for (int i = 1; i < NQ; i++) {
-                    long m = nbr(s, n, i);
+                    long m = nb3(s, x, y, z, i);
                     double fs = s->f[c][i * N + n];
                     if (s->owner[m] == OWN_FLUID) {
                         s->fn[c][i * N + m] = fs;
@@ -574,10 +592,14 @@ void orc_stage_stream(orc_t *s) {
     for (int k = 0; k < s->np; k++)
         for (int d = 0; d < 3; d++) s->P[k].F[d] = s->P[k].T[d] = 0.0;
     s->link_mass = 0.0;
-    for (long n = 0; n < N; n++) {
+    if (s->np == 0 && !s->any_wall) return; /* no solid node: no links */
+    for (int z = 0; z < s->nz; z++)
+      for (int y = 0; y < s->ny; y++)
+        for (int x = 0; x < s->nx; x++) {
+        long n = NODE(s);
         if (s->owner[n] != OWN_FLUID) continue;
         for (int i = 1; i < NQ; i++) {
-            long m = nbr(s, n, i);
+            long m = nb3(s, x, y, z, i);
             if (s->owner[m] == OWN_FLUID) continue;
             for (int c = 0; c < 2; c++) {
                 double r[3];
@@ -908,3 +930,12 @@ void orc_feq(double rho, const double u[3], double out[NQ]) { feq(rho, u, out); 
 
 /* Owner map of a set of particles alone (test use: raster checks). */
 void orc_read_owner(const orc_t *s, int *owner) { memcpy(owner, s->owner, sizeof(int) * (size_t)s->N); }
+
+/* Threads the node loops use (1 without OpenMP). */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

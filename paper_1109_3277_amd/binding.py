@@ -1,0 +1,212 @@
+"""ctypes binding of liblbe's C ABI (include/lbe.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch supplies the device workspace and the stream. Importing this module
+on a machine without the built library raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbe.so")
+
+LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_EUNSTABLE, LB_ESTATE, LB_EGEOM = 0, -1, -2, -3, -4, -5, -6
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp16_dev": 2, "bf16_dev": 3}
+EXPORTED = [
+    "lb_workspace_bytes", "lb_create", "lb_destroy", "lb_init_fields", "lb_add_ellipsoids", "lb_step",
+    "lb_step_async", "lb_read_fields", "lb_num_particles", "lb_read_particles", "lb_stats",
+    "lb_set_body_accel", "lb_state_bytes", "lb_save_state", "lb_load_state", "lb_last_error",
+    "lb_profile_enable", "lb_profile_read",
+]
+PHASES = ["density", "shell", "fused", "bodies", "raster", "killfill"]
+
+
+class LBError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"liblbe error {code}: {msg}")
+        self.code = code
+
+
+class lb_params(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("tau", C.c_double),
+                ("g_br", C.c_double), ("psi_kind", C.c_int32), ("precision", C.c_int32),
+                ("max_particles", C.c_int32)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load liblbe.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run python -m paper_1109_3277_amd.build)")
+    L = C.CDLL(LIB_PATH)
+    vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)
+    pp = C.POINTER(lb_params)
+    L.lb_workspace_bytes.restype = C.c_size_t
+    L.lb_workspace_bytes.argtypes = [pp]
+    L.lb_create.argtypes = [pp, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.lb_destroy.argtypes = [vp]
+    L.lb_destroy.restype = None
+    L.lb_init_fields.argtypes = [vp, dp, dp, dp]
+    L.lb_add_ellipsoids.argtypes = [vp, C.c_int32, dp, dp, dp, dp, dp]
+    L.lb_step.argtypes = [vp, C.c_int32]
+    L.lb_step_async.argtypes = [vp, C.c_int32]
+    L.lb_read_fields.argtypes = [vp, dp, dp, dp, ip]
+    L.lb_num_particles.argtypes = [vp]
+    L.lb_read_particles.argtypes = [vp, dp, dp, dp, dp, dp, dp]
+    L.lb_stats.argtypes = [vp, dp]
+    L.lb_set_body_accel.argtypes = [vp, dp]
+    L.lb_state_bytes.restype = C.c_size_t
+    L.lb_state_bytes.argtypes = [vp]
+    L.lb_save_state.argtypes = [vp, vp, C.c_size_t]
+    L.lb_load_state.argtypes = [vp, vp, C.c_size_t]
+    L.lb_last_error.restype = C.c_char_p
+    L.lb_last_error.argtypes = [vp]
+    L.lb_profile_enable.argtypes = [vp, C.c_int]
+    L.lb_profile_read.argtypes = [vp, dp, C.POINTER(C.c_int64)]
+    _lib = L
+    return L
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a, n=None):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def make_params(dims, tau, g_br, psi_kind=0, precision="fp64", max_particles=0) -> lb_params:
+    nx, ny, nz = (int(v) for v in dims)
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return lb_params(nx, ny, nz, float(tau), float(g_br), int(psi_kind), prec, int(max_particles))
+
+
+def workspace_bytes(params: lb_params) -> int:
+    return int(load_library().lb_workspace_bytes(C.byref(params)))
+
+
+class Lattice:
+    """One periodic two-component system on the GPU (fields [z][y][x])."""
+
+    def __init__(self, dims, tau, g_br, psi_kind=0, precision="fp64", max_particles=0, device="cuda"):
+        import torch
+
+        L = load_library()
+        self.params = make_params(dims, tau, g_br, psi_kind, precision, max_particles)
+        self.dims = tuple(int(v) for v in dims)
+        self.N = self.dims[0] * self.dims[1] * self.dims[2]
+        nbytes = L.lb_workspace_bytes(C.byref(self.params))
+        if nbytes == 0:
+            raise LBError(LB_EINVAL, "invalid parameters")
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self._ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self._ws.device)
+        h = C.c_void_p()
+        rc = L.lb_create(C.byref(self.params), C.c_void_p(self._ws_ptr), nbytes, C.c_void_p(self.stream.cuda_stream),
+                         C.byref(h))
+        if rc != 0:
+            raise LBError(rc, L.lb_last_error(None).decode())
+        self._h = h
+
+    # -- plumbing
+    def _check(self, rc):
+        if rc != 0:
+            raise LBError(rc, load_library().lb_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().lb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- API
+    def init_fields(self, rho_a, rho_b, u=None):
+        ra, rb = _f64(rho_a, self.N), _f64(rho_b, self.N)
+        uu = _f64(u, 3 * self.N)
+        self._check(load_library().lb_init_fields(self._h, _dp(ra), _dp(rb), _dp(uu)))
+
+    def add_ellipsoids(self, radii, pos, quat, delta_rho=None, density=None):
+        radii = _f64(radii)
+        n = radii.size // 2
+        pos, quat = _f64(pos, 3 * n), _f64(quat, 4 * n)
+        dr = _f64(delta_rho, n)
+        de = _f64(density, n)
+        self._check(load_library().lb_add_ellipsoids(self._h, n, _dp(radii), _dp(pos), _dp(quat), _dp(dr), _dp(de)))
+
+    def step(self, n=1):
+        self._check(load_library().lb_step(self._h, int(n)))
+
+    def step_async(self, n=1):
+        self._check(load_library().lb_step_async(self._h, int(n)))
+
+    def set_body_accel(self, a):
+        aa = _f64(a, 3)
+        self._check(load_library().lb_set_body_accel(self._h, _dp(aa)))
+
+    def read_fields(self):
+        ra, rb, u = np.zeros(self.N), np.zeros(self.N), np.zeros(3 * self.N)
+        own = np.zeros(self.N, dtype=np.int32)
+        self._check(load_library().lb_read_fields(self._h, _dp(ra), _dp(rb), _dp(u),
+                                                  own.ctypes.data_as(C.POINTER(C.c_int32))))
+        return ra, rb, u.reshape(-1, 3), own
+
+    def num_particles(self) -> int:
+        return int(load_library().lb_num_particles(self._h))
+
+    def read_particles(self):
+        n = self.num_particles()
+        out = {k: np.zeros((n, 3)) for k in ("pos", "vel", "omega", "force", "torque")}
+        out["quat"] = np.zeros((n, 4))
+        self._check(load_library().lb_read_particles(self._h, _dp(out["pos"]), _dp(out["quat"]), _dp(out["vel"]),
+                                                     _dp(out["omega"]), _dp(out["force"]), _dp(out["torque"])))
+        return out
+
+    def stats(self):
+        o = np.zeros(8)
+        self._check(load_library().lb_stats(self._h, _dp(o)))
+        return o
+
+    def profile(self, on: bool):
+        self._check(load_library().lb_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        """{phase: (total ms, launches)} of the launches recorded since profile(True)."""
+        ms = np.zeros(len(PHASES))
+        cnt = np.zeros(len(PHASES), dtype=np.int64)
+        self._check(load_library().lb_profile_read(self._h, _dp(ms), cnt.ctypes.data_as(C.POINTER(C.c_int64))))
+        return {p: (float(ms[k]), int(cnt[k])) for k, p in enumerate(PHASES)}
+
+    def save_state(self) -> bytes:
+        L = load_library()
+        n = L.lb_state_bytes(self._h)
+        buf = C.create_string_buffer(n)
+        self._check(L.lb_save_state(self._h, buf, n))
+        return buf.raw
+
+    def load_state(self, data: bytes):
+        buf = C.create_string_buffer(data, len(data))
+        self._check(load_library().lb_load_state(self._h, buf, len(data)))

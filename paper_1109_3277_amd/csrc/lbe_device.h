@@ -1,0 +1,119 @@
+// Device-side definitions shared by the HIP kernels of liblbe (gfx950, wave64).
+//
+// Lattice: D3Q19 (the paper's Sec. 2 uses D3Q19, i = 1..19). This library orders
+// the 19 velocities as: 0 rest, 1..9 one member of each opposite pair, and
+// 10..18 their opposites, so opp(i) = i + 9 for 1 <= i <= 9 and i - 9 above.
+// Weights w_i = 1/3, 1/18 (axis), 1/36 (face diagonal); c_s^2 = 1/3.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+namespace lbe {
+
+constexpr int Q = 19;
+constexpr uint32_t OWN_FLUID = 0xFFFFFFFFu;  // owner code of a fluid node
+constexpr uint32_t OWN_WALL = 0xFFFFFFFEu;   // static wall node (no particle)
+
+__host__ __device__ constexpr int cx(int i) {
+    constexpr int t[Q] = {0, 1, 0, 0, 1, 1, 1, 1, 0, 0, -1, 0, 0, -1, -1, -1, -1, 0, 0};
+    return t[i];
+}
+__host__ __device__ constexpr int cy(int i) {
+    constexpr int t[Q] = {0, 0, 1, 0, 1, -1, 0, 0, 1, 1, 0, -1, 0, -1, 1, 0, 0, -1, -1};
+    return t[i];
+}
+__host__ __device__ constexpr int cz(int i) {
+    constexpr int t[Q] = {0, 0, 0, 1, 0, 0, 1, -1, 1, -1, 0, 0, -1, 0, 0, -1, 1, -1, 1};
+    return t[i];
+}
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : (i <= 9 ? i + 9 : i - 9); }
+__host__ __device__ constexpr double wq(int i) {
+    return i == 0 ? 1.0 / 3.0 : ((cx(i) * cx(i) + cy(i) * cy(i) + cz(i) * cz(i)) == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// Particle table: structure of arrays of doubles, field k of particle p at
+// part[k * cap + p].
+enum PField : int {
+    PX = 0, PY, PZ,            // centre
+    QW, QX, QY, QZ,            // orientation quaternion
+    VX, VY, VZ,                // velocity
+    WX, WY, WZ,                // angular velocity (space frame)
+    LX, LY, LZ,                // angular momentum (space frame)
+    RPAR, RPERP, DRHO, MASS, IPERP, IPAR,
+    FX, FY, FZ, TX, TY, TZ,    // bounce-back force / torque of the current step
+    JX, JY, JZ, HX, HY, HZ,    // pending kill/fill impulses
+    LFX, LFY, LFZ, LTX, LTY, LTZ,  // totals applied in the last body update
+    OX, OY, OZ,                // centre before the last body update
+    NPFIELD
+};
+
+// Population storage policies. S is the stored type, R the arithmetic type.
+// Deviation forms store f_i - w_i rho_ref^c.
+struct PolF64 {
+    using S = double;
+    using R = double;
+    static constexpr bool dev = false;
+    __device__ static R ld(const S* p, R) { return *p; }
+    __device__ static void st(S* p, R v, R) { *p = v; }
+};
+struct PolF32 {
+    using S = float;
+    using R = float;
+    static constexpr bool dev = false;
+    __device__ static R ld(const S* p, R) { return *p; }
+    __device__ static void st(S* p, R v, R) { *p = v; }
+};
+struct PolF16 {
+    using S = __half;
+    using R = float;
+    static constexpr bool dev = true;
+    __device__ static R ld(const S* p, R wref) { return __half2float(*p) + wref; }
+    __device__ static void st(S* p, R v, R wref) { *p = __float2half_rn(v - wref); }
+};
+struct PolBF16 {
+    using S = __hip_bfloat16;
+    using R = float;
+    static constexpr bool dev = true;
+    __device__ static R ld(const S* p, R wref) { return __bfloat162float(*p) + wref; }
+    __device__ static void st(S* p, R v, R wref) { *p = __float2bfloat16(v - wref); }
+};
+
+// Everything a kernel needs to know about one periodic box.
+struct Box {
+    int nx, ny, nz;
+    int64_t N;       // nx*ny*nz
+    double tau;
+    double g;        // g_br
+    int psi_kind;    // 0: Psi = rho, 1: Psi = 1 - exp(-rho)
+    double ax, ay, az;  // body acceleration
+    double rref[2];  // deviation reference density per component
+    double rmean0[2];  // initial global mean density per component
+};
+
+__device__ inline int wrapc(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+// Minimum-image difference along one periodic axis of length L.
+__device__ inline double minimg(double d, int L) {
+    double h = 0.5 * (double)L;
+    if (d > h) return d - (double)L;
+    if (d < -h) return d + (double)L;
+    return d;
+}
+
+template <class R>
+__device__ inline R psi_of(R r, int kind) {
+    if (kind == 0) return r;
+    return -expm1(-r);
+}
+// Psi(rho)/rho, equal to 1 at rho = 0 for both kinds.
+template <class R>
+__device__ inline R psi_ratio(R r, int kind) {
+    if (kind == 0) return R(1);
+    if (r == R(0)) return R(1);
+    return -expm1(-r) / r;
+}
+
+}  // namespace lbe

@@ -1,0 +1,183 @@
+"""GPU (HIP, through the C ABI) against the CPU FP64 oracle on the same seeded
+inputs. Gates: FP64 <= 1e-12 relative after 100 steps (densities L-inf,
+velocity L2 over fluid nodes), owner map identical; FP32 <= 1e-5; reduced
+storage <= 1e-3 with the mass drift reported."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1109_3277_amd import workloads as W
+from tests.parity_util import compare, log, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+FP64_GATE = 1e-12
+
+
+def _check_fp64(res, particles=True):
+    log(f"  parity {res}")
+    assert res["e_rho"] <= FP64_GATE, res
+    assert res["e_u"] <= FP64_GATE, res
+    assert res["owner_equal"], res
+    assert res["n_fluid_equal"], res
+    assert res["e_mass"] <= 1e-13, res
+    if particles and "e_pos" in res:
+        assert res["e_pos"] <= 1e-12 and res["e_quat"] <= 1e-12, res
+        assert res["e_vel"] <= 1e-10 and res["e_omega"] <= 1e-10, res
+
+
+def _run(sysm, steps, precision="fp64"):
+    log(f"case {sysm.name} dims={sysm.dims} np={sysm.n_particles} steps={steps} precision={precision}")
+    o = run_oracle(sysm, steps)
+    g = run_gpu(sysm, steps, precision)
+    return o, g, compare(o, g, sysm.dims)
+
+
+def test_fluid_ragged_tiles_fp64():
+    """Box sizes that leave partial tiles in x and y (several tiles, ragged tail)."""
+    s = W.spinodal_system(dims=(40, 20, 12), seed=11)
+    _, _, res = _run(s, 100)
+    _check_fp64(res)
+
+
+def test_zero_steps_and_minimum_box():
+    s = W.spinodal_system(dims=(3, 3, 3), seed=12)
+    o, g, res = _run(s, 0)
+    assert res["e_rho"] <= 1e-15
+    o.step(20)
+    g.step(20)
+    _check_fp64(compare(o, g, s.dims))
+
+
+def test_interface_full_size_fp64():
+    """32x32x64 flat interface with one prolate ellipsoid, 100 steps (full size)."""
+    s = W.interface_system()
+    _, _, res = _run(s, 100)
+    _check_fp64(res)
+
+
+def test_interface_colour_and_psi_kind_fp64():
+    """Non-zero particle colour (both signs) and Psi = 1 - exp(-rho)."""
+    for dr, kind in ((0.2, 0), (-0.25, 1)):
+        s = W.interface_system(dims=(24, 24, 40), rpar=5.0, rperp=3.0, delta_rho=dr, seed=13)
+        s.psi_kind = kind
+        _, _, res = _run(s, 60)
+        _check_fp64(res)
+
+
+def test_spinodal_full_size_fp64():
+    """128^3 spinodal mixture, 100 steps (full size)."""
+    s = W.spinodal_system()
+    _, _, res = _run(s, 100)
+    _check_fp64(res)
+
+
+def test_bijel_scaled_fp64():
+    """64^3 with the bijel recipe (volume fraction 0.15 of (8,4) ellipsoids)."""
+    s = W.bijel_system(dims=(64, 64, 64), seed=14)
+    assert s.n_particles > 50
+    _, _, res = _run(s, 100)
+    _check_fp64(res)
+
+
+def test_bijel_30_70_scaled_fp64():
+    s = W.bijel_system(dims=(48, 40, 56), seed=15, ratio="30/70")
+    _, _, res = _run(s, 60)
+    _check_fp64(res)
+
+
+def test_moving_particles_cross_nodes_fp64():
+    """Particles given a push so they cross lattice nodes (kill / fill)."""
+    s = W.bijel_system(dims=(40, 40, 40), seed=16, phi=0.1)
+    rng = np.random.default_rng(16)
+    u = 0.05 * rng.uniform(-1, 1, (s.N, 3))
+    import oracle
+    from paper_1109_3277_amd.binding import Lattice
+
+    o = oracle.Oracle(s.dims, s.tau, s.g_br)
+    o.init_fields(s.rho_a, s.rho_b, u)
+    o.add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
+    g = Lattice(s.dims, s.tau, s.g_br, max_particles=s.n_particles)
+    g.init_fields(s.rho_a, s.rho_b, u)
+    g.add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
+    own0 = o.owner().copy()
+    o.step(100)
+    g.step(100)
+    res = compare(o, g, s.dims)
+    assert (o.owner() != own0).sum() > 0
+    _check_fp64(res)
+
+
+def test_large_particle_near_half_box_fp64():
+    """Bounding radius just below half the shortest side (largest allowed)."""
+    from paper_1109_3277_amd.workloads import System, layered_fields
+
+    dims = (16, 18, 32)
+    ra, rb = layered_fields(dims, 17)
+    s = System("edge", dims, 1.0, 0.08, ra, rb, np.array([[7.95, 3.0]]), np.array([[8.0, 9.0, 15.5]]),
+               np.array([[0.9, 0.1, 0.3, 0.2]]), np.array([0.1]), np.array([1.0]))
+    _, _, res = _run(s, 50)
+    _check_fp64(res)
+
+
+def test_spinodal_fp32():
+    s = W.spinodal_system(dims=(64, 48, 40), seed=18)
+    _, _, res = _run(s, 100, "fp32")
+    log(f"  fp32 {res}")
+    assert res["e_rho"] <= 1e-5 and res["e_u"] <= 1e-4, res
+
+
+def test_interface_fp32():
+    s = W.interface_system()
+    _, _, res = _run(s, 100, "fp32")
+    log(f"  fp32 {res}")
+    assert res["e_rho"] <= 1e-5, res
+
+
+@pytest.mark.parametrize("prec", ["fp16_dev", "bf16_dev"])
+def test_spinodal_reduced_storage(prec):
+    s = W.spinodal_system(dims=(64, 48, 40), seed=19)
+    o, g, res = _run(s, 100, prec)
+    log(f"  {prec} {res}")
+    gate = 1e-3 if prec == "fp16_dev" else 2e-2
+    assert res["e_rho"] <= gate, res
+
+
+def test_health_flag_reports_nan():
+    from paper_1109_3277_amd.binding import LB_EUNSTABLE, LBError, Lattice
+
+    s = W.spinodal_system(dims=(16, 16, 16), seed=20)
+    ra = s.rho_a.copy()
+    ra[100] = float("nan")
+    g = Lattice(s.dims, 1.0, 0.08)
+    g.init_fields(ra, s.rho_b)
+    with pytest.raises(LBError) as e:
+        g.step(1)
+    assert e.value.code == LB_EUNSTABLE
+    assert g.stats()[7] == 1.0
+
+
+def test_checkpoint_roundtrip():
+    from paper_1109_3277_amd.binding import Lattice
+
+    s = W.interface_system(dims=(24, 24, 40), rpar=5.0, rperp=3.0, seed=21)
+
+    def fresh():
+        g = Lattice(s.dims, s.tau, s.g_br, max_particles=1)
+        g.init_fields(s.rho_a, s.rho_b)
+        g.add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
+        return g
+
+    a = fresh()
+    a.step(30)
+    blob = a.save_state()
+    a.step(20)
+    b = fresh()
+    b.load_state(blob)
+    b.step(20)
+    fa, fb = a.read_fields(), b.read_fields()
+    assert np.array_equal(fa[3], fb[3])
+    assert np.abs(fa[0] - fb[0]).max() <= 1e-13
+    pa, pb = a.read_particles(), b.read_particles()
+    assert np.abs(pa["pos"] - pb["pos"]).max() <= 1e-13
