@@ -54,7 +54,8 @@ typedef enum { LB_FP64 = 0, LB_FP32 = 1, LB_FP16_DEV = 2, LB_BF16_DEV = 3 } lb_p
 /* Problem parameters (Sec. 2 and Sec. 4 of the paper):
  *  tau       BGK relaxation time of both components, Eq. (2); > 1/2.
  *  g_br      cross-component coupling g_AB = g_BA of Eq. (3); > 0 demixes.
- *  psi_kind  effective mass of Eq. (3): 0 -> Psi = rho, 1 -> Psi = 1 - exp(-rho).
+ *  psi_kind  effective mass of Eq. (3): 1 -> Psi = 1 - exp(-rho) (recommended),
+ *            0 -> Psi = rho.
  *  max_particles  particle capacity reserved in the workspace. */
 typedef struct {
     int32_t nx, ny, nz;

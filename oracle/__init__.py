@@ -124,7 +124,7 @@ def feq(rho: float, u) -> np.ndarray:
 class Oracle:
     """One periodic nx*ny*nz system (fields indexed [z][y][x], x fastest)."""
 
-    def __init__(self, dims, tau: float, g_br: float, psi_kind: int = 0):
+    def __init__(self, dims, tau: float, g_br: float, psi_kind: int = 1):
         nx, ny, nz = (int(v) for v in dims)
         self.dims = (nx, ny, nz)
         self.N = nx * ny * nz

@@ -89,7 +89,7 @@ def _f64(a, n=None):
     return a
 
 
-def make_params(dims, tau, g_br, psi_kind=0, precision="fp64", max_particles=0) -> lb_params:
+def make_params(dims, tau, g_br, psi_kind=1, precision="fp64", max_particles=0) -> lb_params:
     nx, ny, nz = (int(v) for v in dims)
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     return lb_params(nx, ny, nz, float(tau), float(g_br), int(psi_kind), prec, int(max_particles))
@@ -102,7 +102,7 @@ def workspace_bytes(params: lb_params) -> int:
 class Lattice:
     """One periodic two-component system on the GPU (fields [z][y][x])."""
 
-    def __init__(self, dims, tau, g_br, psi_kind=0, precision="fp64", max_particles=0, device="cuda"):
+    def __init__(self, dims, tau, g_br, psi_kind=1, precision="fp64", max_particles=0, device="cuda"):
         import torch
 
         L = load_library()

@@ -4,7 +4,7 @@
 //
 // Layout in HBM: populations f[c][i][n] (structure of arrays, x fastest, one
 // plane of N values per (component, velocity)), two copies (current / next);
-// densities rho[c][n]; owner map uint32 per node. One thread per node, tiles
+// effective masses Psi[c][n]; owner map uint32 per node. One thread per node, tiles
 // of 64x4 (or 32x8) nodes of one xy-plane per 256-thread block, tiles of
 // neighbouring z on the same XCD.
 #include "lbe_internal.h"
@@ -67,10 +67,12 @@ __device__ inline void flush_direct(int pid, const double* acc, double* part, in
 }
 
 // ---------------------------------------------------------------- S1
-// rho^c(n) = sum_i f_i^c(n) on fluid nodes; health flag on NaN / rho < 0.
+// rho^c(n) = sum_i f_i^c(n) on fluid nodes, stored as the effective mass
+// Psi^c(n) of Eq. (3), the only form the force stencil reads; health flag on
+// NaN / rho < 0.
 template <class P, bool SOLID>
 __global__ __launch_bounds__(256) void k_density(Box bx, const typename P::S* __restrict__ f,
-                                                 typename P::R* __restrict__ rho,
+                                                 typename P::R* __restrict__ psi,
                                                  const uint32_t* __restrict__ owner, int* __restrict__ health) {
     using R = typename P::R;
     const int64_t N = bx.N;
@@ -84,14 +86,21 @@ __global__ __launch_bounds__(256) void k_density(Box bx, const typename P::S* __
         r0 += P::ld(f + (size_t)i * N + n, R(wq(i)) * ref0);
         r1 += P::ld(f + (size_t)(Q + i) * N + n, R(wq(i)) * ref1);
     }
-    rho[n] = r0;
-    rho[N + n] = r1;
+    psi[n] = psi_of(r0, bx.psi_kind);
+    psi[N + n] = psi_of(r1, bx.psi_kind);
     if (!(r0 >= R(0)) || !(r1 >= R(0))) atomicOr(health, 1);
 }
 
 // ---------------------------------------------------------------- S2
 // Eq. (10): a solid node with fluid neighbours takes their mean density; the
 // particle colour is added to A if positive, its magnitude to B if negative.
+// Densities are recovered from the stored Psi (rho = -log(1 - Psi) for the
+// exponential form) and the result is stored as Psi again.
+template <class R>
+__device__ inline R rho_of_psi(R p, int kind) {
+    return kind == 0 ? p : -log1p(-p);
+}
+
 template <class R>
 __global__ __launch_bounds__(256) void k_shell(Box bx, R* __restrict__ rho, const uint32_t* __restrict__ owner,
                                                const double* __restrict__ part, int cap) {
@@ -110,8 +119,8 @@ __global__ __launch_bounds__(256) void k_shell(Box bx, R* __restrict__ rho, cons
     for (int i = 1; i < Q; i++) {
         const int64_t m = wrapc(x + cx(i), nx) + (int64_t)nx * (wrapc(y + cy(i), ny) + (int64_t)ny * wrapc(z + cz(i), nz));
         if (owner[m] == OWN_FLUID) {
-            s0 += rho[m];
-            s1 += rho[N + m];
+            s0 += rho_of_psi(rho[m], bx.psi_kind);
+            s1 += rho_of_psi(rho[N + m], bx.psi_kind);
             k++;
         }
     }
@@ -124,8 +133,8 @@ __global__ __launch_bounds__(256) void k_shell(Box bx, R* __restrict__ rho, cons
     const double dr = (o < OWN_WALL) ? part[DRHO * cap + o] : 0.0;
     if (dr > 0.0) a += R(dr);
     else if (dr < 0.0) b += R(-dr);
-    rho[n] = a;
-    rho[N + n] = b;
+    rho[n] = psi_of(a, bx.psi_kind);
+    rho[N + n] = psi_of(b, bx.psi_kind);
 }
 
 // ---------------------------------------------------------------- S3-S6
@@ -137,7 +146,7 @@ __global__ __launch_bounds__(256) void k_shell(Box bx, R* __restrict__ rho, cons
 template <class P, bool SOLID>
 __global__ __launch_bounds__(256) void k_fused(Box bx, const typename P::S* __restrict__ fs,
                                                typename P::S* __restrict__ fd,
-                                               const typename P::R* __restrict__ rho,
+                                               const typename P::R* __restrict__ psi,
                                                const uint32_t* __restrict__ owner, double* __restrict__ part,
                                                int cap, int BX, int BY, int tiles_x, int tiles_y) {
     using R = typename P::R;
@@ -195,8 +204,8 @@ __global__ __launch_bounds__(256) void k_fused(Box bx, const typename P::S* __re
 #pragma unroll
         for (int i = 1; i < Q; i++) {
             const int64_t m = LBE_NB(i);
-            const R p0 = psi_of(rho[m], kind);
-            const R p1 = psi_of(rho[N + m], kind);
+            const R p0 = psi[m];
+            const R p1 = psi[N + m];
             if (cx(i) > 0) { s0x += p0; s1x += p1; }
             if (cx(i) < 0) { s0x -= p0; s1x -= p1; }
             if (cy(i) > 0) { s0y += p0; s1y += p1; }

@@ -15,7 +15,7 @@ namespace lbe {
 // Device buffers of one system, carved from the caller's workspace.
 struct Buffers {
     void* f[2] = {nullptr, nullptr};   // populations [2][19][N] in the storage type
-    void* rho = nullptr;               // [2][N] (double for FP64, float otherwise)
+    void* rho = nullptr;               // Psi^c per node [2][N] (double for FP64, float otherwise)
     uint32_t* owner[2] = {nullptr, nullptr};
     double* part = nullptr;            // particle table, NPFIELD x cap
     double* red = nullptr;             // reduction partials, kRedBlocks x 8, then totals

@@ -95,7 +95,7 @@ class System:
     quat: np.ndarray = field(default_factory=lambda: np.zeros((0, 4)))
     delta_rho: np.ndarray = field(default_factory=lambda: np.zeros(0))
     density: np.ndarray = field(default_factory=lambda: np.zeros(0))
-    psi_kind: int = 0
+    psi_kind: int = 1  # Psi = 1 - exp(-rho), the default effective mass
     seed: int = 0
 
     @property
