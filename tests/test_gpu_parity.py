@@ -1,7 +1,8 @@
 """GPU (HIP, through the C ABI) against the CPU FP64 oracle on the same seeded
-inputs. Gates: FP64 <= 1e-12 relative after 100 steps (densities L-inf,
-velocity L2 over fluid nodes), owner map identical; FP32 <= 1e-5; reduced
-storage <= 1e-3 with the mass drift reported."""
+inputs. Gates: FP64 <= 1e-12 relative after 100 steps (densities L-inf over
+max |rho|; velocity L-inf over max(|u|_max, 1e-3), see parity_util), owner
+map identical; FP32 <= 1e-5; reduced storage <= 1e-3 with the mass drift
+reported."""
 import math
 
 import numpy as np
