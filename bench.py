@@ -70,7 +70,7 @@ def run_gpu(s, prec, steps, warmup, profile=True):
 
     from paper_1109_3277_amd.binding import Lattice
 
-    g = Lattice(s.dims, s.tau, s.g_br, s.psi_kind, prec, max_particles=max(1, s.n_particles))
+    g = Lattice(s.dims, s.tau, s.g_br, s.psi_kind, prec, max_particles=s.n_particles, max_radius=s.max_radius)
     g.init_fields(s.rho_a, s.rho_b)
     if s.n_particles:
         g.add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)

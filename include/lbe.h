@@ -42,7 +42,7 @@ extern "C" {
 #define LB_EHIP (-3)       /* a HIP runtime error; the message holds hipGetErrorString */
 #define LB_EUNSTABLE (-4)  /* NaN or negative density found during lb_step */
 #define LB_ESTATE (-5)     /* call-order violation (e.g. lb_step before lb_init_fields) */
-#define LB_EGEOM (-6)      /* particle radius <= 0, or bounding radius >= min(nx,ny,nz)/2 */
+#define LB_EGEOM (-6)      /* particle radius <= 0, or bounding radius > max_radius or >= min(nx,ny,nz)/2 */
 
 /* Storage / arithmetic forms of the populations. FP64 stores and computes in
  * double. FP32 stores and computes in float. FP16_DEV / BF16_DEV store the
@@ -56,7 +56,10 @@ typedef enum { LB_FP64 = 0, LB_FP32 = 1, LB_FP16_DEV = 2, LB_BF16_DEV = 3 } lb_p
  *  g_br      cross-component coupling g_AB = g_BA of Eq. (3); > 0 demixes.
  *  psi_kind  effective mass of Eq. (3): 1 -> Psi = 1 - exp(-rho) (recommended),
  *            0 -> Psi = rho.
- *  max_particles  particle capacity reserved in the workspace. */
+ *  max_particles  particle capacity reserved in the workspace.
+ *  max_radius     largest bounding radius max(R_par, R_perp) any particle
+ *                 may have (sizes the per-particle work space; must be > 0
+ *                 when max_particles > 0 and < min(nx, ny, nz) / 2). */
 typedef struct {
     int32_t nx, ny, nz;
     double tau;
@@ -64,6 +67,7 @@ typedef struct {
     int32_t psi_kind;
     int32_t precision; /* lb_precision */
     int32_t max_particles;
+    double max_radius;
 } lb_params;
 
 typedef struct lb_handle lb_handle;
@@ -83,7 +87,8 @@ void lb_destroy(lb_handle* h);
 /* Initial fields (Sec. 2; populations start at the equilibrium of Eq. (2)):
  * f_i^c = f_i^eq(rho^c, u) on every fluid node. rho_a, rho_b: N doubles each
  * (component A = red, B = blue). u: 3N doubles (x,y,z per node) or NULL for
- * rest. Must precede lb_add_ellipsoids and lb_step. */
+ * rest. Values are not screened: a NaN or negative density makes the next
+ * lb_step return LB_EUNSTABLE. Must precede lb_add_ellipsoids and lb_step. */
 int lb_init_fields(lb_handle* h, const double* rho_a, const double* rho_b, const double* u);
 
 /* Add n rigid ellipsoids (Sec. 2: particles discretised on the lattice,
@@ -100,7 +105,9 @@ int lb_add_ellipsoids(lb_handle* h, int32_t n, const double* radii, const double
  * BGK collision, streaming with moving bounce-back and particle force/torque,
  * rigid-body update, re-rasterisation with kill/fill). Work is enqueued on
  * the handle's stream; the call then waits for it to check the health flag and
- * returns LB_EUNSTABLE if a NaN or negative density appeared. */
+ * returns LB_EUNSTABLE if a NaN or negative density appeared, if a particle
+ * moved more than two lattice spacings in one step, or if particles crowd so
+ * that a fluid node links to more than two of them. */
 int lb_step(lb_handle* h, int32_t nsteps);
 
 /* Same as lb_step but does not wait: no health check; the stream is left
@@ -141,11 +148,12 @@ int lb_load_state(lb_handle* h, const void* host_buf, size_t bytes);
 
 /* Per-phase timing with HIP events recorded on the handle's stream around
  * every kernel launch of lb_step (phases: 0 densities, 1 shell fill, 2 fused
- * force/collide/stream, 3 rigid bodies, 4 raster (clear + rasterise), 5 kill /
- * fill). lb_profile_enable(h, 1) starts a fresh record, 0 stops recording.
+ * force/collide/stream with bounce-back, 3 particle force sums, 4 rigid
+ * bodies, 5 raster (clear + rasterise), 6 kill / fill). lb_profile_enable(h, 1)
+ * starts a fresh record, 0 stops recording.
  * lb_profile_read waits for the recorded events and writes, per phase, the
  * summed milliseconds and the number of launches (arrays of LB_NPHASES). */
-#define LB_NPHASES 6
+#define LB_NPHASES 7
 int lb_profile_enable(lb_handle* h, int on);
 int lb_profile_read(lb_handle* h, double* ms, int64_t* launches);
 

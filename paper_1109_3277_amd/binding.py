@@ -22,7 +22,7 @@ EXPORTED = [
     "lb_set_body_accel", "lb_state_bytes", "lb_save_state", "lb_load_state", "lb_last_error",
     "lb_profile_enable", "lb_profile_read",
 ]
-PHASES = ["density", "shell", "fused", "bodies", "raster", "killfill"]
+PHASES = ["density", "shell", "fused", "forces", "bodies", "raster", "killfill"]
 
 
 class LBError(RuntimeError):
@@ -34,7 +34,7 @@ class LBError(RuntimeError):
 class lb_params(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("tau", C.c_double),
                 ("g_br", C.c_double), ("psi_kind", C.c_int32), ("precision", C.c_int32),
-                ("max_particles", C.c_int32)]
+                ("max_particles", C.c_int32), ("max_radius", C.c_double)]
 
 
 _lib = None
@@ -89,10 +89,10 @@ def _f64(a, n=None):
     return a
 
 
-def make_params(dims, tau, g_br, psi_kind=1, precision="fp64", max_particles=0) -> lb_params:
+def make_params(dims, tau, g_br, psi_kind=1, precision="fp64", max_particles=0, max_radius=0.0) -> lb_params:
     nx, ny, nz = (int(v) for v in dims)
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    return lb_params(nx, ny, nz, float(tau), float(g_br), int(psi_kind), prec, int(max_particles))
+    return lb_params(nx, ny, nz, float(tau), float(g_br), int(psi_kind), prec, int(max_particles), float(max_radius))
 
 
 def workspace_bytes(params: lb_params) -> int:
@@ -102,11 +102,12 @@ def workspace_bytes(params: lb_params) -> int:
 class Lattice:
     """One periodic two-component system on the GPU (fields [z][y][x])."""
 
-    def __init__(self, dims, tau, g_br, psi_kind=1, precision="fp64", max_particles=0, device="cuda"):
+    def __init__(self, dims, tau, g_br, psi_kind=1, precision="fp64", max_particles=0, max_radius=0.0,
+                 device="cuda"):
         import torch
 
         L = load_library()
-        self.params = make_params(dims, tau, g_br, psi_kind, precision, max_particles)
+        self.params = make_params(dims, tau, g_br, psi_kind, precision, max_particles, max_radius)
         self.dims = tuple(int(v) for v in dims)
         self.N = self.dims[0] * self.dims[1] * self.dims[2]
         nbytes = L.lb_workspace_bytes(C.byref(self.params))

@@ -94,6 +94,11 @@ struct Box {
 };
 
 __device__ inline int wrapc(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+// periodic wrap of any integer coordinate
+__device__ inline int wrapc_any(int a, int n) {
+    a %= n;
+    return a < 0 ? a + n : a;
+}
 
 // Minimum-image difference along one periodic axis of length L.
 __device__ inline double minimg(double d, int L) {
@@ -108,12 +113,82 @@ __device__ inline R psi_of(R r, int kind) {
     if (kind == 0) return r;
     return -expm1(-r);
 }
+// Inverse of psi_of: rho = -log(1 - Psi) for the exponential form.
+template <class R>
+__device__ inline R rho_of_psi(R p, int kind) {
+    return kind == 0 ? p : -log1p(-p);
+}
 // Psi(rho)/rho, equal to 1 at rho = 0 for both kinds.
 template <class R>
 __device__ inline R psi_ratio(R r, int kind) {
     if (kind == 0) return R(1);
     if (r == R(0)) return R(1);
     return -expm1(-r) / r;
+}
+
+// Bounding box of particle p: first node lo[d] and extent sz[d] per axis;
+// false if the particle state is not usable (then nothing is touched).
+__device__ inline bool particle_box(const Box& bx, const double* part, int cap, int p, int lo[3], int sz[3]) {
+    const double X[3] = {part[PX * cap + p], part[PY * cap + p], part[PZ * cap + p]};
+    const double rpar = part[RPAR * cap + p], rperp = part[RPERP * cap + p];
+    const double rb = rpar > rperp ? rpar : rperp;
+    const int Ls[3] = {bx.nx, bx.ny, bx.nz};
+    for (int d = 0; d < 3; d++) {
+        if (!isfinite(X[d]) || !(rb < 0.5 * Ls[d])) return false;
+        lo[d] = (int)ceil(X[d] - rb);
+        sz[d] = max(0, min((int)floor(X[d] + rb) - lo[d] + 1, Ls[d]));
+    }
+    return true;
+}
+
+// Tiles of the fused kernel: BX x BY nodes of one xy-plane per 256-thread
+// block. Each tile keeps up to kTileSlots (particle, force, torque) slots for
+// the bounce-back links of its nodes (7 doubles each: id, F, T).
+constexpr int kTileSlots = 48;
+struct Tiles {
+    int BX, BY, tiles_x, tiles_y;
+};
+
+// Launch geometry of the per-particle kernels: one thread per node of a
+// particle's bounding box. grid = (particles, ext z-slices, tiles per slice),
+// flat one-wave blocks of B = 64 threads covering the ext x ext nodes of a
+// slice in `tiles` pieces. Each block owns one partial-sum slot
+// s = slice * tiles + tile, nslab slots per particle.
+struct Slab {
+    int ext;
+    int B;
+    int tiles;
+    int nslab;
+};
+
+// Node (ix, iy, iz) of the box this thread covers; false if none or outside
+// the particle's own extent sz.
+__device__ inline bool slab_node(const Slab& sl, const int sz[3], int& ix, int& iy, int& iz) {
+    const int t = blockIdx.z * sl.B + threadIdx.x;
+    iz = blockIdx.y;
+    if (t >= sl.ext * sl.ext) return false;
+    ix = t % sl.ext;
+    iy = t / sl.ext;
+    return ix < sz[0] && iy < sz[1] && iz < sz[2];
+}
+
+// Deterministic block sum of 6 doubles (every thread of the block calls it;
+// blockDim.x is a multiple of 64). The result is valid in thread 0.
+__device__ inline void block_sum6(double v[6], double out[6]) {
+    __shared__ double sh[16][6];
+#pragma unroll
+    for (int k = 0; k < 6; k++)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    if (lane == 0)
+        for (int k = 0; k < 6; k++) sh[w][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 6; k++) {
+            double s = 0.0;
+            for (int j = 0; j < nw; j++) s += sh[j][k];
+            out[k] = s;
+        }
 }
 
 }  // namespace lbe

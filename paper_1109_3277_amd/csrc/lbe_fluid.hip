@@ -1,12 +1,14 @@
-// Fluid kernels of liblbe (gfx950): densities, shell fill, the fused
-// force + collision + streaming + moving bounce-back step, initialisation,
-// field readout and deterministic FP64 reductions.
+// Fluid kernels of liblbe (gfx950): densities, the fused force + collision +
+// streaming step, initialisation, field readout and deterministic FP64
+// reductions.
 //
 // Layout in HBM: populations f[c][i][n] (structure of arrays, x fastest, one
 // plane of N values per (component, velocity)), two copies (current / next);
 // effective masses Psi[c][n]; owner map uint32 per node. One thread per node, tiles
 // of 64x4 (or 32x8) nodes of one xy-plane per 256-thread block, tiles of
 // neighbouring z on the same XCD.
+#include <limits.h>
+
 #include "lbe_internal.h"
 
 namespace lbe {
@@ -26,53 +28,13 @@ __device__ inline R feq_i(int i, R rho, R ux, R uy, R uz, R uu) {
     return R(wq(i)) * rho * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
 }
 
-// Wave64 reduction of per-lane particle force / torque contributions keyed by
-// particle index, then one set of FP64 atomics per particle touched by the
-// wave. Every lane of the wave must call this.
-__device__ inline void wave_flush(int pid, const double* acc, double* part, int cap) {
-    const int lane = __lane_id();
-    unsigned long long pend = __ballot(pid >= 0);
-    while (pend) {
-        const int leader = __ffsll((long long)pend) - 1;
-        const int p = __shfl(pid, leader, 64);
-        const bool mine = (pid == p);
-        double v[6];
-#pragma unroll
-        for (int k = 0; k < 6; k++) v[k] = mine ? acc[k] : 0.0;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-            for (int k = 0; k < 6; k++) v[k] += __shfl_xor(v[k], off, 64);
-        }
-        if (lane == leader) {
-            unsafeAtomicAdd(part + FX * cap + p, v[0]);
-            unsafeAtomicAdd(part + FY * cap + p, v[1]);
-            unsafeAtomicAdd(part + FZ * cap + p, v[2]);
-            unsafeAtomicAdd(part + TX * cap + p, v[3]);
-            unsafeAtomicAdd(part + TY * cap + p, v[4]);
-            unsafeAtomicAdd(part + TZ * cap + p, v[5]);
-        }
-        if (mine) pid = -1;
-        pend = __ballot(pid >= 0);
-    }
-}
-
-__device__ inline void flush_direct(int pid, const double* acc, double* part, int cap) {
-    unsafeAtomicAdd(part + FX * cap + pid, acc[0]);
-    unsafeAtomicAdd(part + FY * cap + pid, acc[1]);
-    unsafeAtomicAdd(part + FZ * cap + pid, acc[2]);
-    unsafeAtomicAdd(part + TX * cap + pid, acc[3]);
-    unsafeAtomicAdd(part + TY * cap + pid, acc[4]);
-    unsafeAtomicAdd(part + TZ * cap + pid, acc[5]);
-}
-
 // ---------------------------------------------------------------- S1
 // rho^c(n) = sum_i f_i^c(n) on fluid nodes, stored as the effective mass
-// Psi^c(n) of Eq. (3), the only form the force stencil reads; health flag on
-// NaN / rho < 0.
+// Psi^c(n) of Eq. (3) (what the force stencil reads) and, when the shell fill
+// needs it, as rho^c(n); health flag on NaN / rho < 0.
 template <class P, bool SOLID>
 __global__ __launch_bounds__(256) void k_density(Box bx, const typename P::S* __restrict__ f,
-                                                 typename P::R* __restrict__ psi,
+                                                 typename P::R* __restrict__ psi, typename P::R* __restrict__ rho,
                                                  const uint32_t* __restrict__ owner, int* __restrict__ health) {
     using R = typename P::R;
     const int64_t N = bx.N;
@@ -88,85 +50,54 @@ __global__ __launch_bounds__(256) void k_density(Box bx, const typename P::S* __
     }
     psi[n] = psi_of(r0, bx.psi_kind);
     psi[N + n] = psi_of(r1, bx.psi_kind);
+    if (rho) {  // densities themselves, for the shell fill (exponential Psi only)
+        rho[n] = r0;
+        rho[N + n] = r1;
+    }
     if (!(r0 >= R(0)) || !(r1 >= R(0))) atomicOr(health, 1);
-}
-
-// ---------------------------------------------------------------- S2
-// Eq. (10): a solid node with fluid neighbours takes their mean density; the
-// particle colour is added to A if positive, its magnitude to B if negative.
-// Densities are recovered from the stored Psi (rho = -log(1 - Psi) for the
-// exponential form) and the result is stored as Psi again.
-template <class R>
-__device__ inline R rho_of_psi(R p, int kind) {
-    return kind == 0 ? p : -log1p(-p);
-}
-
-template <class R>
-__global__ __launch_bounds__(256) void k_shell(Box bx, R* __restrict__ rho, const uint32_t* __restrict__ owner,
-                                               const double* __restrict__ part, int cap) {
-    const int64_t N = bx.N;
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
-    const uint32_t o = owner[n];
-    if (o == OWN_FLUID) return;
-    const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
-    const int x = (int)(n % nx);
-    const int y = (int)((n / nx) % ny);
-    const int z = (int)(n / ((int64_t)nx * ny));
-    R s0 = R(0), s1 = R(0);
-    int k = 0;
-#pragma unroll
-    for (int i = 1; i < Q; i++) {
-        const int64_t m = wrapc(x + cx(i), nx) + (int64_t)nx * (wrapc(y + cy(i), ny) + (int64_t)ny * wrapc(z + cz(i), nz));
-        if (owner[m] == OWN_FLUID) {
-            s0 += rho_of_psi(rho[m], bx.psi_kind);
-            s1 += rho_of_psi(rho[N + m], bx.psi_kind);
-            k++;
-        }
-    }
-    if (k == 0) {
-        rho[n] = R(0);
-        rho[N + n] = R(0);
-        return;
-    }
-    R a = s0 / R(k), b = s1 / R(k);
-    const double dr = (o < OWN_WALL) ? part[DRHO * cap + o] : 0.0;
-    if (dr > 0.0) a += R(dr);
-    else if (dr < 0.0) b += R(-dr);
-    rho[n] = psi_of(a, bx.psi_kind);
-    rho[N + n] = psi_of(b, bx.psi_kind);
 }
 
 // ---------------------------------------------------------------- S3-S6
 // Per fluid node: Shan-Chen force (Eq. (3)) from neighbour Psi, BGK collision
 // (Eq. (2)) with the common-velocity shift u^eq_c = u' + tau F^c/rho^c, then
-// push streaming (Eq. (1)); links into solid nodes bounce back with
-// C = 6 w_i rho^c (u_b . c_ibar) (Eq. (4)) and add (2 f*_i + C) c_i and its
-// torque about the particle centre to the particle (Eq. (5)).
+// push streaming (Eq. (1)). With solids present, a link i into a solid node
+// is replaced by moving bounce-back (Eq. (4)) in place:
+// f'_ibar(n) = f*_i(n) + C, C = 6 w_i rho^c(n) (u_b . c_ibar), and the
+// particle receives (2 f*_i + C) c_i (Eq. (5)). For a rigid body the surface
+// velocity at the link midpoint, V + W x (r_n + c_i/2), has the same
+// projection on c_i as U_n = V + W x r_n at the node (W x c_i is normal to
+// c_i), and the torque of all links of a node is r_n x their summed force
+// (c_i x c_i = 0): one U_n and one lever arm per node and particle (a node
+// may link to up to three particles; more raise health bit 4). Forces are
+// reduced per block, particle by particle in increasing index, into the
+// tile's slot list (deterministic); k_forces sums the slots per particle.
 template <class P, bool SOLID>
 __global__ __launch_bounds__(256) void k_fused(Box bx, const typename P::S* __restrict__ fs,
                                                typename P::S* __restrict__ fd,
                                                const typename P::R* __restrict__ psi,
-                                               const uint32_t* __restrict__ owner, double* __restrict__ part,
-                                               int cap, int BX, int BY, int tiles_x, int tiles_y) {
+                                               const uint32_t* __restrict__ owner, const double* __restrict__ part,
+                                               int cap, Tiles tl, int* __restrict__ tcount,
+                                               double* __restrict__ tslot, int* __restrict__ health) {
     using R = typename P::R;
     const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
     const int64_t N = bx.N;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    const int txy = tiles_x * tiles_y;
+    const int txy = tl.tiles_x * tl.tiles_y;
     const int z = tile / txy;
     const int rem = tile - z * txy;
-    const int ty = rem / tiles_x;
-    const int tx = rem - ty * tiles_x;
-    const int lx = threadIdx.x % BX, ly = threadIdx.x / BX;
-    const int x = tx * BX + lx, y = ty * BY + ly;
-
-    int pid = -1;
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-
+    const int ty = rem / tl.tiles_x;
+    const int tx = rem - ty * tl.tiles_x;
+    const int lx = threadIdx.x % tl.BX, ly = threadIdx.x / tl.BX;
+    const int x = tx * tl.BX + lx, y = ty * tl.BY + ly;
     const bool active = (x < nx) && (y < ny);
+    if (!SOLID && !active) return;
     const int64_t n = active ? (x + (int64_t)nx * (y + (int64_t)ny * z)) : 0;
     const bool fluid = active && (!SOLID || owner[n] == OWN_FLUID);
+
+    // particles touched by this node's links (at most three) and their sums
+    int pp[3] = {INT_MAX, INT_MAX, INT_MAX};
+    double acc[3][6] = {{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}};
+
     if (fluid) {
         // neighbour coordinates, indexed by velocity component 0, +1, -1
         const int xs[3] = {x, x + 1 == nx ? 0 : x + 1, x == 0 ? nx - 1 : x - 1};
@@ -229,62 +160,146 @@ __global__ __launch_bounds__(256) void k_fused(Box bx, const typename P::S* __re
             f0[i] = f0[i] - om * (f0[i] - feq_i(i, r0, u0x, u0y, u0z, uu0));
             f1[i] = f1[i] - om * (f1[i] - feq_i(i, r1, u1x, u1y, u1z, uu1));
         }
-        // streaming and bounce-back
         P::st(fd + n, f0[0], R(wq(0)) * ref0);
         P::st(fd + (size_t)Q * N + n, f1[0], R(wq(0)) * ref1);
+        if constexpr (!SOLID) {
 #pragma unroll
-        for (int i = 1; i < Q; i++) {
-            const int64_t m = LBE_NB(i);
-            bool solid = false;
-            uint32_t o = OWN_FLUID;
-            if (SOLID) {
-                o = owner[m];
-                solid = (o != OWN_FLUID);
-            }
-            if (!solid) {
+            for (int i = 1; i < Q; i++) {
+                const int64_t m = LBE_NB(i);
                 P::st(fd + (size_t)i * N + m, f0[i], R(wq(i)) * ref0);
                 P::st(fd + (size_t)(Q + i) * N + m, f1[i], R(wq(i)) * ref1);
-            } else {
-                double ubx = 0.0, uby = 0.0, ubz = 0.0, rx = 0.0, ry = 0.0, rz = 0.0;
-                const bool isp = (o < OWN_WALL);
-                if (isp) {
-                    rx = minimg(((double)x + 0.5 * cx(i)) - part[PX * cap + o], nx);
-                    ry = minimg(((double)y + 0.5 * cy(i)) - part[PY * cap + o], ny);
-                    rz = minimg(((double)z + 0.5 * cz(i)) - part[PZ * cap + o], nz);
-                    const double wx = part[WX * cap + o], wy = part[WY * cap + o], wz = part[WZ * cap + o];
-                    ubx = part[VX * cap + o] + (wy * rz - wz * ry);
-                    uby = part[VY * cap + o] + (wz * rx - wx * rz);
-                    ubz = part[VZ * cap + o] + (wx * ry - wy * rx);
-                }
-                // u_b . c_ibar = -(u_b . c_i)
-                const double cub = -(ubx * cx(i) + uby * cy(i) + ubz * cz(i));
-                const R C0 = R(6.0 * wq(i) * cub) * r0;
-                const R C1 = R(6.0 * wq(i) * cub) * r1;
-                const int b = opp(i);
-                P::st(fd + (size_t)b * N + n, f0[i] + C0, R(wq(b)) * ref0);
-                P::st(fd + (size_t)(Q + b) * N + n, f1[i] + C1, R(wq(b)) * ref1);
-                if (isp) {
-                    const double mag = 2.0 * ((double)f0[i] + (double)f1[i]) + ((double)C0 + (double)C1);
-                    const double dFx = mag * cx(i), dFy = mag * cy(i), dFz = mag * cz(i);
-                    if (pid != (int)o) {
-                        if (pid >= 0) flush_direct(pid, acc, part, cap);
-                        pid = (int)o;
+            }
+        } else {
+            uint32_t on[Q];
+            bool anys = false;
 #pragma unroll
-                        for (int k = 0; k < 6; k++) acc[k] = 0.0;
+            for (int i = 1; i < Q; i++) {
+                on[i] = owner[LBE_NB(i)];
+                anys |= (on[i] != OWN_FLUID);
+            }
+            if (!anys) {
+#pragma unroll
+                for (int i = 1; i < Q; i++) {
+                    const int64_t m = LBE_NB(i);
+                    P::st(fd + (size_t)i * N + m, f0[i], R(wq(i)) * ref0);
+                    P::st(fd + (size_t)(Q + i) * N + m, f1[i], R(wq(i)) * ref1);
+                }
+            } else {
+                // the (at most three) particles this node's links touch
+#pragma unroll
+                for (int i = 1; i < Q; i++) {
+                    const int o = (int)on[i];
+                    if (on[i] >= OWN_WALL || o == pp[0] || o == pp[1] || o == pp[2]) continue;
+                    if (pp[0] == INT_MAX) pp[0] = o;
+                    else if (pp[1] == INT_MAX) pp[1] = o;
+                    else if (pp[2] == INT_MAX) pp[2] = o;
+                    else atomicOr(health, 4);
+                }
+                double rr[3][3], uu[3][3];
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    const int q = pp[k];
+                    if (q == INT_MAX) {
+                        rr[k][0] = rr[k][1] = rr[k][2] = 0.0;
+                        uu[k][0] = uu[k][1] = uu[k][2] = 0.0;
+                        continue;
                     }
-                    acc[0] += dFx;
-                    acc[1] += dFy;
-                    acc[2] += dFz;
-                    acc[3] += ry * dFz - rz * dFy;
-                    acc[4] += rz * dFx - rx * dFz;
-                    acc[5] += rx * dFy - ry * dFx;
+                    rr[k][0] = minimg((double)x - part[PX * cap + q], nx);
+                    rr[k][1] = minimg((double)y - part[PY * cap + q], ny);
+                    rr[k][2] = minimg((double)z - part[PZ * cap + q], nz);
+                    const double wx = part[WX * cap + q], wy = part[WY * cap + q], wz = part[WZ * cap + q];
+                    uu[k][0] = part[VX * cap + q] + (wy * rr[k][2] - wz * rr[k][1]);
+                    uu[k][1] = part[VY * cap + q] + (wz * rr[k][0] - wx * rr[k][2]);
+                    uu[k][2] = part[VZ * cap + q] + (wx * rr[k][1] - wy * rr[k][0]);
+                }
+                double F[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+                for (int i = 1; i < Q; i++) {
+                    const uint32_t o = on[i];
+                    if (o == OWN_FLUID) {
+                        const int64_t m = LBE_NB(i);
+                        P::st(fd + (size_t)i * N + m, f0[i], R(wq(i)) * ref0);
+                        P::st(fd + (size_t)(Q + i) * N + m, f1[i], R(wq(i)) * ref1);
+                    } else {
+                        const bool isp = (o < OWN_WALL);
+                        const int k = (int)o == pp[1] ? 1 : ((int)o == pp[2] ? 2 : 0);
+                        const double Ux = isp ? (k == 1 ? uu[1][0] : (k == 2 ? uu[2][0] : uu[0][0])) : 0.0;
+                        const double Uy = isp ? (k == 1 ? uu[1][1] : (k == 2 ? uu[2][1] : uu[0][1])) : 0.0;
+                        const double Uz = isp ? (k == 1 ? uu[1][2] : (k == 2 ? uu[2][2] : uu[0][2])) : 0.0;
+                        // C = 6 w_i rho (u_b . c_ibar) = -6 w_i rho (U . c_i)
+                        const double cu = Ux * cx(i) + Uy * cy(i) + Uz * cz(i);
+                        const R C0 = R(-6.0 * wq(i) * cu) * r0;
+                        const R C1 = R(-6.0 * wq(i) * cu) * r1;
+                        const int b = opp(i);
+                        P::st(fd + (size_t)b * N + n, f0[i] + C0, R(wq(b)) * ref0);
+                        P::st(fd + (size_t)(Q + b) * N + n, f1[i] + C1, R(wq(b)) * ref1);
+                        const double mag = isp ? (2.0 * ((double)f0[i] + (double)f1[i]) + ((double)C0 + (double)C1)) : 0.0;
+#pragma unroll
+                        for (int kk = 0; kk < 3; kk++) {
+                            const double g = (k == kk) ? mag : 0.0;
+                            F[kk][0] += g * cx(i);
+                            F[kk][1] += g * cy(i);
+                            F[kk][2] += g * cz(i);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    acc[k][0] = F[k][0];
+                    acc[k][1] = F[k][1];
+                    acc[k][2] = F[k][2];
+                    acc[k][3] = rr[k][1] * F[k][2] - rr[k][2] * F[k][1];
+                    acc[k][4] = rr[k][2] * F[k][0] - rr[k][0] * F[k][2];
+                    acc[k][5] = rr[k][0] * F[k][1] - rr[k][1] * F[k][0];
                 }
             }
         }
 #undef LBE_NB
 #undef LBE_SEL
     }
-    if (SOLID) wave_flush(pid, acc, part, cap);
+    if constexpr (SOLID) {
+        // Per particle, in increasing index: block-wide deterministic sum of the
+        // lanes' contributions into the next slot of this tile.
+        __shared__ int s_min[4];
+        __shared__ double s_sum[4][6];
+        const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+        double* slots = tslot + (size_t)tile * kTileSlots * 7;
+        int nslot = 0;
+        while (true) {
+            int lm = min(pp[0], min(pp[1], pp[2]));
+            for (int off = 32; off > 0; off >>= 1) lm = min(lm, __shfl_xor(lm, off, 64));
+            if (lane == 0) s_min[w] = lm;
+            __syncthreads();
+            const int pm = min(min(s_min[0], s_min[1]), min(s_min[2], s_min[3]));
+            __syncthreads();
+            if (pm == INT_MAX) break;
+            double v[6];
+#pragma unroll
+            for (int k = 0; k < 6; k++)
+                v[k] = (pp[0] == pm ? acc[0][k] : 0.0) + (pp[1] == pm ? acc[1][k] : 0.0) + (pp[2] == pm ? acc[2][k] : 0.0);
+#pragma unroll
+            for (int k = 0; k < 6; k++)
+                for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+            if (lane == 0)
+                for (int k = 0; k < 6; k++) s_sum[w][k] = v[k];
+            __syncthreads();
+            if (tid == 0) {
+                if (nslot < kTileSlots) {
+                    double* o = slots + (size_t)nslot * 7;
+                    o[0] = (double)pm;
+                    for (int k = 0; k < 6; k++) o[1 + k] = ((s_sum[0][k] + s_sum[1][k]) + s_sum[2][k]) + s_sum[3][k];
+                } else {
+                    atomicOr(health, 4);
+                }
+            }
+            nslot++;
+#pragma unroll
+            for (int k = 0; k < 3; k++)
+                if (pp[k] == pm) pp[k] = INT_MAX;
+            __syncthreads();
+        }
+        if (tid == 0) tcount[tile] = min(nslot, kTileSlots);
+    }
 }
 
 // ---------------------------------------------------------------- init
@@ -446,49 +461,46 @@ hipError_t launch_init(lb_handle* h, const double* ra, const double* rb, const d
 }
 
 hipError_t launch_density(lb_handle* h) {
+    void* rho_out = (h->has_solid && h->prm.psi_kind != 0) ? h->b.rho : nullptr;
     if (h->has_solid) {
         LBE_DISPATCH(h->prm.precision,
                      hipLaunchKernelGGL((k_density<P, true>), dim3(nblk(h->box.N)), dim3(256), 0, h->stream, h->box,
-                                        (const typename P::S*)h->b.f[h->cur], (typename P::R*)h->b.rho,
-                                        h->b.owner[h->ocur], h->b.health));
+                                        (const typename P::S*)h->b.f[h->cur], (typename P::R*)h->b.psi,
+                                        (typename P::R*)rho_out, h->b.owner[h->ocur], h->b.health));
     } else {
         LBE_DISPATCH(h->prm.precision,
                      hipLaunchKernelGGL((k_density<P, false>), dim3(nblk(h->box.N)), dim3(256), 0, h->stream, h->box,
-                                        (const typename P::S*)h->b.f[h->cur], (typename P::R*)h->b.rho,
-                                        h->b.owner[h->ocur], h->b.health));
+                                        (const typename P::S*)h->b.f[h->cur], (typename P::R*)h->b.psi,
+                                        (typename P::R*)nullptr, h->b.owner[h->ocur], h->b.health));
     }
     return hipGetLastError();
 }
 
-hipError_t launch_shell(lb_handle* h) {
-    if (h->prm.precision == LB_FP64)
-        hipLaunchKernelGGL(k_shell<double>, dim3(nblk(h->box.N)), dim3(256), 0, h->stream, h->box,
-                           (double*)h->b.rho, h->b.owner[h->ocur], h->b.part, h->cap);
-    else
-        hipLaunchKernelGGL(k_shell<float>, dim3(nblk(h->box.N)), dim3(256), 0, h->stream, h->box,
-                           (float*)h->b.rho, h->b.owner[h->ocur], h->b.part, h->cap);
-    return hipGetLastError();
+Tiles fused_tiles(int nx, int ny) {
+    Tiles t;
+    t.BX = nx >= 64 ? 64 : 32;
+    t.BY = 256 / t.BX;
+    t.tiles_x = (nx + t.BX - 1) / t.BX;
+    t.tiles_y = (ny + t.BY - 1) / t.BY;
+    return t;
 }
 
 hipError_t launch_fused(lb_handle* h) {
-    const int BX = h->box.nx >= 64 ? 64 : 32;
-    const int BY = 256 / BX;
-    const int tiles_x = (h->box.nx + BX - 1) / BX;
-    const int tiles_y = (h->box.ny + BY - 1) / BY;
-    const unsigned grid = (unsigned)(tiles_x * tiles_y * h->box.nz);
+    const Tiles tl = fused_tiles(h->box.nx, h->box.ny);
+    const unsigned grid = (unsigned)(tl.tiles_x * tl.tiles_y * h->box.nz);
     const int o = h->cur, d = 1 - h->cur;
     if (h->has_solid) {
         LBE_DISPATCH(h->prm.precision,
                      hipLaunchKernelGGL((k_fused<P, true>), dim3(grid), dim3(256), 0, h->stream, h->box,
                                         (const typename P::S*)h->b.f[o], (typename P::S*)h->b.f[d],
-                                        (const typename P::R*)h->b.rho, h->b.owner[h->ocur], h->b.part, h->cap, BX, BY,
-                                        tiles_x, tiles_y));
+                                        (const typename P::R*)h->b.psi, h->b.owner[h->ocur], h->b.part, h->cap, tl,
+                                        h->b.tcount, h->b.tslot, h->b.health));
     } else {
         LBE_DISPATCH(h->prm.precision,
                      hipLaunchKernelGGL((k_fused<P, false>), dim3(grid), dim3(256), 0, h->stream, h->box,
                                         (const typename P::S*)h->b.f[o], (typename P::S*)h->b.f[d],
-                                        (const typename P::R*)h->b.rho, h->b.owner[h->ocur], h->b.part, h->cap, BX, BY,
-                                        tiles_x, tiles_y));
+                                        (const typename P::R*)h->b.psi, h->b.owner[h->ocur], h->b.part, h->cap, tl,
+                                        h->b.tcount, h->b.tslot, h->b.health));
     }
     return hipGetLastError();
 }

@@ -15,9 +15,13 @@ namespace lbe {
 // Device buffers of one system, carved from the caller's workspace.
 struct Buffers {
     void* f[2] = {nullptr, nullptr};   // populations [2][19][N] in the storage type
-    void* rho = nullptr;               // Psi^c per node [2][N] (double for FP64, float otherwise)
+    void* psi = nullptr;               // Psi^c per node [2][N] (double for FP64, float otherwise)
+    void* rho = nullptr;               // rho^c per node [2][N], for the shell fill (exponential Psi)
     uint32_t* owner[2] = {nullptr, nullptr};
     double* part = nullptr;            // particle table, NPFIELD x cap
+    int* tcount = nullptr;             // bounce-back slots used per fused tile
+    double* tslot = nullptr;           // per tile: kTileSlots x (particle, F, T)
+    double* kpart = nullptr;           // kill/fill impulse partial slots, cap x nslab x 6
     double* red = nullptr;             // reduction partials, kRedBlocks x 8, then totals
     double* counters = nullptr;        // [0] mass removed (cumulative), [1] kill mass, [2] fill mass
     int* health = nullptr;             // nonzero once a NaN / negative density was seen
@@ -38,6 +42,7 @@ struct lb_handle {
     int ocur = 0;        // index of the current owner map
     int np = 0, cap = 0;
     double rmax = 0.0;   // largest bounding radius of any particle
+    int64_t kpart_len = 0;  // doubles in the kill/fill slot buffer
     bool inited = false;
     bool has_solid = false;
     std::string err;
@@ -58,6 +63,8 @@ hipError_t launch_init(lb_handle* h, const double* d_rho_a, const double* d_rho_
 hipError_t launch_density(lb_handle* h);
 hipError_t launch_shell(lb_handle* h);
 hipError_t launch_fused(lb_handle* h);
+hipError_t launch_forces(lb_handle* h);
+Tiles fused_tiles(int nx, int ny);
 hipError_t launch_fields(lb_handle* h, double* d_out);       // rho_a, rho_b, u (5 x N doubles)
 hipError_t launch_stats(lb_handle* h);                       // totals into b.red[kRedBlocks*8 ...]
 hipError_t launch_remove_covered(lb_handle* h);
@@ -65,6 +72,10 @@ hipError_t launch_bodies(lb_handle* h);
 hipError_t launch_raster(lb_handle* h, uint32_t* owner, int first, int count);
 hipError_t launch_clear_owner(lb_handle* h, uint32_t* owner);
 hipError_t launch_killfill(lb_handle* h);
+hipError_t launch_fold_impulses(lb_handle* h);
+Slab make_slab(int ext);
+int raster_extent(int nx, int ny, int nz, double rb);
+int killfill_extent(int nx, int ny, int nz, double rb);
 hipError_t launch_fill_u32(lb_handle* h, uint32_t* p, uint32_t v, int64_t n);
 hipError_t launch_fill_f64(lb_handle* h, double* p, double v, int64_t n);
 

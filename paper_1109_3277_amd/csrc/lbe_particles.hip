@@ -1,6 +1,17 @@
-// Particle kernels of liblbe (gfx950): rigid-body update, rasterisation of the
-// ellipsoids onto the owner map, and kill / fill of nodes that change side.
+// Particle kernels of liblbe (gfx950): shell fill, the per-particle sum of the
+// bounce-back forces, rigid-body update, rasterisation of the ellipsoids onto
+// the owner map, and kill / fill of nodes that change side.
+//
+// Every per-node particle kernel runs one thread per node of a particle's
+// bounding box (Slab geometry, one-wave blocks), so the dependent loads of
+// neighbouring nodes are spread over many short-lived waves instead of looped.
+// Forces, torques and kill/fill impulses are summed in fixed orders (tile slot
+// lists, per-block partial slots): particle state is reproducible bit for bit.
 // Particle state is FP64 in every precision form.
+#include <math.h>
+
+#include <algorithm>
+
 #include "lbe_internal.h"
 
 namespace lbe {
@@ -32,23 +43,168 @@ __device__ inline bool inside_test(const double R[3][3], double dx, double dy, d
     return q <= 1.0;
 }
 
+__device__ inline int64_t node_index(const Box& bx, int x, int y, int z) {
+    return x + (int64_t)bx.nx * (y + (int64_t)bx.ny * z);
+}
+
+// ---------------------------------------------------------------- raster
+// Rasterise particles [first, first + gridDim.x) into owner with atomicMin:
+// the smallest index owns a node covered by several particles.
+__global__ void k_raster(Box bx, const double* __restrict__ part, int cap, uint32_t* __restrict__ owner, int first,
+                         Slab sl) {
+    const int p = first + blockIdx.x;
+    int lo[3], sz[3], ix, iy, iz;
+    if (!particle_box(bx, part, cap, p, lo, sz)) return;  // invalid state: touch nothing
+    if (!slab_node(sl, sz, ix, iy, iz)) return;
+    const int x = wrapc_any(lo[0] + ix, bx.nx), y = wrapc_any(lo[1] + iy, bx.ny), z = wrapc_any(lo[2] + iz, bx.nz);
+    const double X[3] = {part[PX * cap + p], part[PY * cap + p], part[PZ * cap + p]};
+    double R[3][3];
+    qrot(part[QW * cap + p], part[QX * cap + p], part[QY * cap + p], part[QZ * cap + p], R);
+    const double dx = minimg((double)x - X[0], bx.nx);
+    const double dy = minimg((double)y - X[1], bx.ny);
+    const double dz = minimg((double)z - X[2], bx.nz);
+    if (!inside_test(R, dx, dy, dz, part[RPAR * cap + p], part[RPERP * cap + p])) return;
+    const int64_t n = node_index(bx, x, y, z);
+    if (owner[n] == OWN_WALL) return;
+    atomicMin(owner + n, (uint32_t)p);
+}
+
+// ---------------------------------------------------------------- S2
+// Eq. (10): a node of particle p with fluid neighbours (over the 18 links)
+// takes their mean density; the particle colour is added to A if positive,
+// its magnitude to B if negative. Densities are recovered from the stored
+// Psi and the result is stored as Psi.
+template <class R>
+__global__ void k_shell(Box bx, R* __restrict__ psi, const R* __restrict__ rho, const uint32_t* __restrict__ owner,
+                        const double* __restrict__ part, int cap, Slab sl) {
+    const int p = blockIdx.x;
+    int lo[3], sz[3], ix, iy, iz;
+    if (!particle_box(bx, part, cap, p, lo, sz)) return;
+    if (!slab_node(sl, sz, ix, iy, iz)) return;
+    const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
+    const int x = wrapc_any(lo[0] + ix, nx), y = wrapc_any(lo[1] + iy, ny), z = wrapc_any(lo[2] + iz, nz);
+    const int64_t n = node_index(bx, x, y, z);
+    if (owner[n] != (uint32_t)p) return;
+    const int64_t N = bx.N;
+    // densities of fluid nodes: the stored rho (Psi itself when Psi = rho)
+    const R* dens = bx.psi_kind == 0 ? psi : rho;
+    int64_t mi[Q];
+    uint32_t on[Q];
+    R d0[Q], d1[Q];
+#pragma unroll
+    for (int i = 1; i < Q; i++) {
+        mi[i] = node_index(bx, wrapc(x + cx(i), nx), wrapc(y + cy(i), ny), wrapc(z + cz(i), nz));
+        on[i] = owner[mi[i]];
+        d0[i] = dens[mi[i]];
+        d1[i] = dens[N + mi[i]];
+    }
+    R s0 = R(0), s1 = R(0);
+    int k = 0;
+#pragma unroll
+    for (int i = 1; i < Q; i++) {
+        if (on[i] != OWN_FLUID) continue;
+        s0 += d0[i];
+        s1 += d1[i];
+        k++;
+    }
+    if (k == 0) {
+        psi[n] = R(0);
+        psi[N + n] = R(0);
+        return;
+    }
+    const double dr = part[DRHO * cap + p];
+    R a = s0 / R(k), b = s1 / R(k);
+    if (dr > 0.0) a += R(dr);
+    else if (dr < 0.0) b += R(-dr);
+    psi[n] = psi_of(a, bx.psi_kind);
+    psi[N + n] = psi_of(b, bx.psi_kind);
+}
+
+// ---------------------------------------------------------------- S6 forces
+// Bounce-back force and torque of particle p (Eq. (5)): the sum of the slots
+// that the fused kernel left for p in the tiles overlapping p's bounding box
+// grown by one node (a link's fluid end lies at most one node outside it),
+// tiles visited and summed in a fixed order.
+__global__ __launch_bounds__(256) void k_forces(Box bx, double* __restrict__ part, int cap, Tiles tl,
+                                                const int* __restrict__ tcount, const double* __restrict__ tslot) {
+    __shared__ int s_tx[512], s_ty[512], s_n[3], s_z0, s_ok;
+    const int p = blockIdx.x;
+    const int Ls[3] = {bx.nx, bx.ny, bx.nz};
+    if (threadIdx.x == 0) {
+        int lo[3], sz[3];
+        s_ok = particle_box(bx, part, cap, p, lo, sz) ? 1 : 0;
+        if (s_ok) {
+            // distinct x tiles, y tiles and z planes of the grown box
+            const int tdim[2] = {tl.BX, tl.BY};
+            int* lists[2] = {s_tx, s_ty};
+            for (int d = 0; d < 2; d++) {
+                const int a = lo[d] - 1, len = min(sz[d] + 2, Ls[d]);
+                int cnt = 0;
+                for (int v = a; v < a + len; v++) {
+                    const int t = wrapc_any(v, Ls[d]) / tdim[d];
+                    bool seen = false;
+                    for (int j = 0; j < cnt; j++) seen |= (lists[d][j] == t);
+                    if (!seen && cnt < 512) lists[d][cnt++] = t;
+                }
+                s_n[d] = cnt;
+            }
+            s_n[2] = min(sz[2] + 2, Ls[2]);
+            s_z0 = lo[2] - 1;
+        }
+    }
+    __syncthreads();
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    if (s_ok) {
+        const int ntx = s_n[0], nty = s_n[1], nzr = s_n[2], z0 = s_z0;
+        const int total = ntx * nty * nzr;
+        for (int t = threadIdx.x; t < total; t += blockDim.x) {
+            const int ix = t % ntx, iy = (t / ntx) % nty, iz = t / (ntx * nty);
+            const int z = wrapc_any(z0 + iz, Ls[2]);
+            const int tile = (z * tl.tiles_y + s_ty[iy]) * tl.tiles_x + s_tx[ix];
+            const int c = tcount[tile];
+            const double* sl = tslot + (size_t)tile * kTileSlots * 7;
+            for (int k = 0; k < c; k++) {
+                if ((int)sl[k * 7] != p) continue;
+                for (int j = 0; j < 6; j++) acc[j] += sl[k * 7 + 1 + j];
+            }
+        }
+    }
+    double tot[6];
+    block_sum6(acc, tot);
+    if (threadIdx.x == 0) {
+        const int f[6] = {FX, FY, FZ, TX, TY, TZ};
+        for (int k = 0; k < 6; k++) part[f[k] * cap + p] = tot[k];
+    }
+}
+
+// ---------------------------------------------------------------- S7
 // Newton-Euler update, dt = 1: F = F_links + J, T = T_links + H; V += F/M,
 // X = wrap(X + V); L += T; W = R I^-1 R^T L with the old orientation;
-// q <- normalise(exp(W/2) (x) q). Link accumulators and impulses are cleared.
-__global__ void k_bodies(Box bx, double* __restrict__ part, int cap, int np) {
+// q <- normalise(exp(W/2) (x) q). F_links / T_links come from k_forces; J / H
+// are the stored impulses plus the kill/fill slots, summed in order.
+__global__ void k_bodies(Box bx, double* __restrict__ part, int cap, int np, const double* __restrict__ kpart,
+                         int nk) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
     double* P = part;
 #define F_(k) P[(k) * cap + p]
+    const double Fl[6] = {F_(FX), F_(FY), F_(FZ), F_(TX), F_(TY), F_(TZ)};
+    double Jk[6] = {0, 0, 0, 0, 0, 0};
+    for (int s = 0; s < nk; s++)
+        for (int k = 0; k < 6; k++) Jk[k] += kpart[((size_t)p * nk + s) * 6 + k];
+    const double J[3] = {F_(JX) + Jk[0], F_(JY) + Jk[1], F_(JZ) + Jk[2]};
+    const double H[3] = {F_(HX) + Jk[3], F_(HY) + Jk[4], F_(HZ) + Jk[5]};
     double F[3], T[3];
-    F[0] = F_(FX) + F_(JX);
-    F[1] = F_(FY) + F_(JY);
-    F[2] = F_(FZ) + F_(JZ);
-    T[0] = F_(TX) + F_(HX);
-    T[1] = F_(TY) + F_(HY);
-    T[2] = F_(TZ) + F_(HZ);
-    F_(FX) = F_(FY) = F_(FZ) = 0.0;
-    F_(TX) = F_(TY) = F_(TZ) = 0.0;
+    for (int d = 0; d < 3; d++) {
+        F[d] = Fl[d] + J[d];
+        T[d] = Fl[3 + d] + H[d];
+    }
+    F_(FX) = Fl[0];
+    F_(FY) = Fl[1];
+    F_(FZ) = Fl[2];
+    F_(TX) = Fl[3];
+    F_(TY) = Fl[4];
+    F_(TZ) = Fl[5];
     F_(JX) = F_(JY) = F_(JZ) = 0.0;
     F_(HX) = F_(HY) = F_(HZ) = 0.0;
     F_(LFX) = F[0];
@@ -99,10 +255,10 @@ __global__ void k_bodies(Box bx, double* __restrict__ part, int cap, int np) {
         dz = sh * W[2];
     }
     // Hamilton product dq (x) q
-    double nw = dw * qw - dx * qx - dy * qy - dz * qz;
-    double nxq = dw * qx + dx * qw + dy * qz - dz * qy;
-    double nyq = dw * qy - dx * qz + dy * qw + dz * qx;
-    double nzq = dw * qz + dx * qy - dy * qx + dz * qw;
+    const double nw = dw * qw - dx * qx - dy * qy - dz * qz;
+    const double nxq = dw * qx + dx * qw + dy * qz - dz * qy;
+    const double nyq = dw * qy - dx * qz + dy * qw + dz * qx;
+    const double nzq = dw * qz + dx * qy - dy * qx + dz * qw;
     const double nn = sqrt(nw * nw + nxq * nxq + nyq * nyq + nzq * nzq);
     F_(QW) = nw / nn;
     F_(QX) = nxq / nn;
@@ -111,44 +267,22 @@ __global__ void k_bodies(Box bx, double* __restrict__ part, int cap, int np) {
 #undef F_
 }
 
-// Rasterise particles [first, first + gridDim.x) into owner with atomicMin
-// (smallest index wins). One block per particle, threads over its bounding box.
-__global__ __launch_bounds__(256) void k_raster(Box bx, const double* __restrict__ part, int cap,
-                                                uint32_t* __restrict__ owner, int first) {
-    const int p = first + blockIdx.x;
-    const double X[3] = {part[PX * cap + p], part[PY * cap + p], part[PZ * cap + p]};
-    const double rpar = part[RPAR * cap + p], rperp = part[RPERP * cap + p];
-    double R[3][3];
-    qrot(part[QW * cap + p], part[QX * cap + p], part[QY * cap + p], part[QZ * cap + p], R);
-    const double rb = rpar > rperp ? rpar : rperp;
-    const int Ls[3] = {bx.nx, bx.ny, bx.nz};
-    int lo[3], sz[3];
-    for (int d = 0; d < 3; d++) {
-        if (!isfinite(X[d]) || !(rb < 0.5 * Ls[d])) return;  // invalid state: touch nothing
-        lo[d] = (int)ceil(X[d] - rb);
-        sz[d] = (int)floor(X[d] + rb) - lo[d] + 1;
-        sz[d] = max(0, min(sz[d], Ls[d]));
-    }
-    const int total = sz[0] * sz[1] * sz[2];
-    for (int t = threadIdx.x; t < total; t += blockDim.x) {
-        const int ix = t % sz[0];
-        const int iy = (t / sz[0]) % sz[1];
-        const int iz = t / (sz[0] * sz[1]);
-        int c[3] = {lo[0] + ix, lo[1] + iy, lo[2] + iz};
-        for (int d = 0; d < 3; d++) {
-            c[d] %= Ls[d];
-            if (c[d] < 0) c[d] += Ls[d];
+// Pending kill/fill impulses: add the partial slots into the particle's J, H
+// and clear the slots (before the slot layout changes or the state is saved).
+__global__ void k_fold_impulses(double* __restrict__ part, int cap, int np, double* __restrict__ kpart, int nk) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    double J[6] = {0, 0, 0, 0, 0, 0};
+    for (int s = 0; s < nk; s++)
+        for (int k = 0; k < 6; k++) {
+            J[k] += kpart[((size_t)p * nk + s) * 6 + k];
+            kpart[((size_t)p * nk + s) * 6 + k] = 0.0;
         }
-        const double dx = minimg((double)c[0] - X[0], Ls[0]);
-        const double dy = minimg((double)c[1] - X[1], Ls[1]);
-        const double dz = minimg((double)c[2] - X[2], Ls[2]);
-        if (!inside_test(R, dx, dy, dz, rpar, rperp)) continue;
-        const int64_t n = c[0] + (int64_t)Ls[0] * (c[1] + (int64_t)Ls[1] * c[2]);
-        if (owner[n] == OWN_WALL) continue;
-        atomicMin(owner + n, (uint32_t)p);
-    }
+    const int fld[6] = {JX, JY, JZ, HX, HY, HZ};
+    for (int k = 0; k < 6; k++) part[fld[k] * cap + p] += J[k];
 }
 
+// ---------------------------------------------------------------- S8
 template <class R>
 __device__ inline R feq_p(int i, R rho, R ux, R uy, R uz) {
     const R uu = ux * ux + uy * uy + uz * uz;
@@ -162,111 +296,175 @@ __device__ inline R feq_p(int i, R rho, R ux, R uy, R uz) {
 //   o == p, o2 fluid : fill  -> rho_new^c = mean rho^c of neighbours fluid
 //                      before and after (initial mean if none), u = V + W x r,
 //                      f = f^eq(rho_new^c, u), J_p -= sum_c rho_new^c u, H_p -= r x that.
-// Each changing node is handled by exactly one block (its owner).
+// Each changing node is handled by exactly one thread (of its owner's grid).
+// Impulses go to the block's partial slot; a move the union box cannot cover
+// raises health bit 2.
 template <class P>
-__global__ __launch_bounds__(256) void k_killfill(Box bx, typename P::S* __restrict__ f,
-                                                  const uint32_t* __restrict__ own_old,
-                                                  const uint32_t* __restrict__ own_new, double* __restrict__ part,
-                                                  int cap, double* __restrict__ counters) {
+__global__ void k_killfill(Box bx, typename P::S* __restrict__ f, const uint32_t* __restrict__ own_old,
+                           const uint32_t* __restrict__ own_new, const double* __restrict__ part, int cap, Slab sl,
+                           double* __restrict__ kpart, double* __restrict__ counters, int* __restrict__ health) {
     using R = typename P::R;
     const int64_t N = bx.N;
     const int p = blockIdx.x;
     const int Ls[3] = {bx.nx, bx.ny, bx.nz};
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int lo[3] = {0, 0, 0}, sz[3] = {0, 0, 0}, ix = 0, iy = 0, iz = 0;
+    bool ok = true;
     const double Xn[3] = {part[PX * cap + p], part[PY * cap + p], part[PZ * cap + p]};
     const double Xo[3] = {part[OX * cap + p], part[OY * cap + p], part[OZ * cap + p]};
     const double rpar = part[RPAR * cap + p], rperp = part[RPERP * cap + p];
     const double rb = rpar > rperp ? rpar : rperp;
-    int lo[3], sz[3];
     for (int d = 0; d < 3; d++) {
-        if (!isfinite(Xn[d]) || !isfinite(Xo[d]) || !(rb < 0.5 * Ls[d])) return;  // invalid state
+        if (!isfinite(Xn[d]) || !isfinite(Xo[d]) || !(rb < 0.5 * Ls[d])) {
+            ok = false;
+            break;
+        }
         const double xn = Xo[d] + minimg(Xn[d] - Xo[d], Ls[d]);  // unwrapped new centre
         const int a = min((int)ceil(Xo[d] - rb), (int)ceil(xn - rb));
         const int b = max((int)floor(Xo[d] + rb), (int)floor(xn + rb));
         lo[d] = a;
         sz[d] = max(0, min(b - a + 1, Ls[d]));
+        if (sz[d] > sl.ext && threadIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) atomicOr(health, 2);
     }
-    const double V[3] = {part[VX * cap + p], part[VY * cap + p], part[VZ * cap + p]};
-    const double W[3] = {part[WX * cap + p], part[WY * cap + p], part[WZ * cap + p]};
-    const int total = sz[0] * sz[1] * sz[2];
-    for (int t = threadIdx.x; t < total; t += blockDim.x) {
-        int c[3] = {lo[0] + t % sz[0], lo[1] + (t / sz[0]) % sz[1], lo[2] + t / (sz[0] * sz[1])};
-        for (int d = 0; d < 3; d++) {
-            c[d] %= Ls[d];
-            if (c[d] < 0) c[d] += Ls[d];
-        }
-        const int64_t n = c[0] + (int64_t)Ls[0] * (c[1] + (int64_t)Ls[1] * c[2]);
+    if (ok) ok = slab_node(sl, sz, ix, iy, iz);
+    if (ok) {
+        const int x = wrapc_any(lo[0] + ix, Ls[0]), y = wrapc_any(lo[1] + iy, Ls[1]), z = wrapc_any(lo[2] + iz, Ls[2]);
+        const int64_t n = node_index(bx, x, y, z);
         const uint32_t o = own_old[n], o2 = own_new[n];
         const bool kill = (o == OWN_FLUID && o2 == (uint32_t)p);
         const bool fill = (o == (uint32_t)p && o2 == OWN_FLUID);
-        if (!kill && !fill) continue;
-        const double r[3] = {minimg((double)c[0] - Xn[0], Ls[0]), minimg((double)c[1] - Xn[1], Ls[1]),
-                             minimg((double)c[2] - Xn[2], Ls[2])};
-        if (kill) {
-            double j[3] = {0.0, 0.0, 0.0}, m = 0.0;
-            for (int cc = 0; cc < 2; cc++) {
-                const R ref = R(bx.rref[cc]);
-#pragma unroll
-                for (int i = 0; i < Q; i++) {
-                    typename P::S* ptr = f + (size_t)(cc * Q + i) * N + n;
-                    const double v = (double)P::ld(ptr, R(wq(i)) * ref);
-                    m += v;
-                    j[0] += v * cx(i);
-                    j[1] += v * cy(i);
-                    j[2] += v * cz(i);
-                    P::st(ptr, R(0), R(wq(i)) * ref);
-                }
-            }
-            unsafeAtomicAdd(part + JX * cap + p, j[0]);
-            unsafeAtomicAdd(part + JY * cap + p, j[1]);
-            unsafeAtomicAdd(part + JZ * cap + p, j[2]);
-            unsafeAtomicAdd(part + HX * cap + p, r[1] * j[2] - r[2] * j[1]);
-            unsafeAtomicAdd(part + HY * cap + p, r[2] * j[0] - r[0] * j[2]);
-            unsafeAtomicAdd(part + HZ * cap + p, r[0] * j[1] - r[1] * j[0]);
-            unsafeAtomicAdd(counters + 0, m);
-            unsafeAtomicAdd(counters + 1, m);
-        } else {
-            double rn[2] = {0.0, 0.0};
-            int cnt = 0;
-#pragma unroll
-            for (int i = 1; i < Q; i++) {
-                const int64_t m = wrapc(c[0] + cx(i), Ls[0]) +
-                                  (int64_t)Ls[0] * (wrapc(c[1] + cy(i), Ls[1]) + (int64_t)Ls[1] * wrapc(c[2] + cz(i), Ls[2]));
-                if (own_old[m] != OWN_FLUID || own_new[m] != OWN_FLUID) continue;
+        if (kill || fill) {
+            const double r[3] = {minimg((double)x - Xn[0], Ls[0]), minimg((double)y - Xn[1], Ls[1]),
+                                 minimg((double)z - Xn[2], Ls[2])};
+            if (kill) {
+                double j[3] = {0.0, 0.0, 0.0}, m = 0.0;
                 for (int cc = 0; cc < 2; cc++) {
                     const R ref = R(bx.rref[cc]);
-                    double s = 0.0;
-                    for (int q = 0; q < Q; q++) s += (double)P::ld(f + (size_t)(cc * Q + q) * N + m, R(wq(q)) * ref);
-                    rn[cc] += s;
-                }
-                cnt++;
-            }
-            for (int cc = 0; cc < 2; cc++) rn[cc] = cnt > 0 ? rn[cc] / (double)cnt : bx.rmean0[cc];
-            const double ub[3] = {V[0] + (W[1] * r[2] - W[2] * r[1]), V[1] + (W[2] * r[0] - W[0] * r[2]),
-                                  V[2] + (W[0] * r[1] - W[1] * r[0])};
-            double jm[3] = {0.0, 0.0, 0.0};
-            for (int cc = 0; cc < 2; cc++) {
-                const R ref = R(bx.rref[cc]);
 #pragma unroll
-                for (int i = 0; i < Q; i++)
-                    P::st(f + (size_t)(cc * Q + i) * N + n, R(feq_p<double>(i, rn[cc], ub[0], ub[1], ub[2])),
-                          R(wq(i)) * ref);
-                for (int d = 0; d < 3; d++) jm[d] += rn[cc] * ub[d];
+                    for (int i = 0; i < Q; i++) {
+                        typename P::S* ptr = f + (size_t)(cc * Q + i) * N + n;
+                        const double v = (double)P::ld(ptr, R(wq(i)) * ref);
+                        m += v;
+                        j[0] += v * cx(i);
+                        j[1] += v * cy(i);
+                        j[2] += v * cz(i);
+                        P::st(ptr, R(0), R(wq(i)) * ref);
+                    }
+                }
+                acc[0] = j[0];
+                acc[1] = j[1];
+                acc[2] = j[2];
+                acc[3] = r[1] * j[2] - r[2] * j[1];
+                acc[4] = r[2] * j[0] - r[0] * j[2];
+                acc[5] = r[0] * j[1] - r[1] * j[0];
+                unsafeAtomicAdd(counters + 0, m);
+                unsafeAtomicAdd(counters + 1, m);
+            } else {
+                const double V[3] = {part[VX * cap + p], part[VY * cap + p], part[VZ * cap + p]};
+                const double W[3] = {part[WX * cap + p], part[WY * cap + p], part[WZ * cap + p]};
+                double rn[2] = {0.0, 0.0};
+                int cnt = 0;
+#pragma unroll
+                for (int i = 1; i < Q; i++) {
+                    const int64_t m =
+                        node_index(bx, wrapc(x + cx(i), Ls[0]), wrapc(y + cy(i), Ls[1]), wrapc(z + cz(i), Ls[2]));
+                    if (own_old[m] != OWN_FLUID || own_new[m] != OWN_FLUID) continue;
+                    for (int cc = 0; cc < 2; cc++) {
+                        const R ref = R(bx.rref[cc]);
+                        double s = 0.0;
+                        for (int q = 0; q < Q; q++) s += (double)P::ld(f + (size_t)(cc * Q + q) * N + m, R(wq(q)) * ref);
+                        rn[cc] += s;
+                    }
+                    cnt++;
+                }
+                for (int cc = 0; cc < 2; cc++) rn[cc] = cnt > 0 ? rn[cc] / (double)cnt : bx.rmean0[cc];
+                const double ub[3] = {V[0] + (W[1] * r[2] - W[2] * r[1]), V[1] + (W[2] * r[0] - W[0] * r[2]),
+                                      V[2] + (W[0] * r[1] - W[1] * r[0])};
+                double jm[3] = {0.0, 0.0, 0.0};
+                for (int cc = 0; cc < 2; cc++) {
+                    const R ref = R(bx.rref[cc]);
+#pragma unroll
+                    for (int i = 0; i < Q; i++)
+                        P::st(f + (size_t)(cc * Q + i) * N + n, R(feq_p<double>(i, rn[cc], ub[0], ub[1], ub[2])),
+                              R(wq(i)) * ref);
+                    for (int d = 0; d < 3; d++) jm[d] += rn[cc] * ub[d];
+                }
+                acc[0] = -jm[0];
+                acc[1] = -jm[1];
+                acc[2] = -jm[2];
+                acc[3] = -(r[1] * jm[2] - r[2] * jm[1]);
+                acc[4] = -(r[2] * jm[0] - r[0] * jm[2]);
+                acc[5] = -(r[0] * jm[1] - r[1] * jm[0]);
+                unsafeAtomicAdd(counters + 0, -(rn[0] + rn[1]));
+                unsafeAtomicAdd(counters + 2, rn[0] + rn[1]);
             }
-            unsafeAtomicAdd(part + JX * cap + p, -jm[0]);
-            unsafeAtomicAdd(part + JY * cap + p, -jm[1]);
-            unsafeAtomicAdd(part + JZ * cap + p, -jm[2]);
-            unsafeAtomicAdd(part + HX * cap + p, -(r[1] * jm[2] - r[2] * jm[1]));
-            unsafeAtomicAdd(part + HY * cap + p, -(r[2] * jm[0] - r[0] * jm[2]));
-            unsafeAtomicAdd(part + HZ * cap + p, -(r[0] * jm[1] - r[1] * jm[0]));
-            unsafeAtomicAdd(counters + 0, -(rn[0] + rn[1]));
-            unsafeAtomicAdd(counters + 2, rn[0] + rn[1]);
         }
     }
+    double tot[6];
+    block_sum6(acc, tot);
+    if (threadIdx.x == 0) {
+        double* o = kpart + ((size_t)p * sl.nslab + blockIdx.y * sl.tiles + blockIdx.z) * 6;
+        for (int k = 0; k < 6; k++) o[k] = tot[k];
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+Slab make_slab(int ext) {
+    Slab s;
+    s.ext = ext < 1 ? 1 : ext;
+    s.B = 64;
+    s.tiles = (s.ext * s.ext + 63) / 64;
+    s.nslab = s.ext * s.tiles;
+    return s;
+}
+
+// Extent of the raster box for bounding radius rb: floor(2 rb) + 1, at most
+// the longest side; the kill/fill union box has two more nodes.
+int raster_extent(int nx, int ny, int nz, double rb) {
+    const int L = std::max(nx, std::max(ny, nz));
+    return std::min((int)floor(2.0 * rb) + 1, L);
+}
+int killfill_extent(int nx, int ny, int nz, double rb) {
+    const int L = std::max(nx, std::max(ny, nz));
+    return std::min(raster_extent(nx, ny, nz, rb) + 2, L);
+}
+Slab slab_raster(const lb_handle* h) { return make_slab(raster_extent(h->box.nx, h->box.ny, h->box.nz, h->rmax)); }
+Slab slab_killfill(const lb_handle* h) {
+    return make_slab(killfill_extent(h->box.nx, h->box.ny, h->box.nz, h->rmax));
+}
+
+hipError_t launch_shell(lb_handle* h) {
+    if (h->np <= 0) return hipSuccess;
+    const Slab s = slab_raster(h);
+    const dim3 g(h->np, s.ext, s.tiles);
+    if (h->prm.precision == LB_FP64)
+        hipLaunchKernelGGL(k_shell<double>, g, dim3(s.B), 0, h->stream, h->box, (double*)h->b.psi,
+                           (const double*)h->b.rho, h->b.owner[h->ocur], h->b.part, h->cap, s);
+    else
+        hipLaunchKernelGGL(k_shell<float>, g, dim3(s.B), 0, h->stream, h->box, (float*)h->b.psi,
+                           (const float*)h->b.rho, h->b.owner[h->ocur], h->b.part, h->cap, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_forces(lb_handle* h) {
+    if (h->np <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_forces, dim3(h->np), dim3(256), 0, h->stream, h->box, h->b.part, h->cap,
+                       fused_tiles(h->box.nx, h->box.ny), h->b.tcount, h->b.tslot);
+    return hipGetLastError();
 }
 
 hipError_t launch_bodies(lb_handle* h) {
     if (h->np <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bodies, dim3((h->np + 63) / 64), dim3(64), 0, h->stream, h->box, h->b.part, h->cap, h->np);
+    hipLaunchKernelGGL(k_bodies, dim3((h->np + 63) / 64), dim3(64), 0, h->stream, h->box, h->b.part, h->cap, h->np,
+                       h->b.kpart, slab_killfill(h).nslab);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_impulses(lb_handle* h) {
+    if (h->np <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fold_impulses, dim3((h->np + 63) / 64), dim3(64), 0, h->stream, h->b.part, h->cap, h->np,
+                       h->b.kpart, slab_killfill(h).nslab);
     return hipGetLastError();
 }
 
@@ -274,7 +472,9 @@ hipError_t launch_clear_owner(lb_handle* h, uint32_t* owner) { return launch_fil
 
 hipError_t launch_raster(lb_handle* h, uint32_t* owner, int first, int count) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_raster, dim3(count), dim3(256), 0, h->stream, h->box, h->b.part, h->cap, owner, first);
+    const Slab s = slab_raster(h);
+    hipLaunchKernelGGL(k_raster, dim3(count, s.ext, s.tiles), dim3(s.B), 0, h->stream, h->box, h->b.part, h->cap, owner,
+                       first, s);
     return hipGetLastError();
 }
 
@@ -283,22 +483,24 @@ hipError_t launch_killfill(lb_handle* h) {
     uint32_t* oo = h->b.owner[h->ocur];
     uint32_t* on = h->b.owner[1 - h->ocur];
     void* fn = h->b.f[1 - h->cur];
+    const Slab s = slab_killfill(h);
+    const dim3 g(h->np, s.ext, s.tiles);
     switch (h->prm.precision) {
         case LB_FP64:
-            hipLaunchKernelGGL(k_killfill<PolF64>, dim3(h->np), dim3(256), 0, h->stream, h->box, (double*)fn, oo, on,
-                               h->b.part, h->cap, h->b.counters);
+            hipLaunchKernelGGL(k_killfill<PolF64>, g, dim3(s.B), 0, h->stream, h->box, (double*)fn, oo, on, h->b.part,
+                               h->cap, s, h->b.kpart, h->b.counters, h->b.health);
             break;
         case LB_FP32:
-            hipLaunchKernelGGL(k_killfill<PolF32>, dim3(h->np), dim3(256), 0, h->stream, h->box, (float*)fn, oo, on,
-                               h->b.part, h->cap, h->b.counters);
+            hipLaunchKernelGGL(k_killfill<PolF32>, g, dim3(s.B), 0, h->stream, h->box, (float*)fn, oo, on, h->b.part,
+                               h->cap, s, h->b.kpart, h->b.counters, h->b.health);
             break;
         case LB_FP16_DEV:
-            hipLaunchKernelGGL(k_killfill<PolF16>, dim3(h->np), dim3(256), 0, h->stream, h->box, (__half*)fn, oo, on,
-                               h->b.part, h->cap, h->b.counters);
+            hipLaunchKernelGGL(k_killfill<PolF16>, g, dim3(s.B), 0, h->stream, h->box, (__half*)fn, oo, on, h->b.part,
+                               h->cap, s, h->b.kpart, h->b.counters, h->b.health);
             break;
         default:
-            hipLaunchKernelGGL(k_killfill<PolBF16>, dim3(h->np), dim3(256), 0, h->stream, h->box,
-                               (__hip_bfloat16*)fn, oo, on, h->b.part, h->cap, h->b.counters);
+            hipLaunchKernelGGL(k_killfill<PolBF16>, g, dim3(s.B), 0, h->stream, h->box, (__hip_bfloat16*)fn, oo, on,
+                               h->b.part, h->cap, s, h->b.kpart, h->b.counters, h->b.health);
             break;
     }
     return hipGetLastError();

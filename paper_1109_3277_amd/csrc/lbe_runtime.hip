@@ -39,11 +39,18 @@ bool params_ok(const lb_params* p, std::string* why) {
     if (p->psi_kind != 0 && p->psi_kind != 1) { *why = "psi_kind must be 0 or 1"; return false; }
     if (p->precision < LB_FP64 || p->precision > LB_BF16_DEV) { *why = "unknown precision"; return false; }
     if (p->max_particles < 0) { *why = "max_particles must be >= 0"; return false; }
+    if (p->max_particles > 0) {
+        const double minL = (double)std::min(p->nx, std::min(p->ny, p->nz));
+        if (!(p->max_radius > 0.0) || !(p->max_radius < 0.5 * minL)) {
+            *why = "max_radius must be > 0 and < min(nx, ny, nz)/2 when particles are allowed";
+            return false;
+        }
+    }
     return true;
 }
 
 struct Layout {
-    size_t f, rho, owner, part, red, counters, health, total;
+    size_t f, psi, rho, owner, part, tcount, tslot, kpart, red, counters, health, total;
 };
 
 Layout layout_of(const lb_params* p) {
@@ -51,13 +58,22 @@ Layout layout_of(const lb_params* p) {
     const size_t cap = (size_t)std::max(p->max_particles, 1);
     Layout L;
     L.f = align_up(2 * Q * N * elem_bytes(p->precision));
-    L.rho = align_up(2 * N * rho_elem_bytes(p->precision));
+    L.psi = align_up(2 * N * rho_elem_bytes(p->precision));
+    L.rho = p->max_particles > 0 ? align_up(2 * N * rho_elem_bytes(p->precision)) : 0;
     L.owner = align_up(N * sizeof(uint32_t));
     L.part = align_up(NPFIELD * cap * sizeof(double));
+    const double rmax = p->max_particles > 0 ? p->max_radius : 0.5;
+    const Slab s2 = make_slab(killfill_extent(p->nx, p->ny, p->nz, rmax));
+    const Tiles tl = fused_tiles(p->nx, p->ny);
+    const size_t ntiles = (size_t)tl.tiles_x * tl.tiles_y * p->nz;
+    L.tcount = p->max_particles > 0 ? align_up(ntiles * sizeof(int)) : 0;
+    L.tslot = p->max_particles > 0 ? align_up(ntiles * kTileSlots * 7 * sizeof(double)) : 0;
+    L.kpart = align_up(cap * (size_t)s2.nslab * 6 * sizeof(double));
     L.red = align_up((kRedBlocks + 1) * 8 * sizeof(double));
     L.counters = align_up(8 * sizeof(double));
     L.health = align_up(sizeof(int));
-    L.total = 2 * L.f + L.rho + 2 * L.owner + L.part + L.red + L.counters + L.health;
+    L.total = 2 * L.f + L.psi + L.rho + 2 * L.owner + L.part + L.tcount + L.tslot + L.kpart + L.red + L.counters +
+              L.health;
     return L;
 }
 
@@ -91,16 +107,17 @@ hipError_t mark(lb_handle* h, int phase, bool start) {
 
 int enqueue_step(lb_handle* h) {
     LBE_PHASE(h, 0, launch_density(h));
-    if (h->has_solid) LBE_PHASE(h, 1, launch_shell(h));
+    if (h->np > 0) LBE_PHASE(h, 1, launch_shell(h));
     LBE_PHASE(h, 2, launch_fused(h));
     if (h->np > 0) {
-        LBE_PHASE(h, 3, launch_bodies(h));
+        LBE_PHASE(h, 3, launch_forces(h));
+        LBE_PHASE(h, 4, launch_bodies(h));
         uint32_t* on = h->b.owner[1 - h->ocur];
-        LBE_HIP(h, mark(h, 4, true));
+        LBE_HIP(h, mark(h, 5, true));
         LBE_HIP(h, launch_clear_owner(h, on));
         LBE_HIP(h, launch_raster(h, on, 0, h->np));
-        LBE_HIP(h, mark(h, 4, false));
-        LBE_PHASE(h, 5, launch_killfill(h));
+        LBE_HIP(h, mark(h, 5, false));
+        LBE_PHASE(h, 6, launch_killfill(h));
         h->ocur = 1 - h->ocur;
     }
     h->cur = 1 - h->cur;
@@ -147,10 +164,14 @@ int lb_create(const lb_params* prm, void* dev_ws, size_t ws_bytes, void* hip_str
     char* p = h->ws;
     h->b.f[0] = p; p += L.f;
     h->b.f[1] = p; p += L.f;
-    h->b.rho = p; p += L.rho;
+    h->b.psi = p; p += L.psi;
+    h->b.rho = L.rho ? p : nullptr; p += L.rho;
     h->b.owner[0] = (uint32_t*)p; p += L.owner;
     h->b.owner[1] = (uint32_t*)p; p += L.owner;
     h->b.part = (double*)p; p += L.part;
+    h->b.tcount = L.tcount ? (int*)p : nullptr; p += L.tcount;
+    h->b.tslot = L.tslot ? (double*)p : nullptr; p += L.tslot;
+    h->b.kpart = (double*)p; p += L.kpart;
     h->b.red = (double*)p; p += L.red;
     h->b.counters = (double*)p; p += L.counters;
     h->b.health = (int*)p; p += L.health;
@@ -161,6 +182,8 @@ int lb_create(const lb_params* prm, void* dev_ws, size_t ws_bytes, void* hip_str
     chk(launch_fill_u32(h, h->b.owner[0], OWN_FLUID, b.N), "clear owner");
     chk(launch_fill_u32(h, h->b.owner[1], OWN_FLUID, b.N), "clear owner");
     chk(launch_fill_f64(h, h->b.part, 0.0, (int64_t)NPFIELD * h->cap), "clear particles");
+    chk(launch_fill_f64(h, h->b.kpart, 0.0, (int64_t)(L.kpart / sizeof(double))), "clear impulse slots");
+    h->kpart_len = (int64_t)(L.kpart / sizeof(double));
     chk(launch_fill_f64(h, h->b.counters, 0.0, 8), "clear counters");
     chk(launch_fill_u32(h, (uint32_t*)h->b.health, 0u, 1), "clear health");
     chk(hipStreamSynchronize(h->stream), "synchronize");
@@ -244,6 +267,8 @@ int lb_add_ellipsoids(lb_handle* h, int32_t n, const double* radii, const double
             return fail(h, LB_EGEOM, "particle " + std::to_string(k) + ": radii must be finite and > 0");
         if (!(std::max(a, b) < 0.5 * minL))
             return fail(h, LB_EGEOM, "particle " + std::to_string(k) + ": bounding radius must be < min(L)/2");
+        if (!(std::max(a, b) <= h->prm.max_radius))
+            return fail(h, LB_EGEOM, "particle " + std::to_string(k) + ": bounding radius exceeds max_radius");
         for (int d = 0; d < 3; d++)
             if (!isfinite(pos[3 * k + d])) return fail(h, LB_EINVAL, "non-finite particle position");
         const double* q = quat + 4 * k;
@@ -252,6 +277,9 @@ int lb_add_ellipsoids(lb_handle* h, int32_t n, const double* radii, const double
         if (delta_rho && !isfinite(delta_rho[k])) return fail(h, LB_EINVAL, "non-finite delta_rho");
         if (density && !(density[k] > 0.0 && isfinite(density[k]))) return fail(h, LB_EINVAL, "density must be > 0");
     }
+    // pending kill/fill impulses move into the particle table before the
+    // partial-slot layout (set by the largest radius) can change
+    LBE_HIP(h, launch_fold_impulses(h));
     std::vector<double> t((size_t)NPFIELD * n, 0.0);
     auto F = [&](int field, int k) -> double& { return t[(size_t)field * n + k]; };
     for (int k = 0; k < n; k++) {
@@ -312,6 +340,11 @@ int lb_step(lb_handle* h, int32_t nsteps) {
     int bad = 0;
     LBE_HIP(h, hipMemcpyAsync(&bad, h->b.health, sizeof(int), hipMemcpyDeviceToHost, h->stream));
     LBE_HIP(h, hipStreamSynchronize(h->stream));
+    if (bad & 2) return fail(h, LB_EUNSTABLE, "a particle moved more than two lattice spacings in one step");
+    if (bad & 4)
+        return fail(h, LB_EUNSTABLE,
+                    "particles too crowded: a node touches more than two particles or a tile more than " +
+                        std::to_string(kTileSlots));
     if (bad) return fail(h, LB_EUNSTABLE, "NaN or negative density detected");
     return LB_OK;
 }
@@ -406,6 +439,7 @@ int lb_save_state(lb_handle* h, void* host_buf, size_t bytes) {
     if (!h || !host_buf) return LB_EINVAL;
     if (!h->inited) return fail(h, LB_ESTATE, "fields not initialised");
     if (bytes < lb_state_bytes(h)) return fail(h, LB_EINVAL, "buffer too small");
+    LBE_HIP(h, launch_fold_impulses(h));
     const size_t N = (size_t)h->box.N;
     char* p = (char*)host_buf;
     double hdr[8] = {(double)h->np, h->box.rmean0[0], h->box.rmean0[1], h->box.rref[0], h->box.rref[1], h->rmax,
@@ -433,7 +467,8 @@ int lb_load_state(lb_handle* h, const void* host_buf, size_t bytes) {
     double hdr[8];
     memcpy(hdr, p, sizeof hdr);
     p += sizeof hdr;
-    if ((int)hdr[6] != h->prm.precision || (size_t)hdr[7] != N || (int)hdr[0] > h->prm.max_particles)
+    if ((int)hdr[6] != h->prm.precision || (size_t)hdr[7] != N || (int)hdr[0] > h->prm.max_particles ||
+        (hdr[0] > 0 && !(hdr[5] <= h->prm.max_radius)))
         return fail(h, LB_EINVAL, "state does not match this handle's parameters");
     const size_t fb = 2 * Q * N * elem_bytes(h->prm.precision);
     {
@@ -453,6 +488,7 @@ int lb_load_state(lb_handle* h, const void* host_buf, size_t bytes) {
     p += pb;
     LBE_HIP(h, hipMemcpyAsync(h->b.counters, p, 8 * sizeof(double), hipMemcpyHostToDevice, h->stream));
     LBE_HIP(h, launch_fill_u32(h, (uint32_t*)h->b.health, 0u, 1));
+    LBE_HIP(h, launch_fill_f64(h, h->b.kpart, 0.0, h->kpart_len));
     LBE_HIP(h, hipStreamSynchronize(h->stream));
     h->np = (int)hdr[0];
     h->box.rmean0[0] = hdr[1];

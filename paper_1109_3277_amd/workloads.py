@@ -106,6 +106,11 @@ class System:
     def n_particles(self) -> int:
         return int(self.radii.shape[0])
 
+    @property
+    def max_radius(self) -> float:
+        """Largest bounding radius max(R_par, R_perp) of the particles (0 if none)."""
+        return float(self.radii.max()) if self.n_particles else 0.0
+
 
 def _zcoord(dims) -> np.ndarray:
     nx, ny, nz = dims

@@ -29,7 +29,8 @@ def run_oracle(sysm, steps: int):
 def run_gpu(sysm, steps: int, precision: str = "fp64"):
     from paper_1109_3277_amd.binding import Lattice
 
-    g = Lattice(sysm.dims, sysm.tau, sysm.g_br, sysm.psi_kind, precision, max_particles=max(1, sysm.n_particles))
+    g = Lattice(sysm.dims, sysm.tau, sysm.g_br, sysm.psi_kind, precision, max_particles=sysm.n_particles,
+                max_radius=sysm.max_radius)
     g.init_fields(sysm.rho_a, sysm.rho_b)
     if sysm.n_particles:
         g.add_ellipsoids(sysm.radii, sysm.pos, sysm.quat, sysm.delta_rho, sysm.density)

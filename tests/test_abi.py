@@ -42,14 +42,16 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_workspace_bytes_validates(lib):
     from paper_1109_3277_amd import binding as B
-    ok = B.make_params((32, 32, 64), 1.0, 0.08, max_particles=1)
+    ok = B.make_params((32, 32, 64), 1.0, 0.08, max_particles=1, max_radius=8.0)
     n = lib.lb_workspace_bytes(C.byref(ok))
     N = 32 * 32 * 64
     assert n >= 2 * 2 * 19 * N * 8 + 2 * N * 8 + 2 * N * 4
     for bad in (B.make_params((2, 32, 64), 1.0, 0.08), B.make_params((8, 8, 8), 0.5, 0.08),
                 B.make_params((8, 8, 8), float("nan"), 0.08), B.make_params((8, 8, 8), 1.0, float("inf")),
                 B.make_params((8, 8, 8), 1.0, 0.08, psi_kind=2), B.make_params((8, 8, 8), 1.0, 0.08, precision=7),
-                B.make_params((8, 8, 8), 1.0, 0.08, max_particles=-1)):
+                B.make_params((8, 8, 8), 1.0, 0.08, max_particles=-1),
+                B.make_params((8, 8, 8), 1.0, 0.08, max_particles=2),
+                B.make_params((8, 8, 8), 1.0, 0.08, max_particles=2, max_radius=4.0)):
         assert lib.lb_workspace_bytes(C.byref(bad)) == 0
     # reduced storage needs less memory
     n16 = lib.lb_workspace_bytes(C.byref(B.make_params((32, 32, 64), 1.0, 0.08, precision="fp16_dev")))
