@@ -86,12 +86,24 @@ struct Box {
     int nx, ny, nz;
     int64_t N;       // nx*ny*nz
     double tau;
+    double omega;    // 1 / tau
     double g;        // g_br
     int psi_kind;    // 0: Psi = rho, 1: Psi = 1 - exp(-rho)
     double ax, ay, az;  // body acceleration
     double rref[2];  // deviation reference density per component
     double rmean0[2];  // initial global mean density per component
 };
+
+// Element at a 32-bit byte offset from a uniform base (lets the compiler use a
+// scalar base plus one 32-bit vector offset per access).
+template <class T>
+__device__ inline const T* at(const T* base, uint32_t byte_off) {
+    return (const T*)((const char*)base + byte_off);
+}
+template <class T>
+__device__ inline T* atw(T* base, uint32_t byte_off) {
+    return (T*)((char*)base + byte_off);
+}
 
 __device__ inline int wrapc(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 // periodic wrap of any integer coordinate

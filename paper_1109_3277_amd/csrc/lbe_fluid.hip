@@ -37,16 +37,17 @@ __global__ __launch_bounds__(256) void k_density(Box bx, const typename P::S* __
                                                  typename P::R* __restrict__ psi, typename P::R* __restrict__ rho,
                                                  const uint32_t* __restrict__ owner, int* __restrict__ health) {
     using R = typename P::R;
-    const int64_t N = bx.N;
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t N = (uint32_t)bx.N;
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     if (SOLID && owner[n] != OWN_FLUID) return;
+    const uint32_t nb = n * (uint32_t)sizeof(typename P::S);
     const R ref0 = R(bx.rref[0]), ref1 = R(bx.rref[1]);
     R r0 = R(0), r1 = R(0);
 #pragma unroll
     for (int i = 0; i < Q; i++) {
-        r0 += P::ld(f + (size_t)i * N + n, R(wq(i)) * ref0);
-        r1 += P::ld(f + (size_t)(Q + i) * N + n, R(wq(i)) * ref1);
+        r0 += P::ld(at(f + (size_t)i * N, nb), R(wq(i)) * ref0);
+        r1 += P::ld(at(f + (size_t)(Q + i) * N, nb), R(wq(i)) * ref1);
     }
     psi[n] = psi_of(r0, bx.psi_kind);
     psi[N + n] = psi_of(r1, bx.psi_kind);
@@ -71,51 +72,73 @@ __global__ __launch_bounds__(256) void k_density(Box bx, const typename P::S* __
 // may link to up to three particles; more raise health bit 4). Forces are
 // reduced per block, particle by particle in increasing index, into the
 // tile's slot list (deterministic); k_forces sums the slots per particle.
-template <class P, bool SOLID>
-__global__ __launch_bounds__(256) void k_fused(Box bx, const typename P::S* __restrict__ fs,
+template <class P, bool SOLID, int BX, int BY>
+__global__ __launch_bounds__(256, SOLID ? 2 : 3) void k_fused(Box bx, const typename P::S* __restrict__ fs,
                                                typename P::S* __restrict__ fd,
                                                const typename P::R* __restrict__ psi,
                                                const uint32_t* __restrict__ owner, const double* __restrict__ part,
-                                               int cap, Tiles tl, int* __restrict__ tcount,
+                                               int cap, int tiles_x, int tiles_y, int* __restrict__ tcount,
                                                double* __restrict__ tslot, int* __restrict__ health) {
     using R = typename P::R;
+    using S = typename P::S;
+    static_assert(BX * BY == 256, "one node per thread");
+    constexpr int TX = BX + 2, TY = BY + 2, TP = TX * TY;  // tile plane with a one-node halo
+    __shared__ R s_psi[2][3 * TP];
+    __shared__ uint32_t s_own[SOLID ? 3 * TP : 1];
+
     const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
-    const int64_t N = bx.N;
+    const uint32_t N = (uint32_t)bx.N;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    const int txy = tl.tiles_x * tl.tiles_y;
+    const int txy = tiles_x * tiles_y;
     const int z = tile / txy;
     const int rem = tile - z * txy;
-    const int ty = rem / tl.tiles_x;
-    const int tx = rem - ty * tl.tiles_x;
-    const int lx = threadIdx.x % tl.BX, ly = threadIdx.x / tl.BX;
-    const int x = tx * tl.BX + lx, y = ty * tl.BY + ly;
+    const int ty = rem / tiles_x;
+    const int tx = rem - ty * tiles_x;
+    const int lx = threadIdx.x % BX, ly = threadIdx.x / BX;
+    const int x0 = tx * BX, y0 = ty * BY;
+    const int x = x0 + lx, y = y0 + ly;
     const bool active = (x < nx) && (y < ny);
-    if (!SOLID && !active) return;
-    const int64_t n = active ? (x + (int64_t)nx * (y + (int64_t)ny * z)) : 0;
+    const uint32_t n = active ? (uint32_t)(x + nx * (y + ny * z)) : 0u;
     const bool fluid = active && (!SOLID || owner[n] == OWN_FLUID);
+    const uint32_t nb = n * (uint32_t)sizeof(S);  // byte offset of the node within a plane
+    const R ref0 = R(bx.rref[0]), ref1 = R(bx.rref[1]);
+
+    // 1. this node's 2 x 19 populations (in flight while the tile loads)
+    R f0[Q], f1[Q];
+    if (fluid) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            f0[i] = P::ld(at(fs + (size_t)i * N, nb), R(wq(i)) * ref0);
+            f1[i] = P::ld(at(fs + (size_t)(Q + i) * N, nb), R(wq(i)) * ref1);
+        }
+    }
+    // 2. Psi (and owner codes) of the tile and its halo into LDS
+    for (int e = threadIdx.x; e < 3 * TP; e += 256) {
+        const int lz = e / TP, r = e - lz * TP, yy = r / TX, xx = r - yy * TX;
+        const int gx = wrapc_any(x0 - 1 + xx, nx), gy = wrapc_any(y0 - 1 + yy, ny), gz = wrapc_any(z - 1 + lz, nz);
+        const uint32_t m = (uint32_t)(gx + nx * (gy + ny * gz));
+        s_psi[0][e] = psi[m];
+        s_psi[1][e] = psi[N + m];
+        if (SOLID) s_own[e] = owner[m];
+    }
+    __syncthreads();
 
     // particles touched by this node's links (at most three) and their sums
     int pp[3] = {INT_MAX, INT_MAX, INT_MAX};
     double acc[3][6] = {{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}};
 
     if (fluid) {
-        // neighbour coordinates, indexed by velocity component 0, +1, -1
+        // LDS slot of neighbour i, and its global node index (for the push)
+#define LBE_LS(i) ((1 + cz(i)) * TP + (ly + 1 + cy(i)) * TX + (lx + 1 + cx(i)))
         const int xs[3] = {x, x + 1 == nx ? 0 : x + 1, x == 0 ? nx - 1 : x - 1};
-        const int64_t ys[3] = {(int64_t)y * nx, (int64_t)(y + 1 == ny ? 0 : y + 1) * nx,
-                               (int64_t)(y == 0 ? ny - 1 : y - 1) * nx};
-        const int64_t pl = (int64_t)nx * ny;
-        const int64_t zs[3] = {(int64_t)z * pl, (int64_t)(z + 1 == nz ? 0 : z + 1) * pl,
-                               (int64_t)(z == 0 ? nz - 1 : z - 1) * pl};
+        const uint32_t ys[3] = {(uint32_t)(y * nx), (uint32_t)((y + 1 == ny ? 0 : y + 1) * nx),
+                                (uint32_t)((y == 0 ? ny - 1 : y - 1) * nx)};
+        const uint32_t pl = (uint32_t)(nx * ny);
+        const uint32_t zs[3] = {(uint32_t)z * pl, (uint32_t)(z + 1 == nz ? 0 : z + 1) * pl,
+                                (uint32_t)(z == 0 ? nz - 1 : z - 1) * pl};
 #define LBE_SEL(c) ((c) == 0 ? 0 : ((c) > 0 ? 1 : 2))
-#define LBE_NB(i) (xs[LBE_SEL(cx(i))] + ys[LBE_SEL(cy(i))] + zs[LBE_SEL(cz(i))])
+#define LBE_NB(i) ((uint32_t)xs[LBE_SEL(cx(i))] + ys[LBE_SEL(cy(i))] + zs[LBE_SEL(cz(i))])
 
-        const R ref0 = R(bx.rref[0]), ref1 = R(bx.rref[1]);
-        R f0[Q], f1[Q];
-#pragma unroll
-        for (int i = 0; i < Q; i++) {
-            f0[i] = P::ld(fs + (size_t)i * N + n, R(wq(i)) * ref0);
-            f1[i] = P::ld(fs + (size_t)(Q + i) * N + n, R(wq(i)) * ref1);
-        }
         R r0 = R(0), r1 = R(0), jx = R(0), jy = R(0), jz = R(0);
 #pragma unroll
         for (int i = 0; i < Q; i++) {
@@ -134,9 +157,8 @@ __global__ __launch_bounds__(256) void k_fused(Box bx, const typename P::S* __re
         R s0x = R(0), s0y = R(0), s0z = R(0), s1x = R(0), s1y = R(0), s1z = R(0);
 #pragma unroll
         for (int i = 1; i < Q; i++) {
-            const int64_t m = LBE_NB(i);
-            const R p0 = psi[m];
-            const R p1 = psi[N + m];
+            const R p0 = s_psi[0][LBE_LS(i)];
+            const R p1 = s_psi[1][LBE_LS(i)];
             if (cx(i) > 0) { s0x += p0; s1x += p1; }
             if (cx(i) < 0) { s0x -= p0; s1x -= p1; }
             if (cy(i) > 0) { s0y += p0; s1y += p1; }
@@ -145,8 +167,8 @@ __global__ __launch_bounds__(256) void k_fused(Box bx, const typename P::S* __re
             if (cz(i) < 0) { s0z -= p0; s1z -= p1; }
         }
         const R tau = R(bx.tau);
-        const R rt = r0 + r1;
-        const R ux = jx / rt, uy = jy / rt, uz = jz / rt;
+        const R irt = R(1) / (r0 + r1);
+        const R ux = jx * irt, uy = jy * irt, uz = jz * irt;
         const R k0 = -R(bx.g) * psi_ratio(r0, kind);
         const R k1 = -R(bx.g) * psi_ratio(r1, kind);
         const R ax = R(bx.ax), ay = R(bx.ay), az = R(bx.az);
@@ -154,108 +176,102 @@ __global__ __launch_bounds__(256) void k_fused(Box bx, const typename P::S* __re
         const R u1x = ux + tau * (k1 * s0x + ax), u1y = uy + tau * (k1 * s0y + ay), u1z = uz + tau * (k1 * s0z + az);
         const R uu0 = u0x * u0x + u0y * u0y + u0z * u0z;
         const R uu1 = u1x * u1x + u1y * u1y + u1z * u1z;
-        const R om = R(1) / tau;
+        const R om = R(bx.omega);
 #pragma unroll
         for (int i = 0; i < Q; i++) {
             f0[i] = f0[i] - om * (f0[i] - feq_i(i, r0, u0x, u0y, u0z, uu0));
             f1[i] = f1[i] - om * (f1[i] - feq_i(i, r1, u1x, u1y, u1z, uu1));
         }
-        P::st(fd + n, f0[0], R(wq(0)) * ref0);
-        P::st(fd + (size_t)Q * N + n, f1[0], R(wq(0)) * ref1);
-        if constexpr (!SOLID) {
+        P::st(atw(fd, nb), f0[0], R(wq(0)) * ref0);
+        P::st(atw(fd + (size_t)Q * N, nb), f1[0], R(wq(0)) * ref1);
+        bool anys = false;
+        uint32_t on[Q];
+        if constexpr (SOLID) {
 #pragma unroll
             for (int i = 1; i < Q; i++) {
-                const int64_t m = LBE_NB(i);
-                P::st(fd + (size_t)i * N + m, f0[i], R(wq(i)) * ref0);
-                P::st(fd + (size_t)(Q + i) * N + m, f1[i], R(wq(i)) * ref1);
-            }
-        } else {
-            uint32_t on[Q];
-            bool anys = false;
-#pragma unroll
-            for (int i = 1; i < Q; i++) {
-                on[i] = owner[LBE_NB(i)];
+                on[i] = s_own[LBE_LS(i)];
                 anys |= (on[i] != OWN_FLUID);
             }
-            if (!anys) {
+        }
+        if (!anys) {
 #pragma unroll
-                for (int i = 1; i < Q; i++) {
-                    const int64_t m = LBE_NB(i);
-                    P::st(fd + (size_t)i * N + m, f0[i], R(wq(i)) * ref0);
-                    P::st(fd + (size_t)(Q + i) * N + m, f1[i], R(wq(i)) * ref1);
+            for (int i = 1; i < Q; i++) {
+                const uint32_t mb = LBE_NB(i) * (uint32_t)sizeof(S);
+                P::st(atw(fd + (size_t)i * N, mb), f0[i], R(wq(i)) * ref0);
+                P::st(atw(fd + (size_t)(Q + i) * N, mb), f1[i], R(wq(i)) * ref1);
+            }
+        } else if constexpr (SOLID) {
+            // the (at most three) particles this node's links touch
+#pragma unroll
+            for (int i = 1; i < Q; i++) {
+                const int o = (int)on[i];
+                if (on[i] >= OWN_WALL || o == pp[0] || o == pp[1] || o == pp[2]) continue;
+                if (pp[0] == INT_MAX) pp[0] = o;
+                else if (pp[1] == INT_MAX) pp[1] = o;
+                else if (pp[2] == INT_MAX) pp[2] = o;
+                else atomicOr(health, 4);
+            }
+            double rr[3][3], uu[3][3];
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const int q = pp[k];
+                if (q == INT_MAX) {
+                    rr[k][0] = rr[k][1] = rr[k][2] = 0.0;
+                    uu[k][0] = uu[k][1] = uu[k][2] = 0.0;
+                    continue;
                 }
-            } else {
-                // the (at most three) particles this node's links touch
+                rr[k][0] = minimg((double)x - part[PX * cap + q], nx);
+                rr[k][1] = minimg((double)y - part[PY * cap + q], ny);
+                rr[k][2] = minimg((double)z - part[PZ * cap + q], nz);
+                const double wx = part[WX * cap + q], wy = part[WY * cap + q], wz = part[WZ * cap + q];
+                uu[k][0] = part[VX * cap + q] + (wy * rr[k][2] - wz * rr[k][1]);
+                uu[k][1] = part[VY * cap + q] + (wz * rr[k][0] - wx * rr[k][2]);
+                uu[k][2] = part[VZ * cap + q] + (wx * rr[k][1] - wy * rr[k][0]);
+            }
+            double F[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 #pragma unroll
-                for (int i = 1; i < Q; i++) {
-                    const int o = (int)on[i];
-                    if (on[i] >= OWN_WALL || o == pp[0] || o == pp[1] || o == pp[2]) continue;
-                    if (pp[0] == INT_MAX) pp[0] = o;
-                    else if (pp[1] == INT_MAX) pp[1] = o;
-                    else if (pp[2] == INT_MAX) pp[2] = o;
-                    else atomicOr(health, 4);
-                }
-                double rr[3][3], uu[3][3];
+            for (int i = 1; i < Q; i++) {
+                const uint32_t o = on[i];
+                if (o == OWN_FLUID) {
+                    const uint32_t mb = LBE_NB(i) * (uint32_t)sizeof(S);
+                    P::st(atw(fd + (size_t)i * N, mb), f0[i], R(wq(i)) * ref0);
+                    P::st(atw(fd + (size_t)(Q + i) * N, mb), f1[i], R(wq(i)) * ref1);
+                } else {
+                    const bool isp = (o < OWN_WALL);
+                    const int k = (int)o == pp[1] ? 1 : ((int)o == pp[2] ? 2 : 0);
+                    const double Ux = isp ? (k == 1 ? uu[1][0] : (k == 2 ? uu[2][0] : uu[0][0])) : 0.0;
+                    const double Uy = isp ? (k == 1 ? uu[1][1] : (k == 2 ? uu[2][1] : uu[0][1])) : 0.0;
+                    const double Uz = isp ? (k == 1 ? uu[1][2] : (k == 2 ? uu[2][2] : uu[0][2])) : 0.0;
+                    // C = 6 w_i rho (u_b . c_ibar) = -6 w_i rho (U . c_i)
+                    const double cu = Ux * cx(i) + Uy * cy(i) + Uz * cz(i);
+                    const R C0 = R(-6.0 * wq(i) * cu) * r0;
+                    const R C1 = R(-6.0 * wq(i) * cu) * r1;
+                    const int b = opp(i);
+                    P::st(atw(fd + (size_t)b * N, nb), f0[i] + C0, R(wq(b)) * ref0);
+                    P::st(atw(fd + (size_t)(Q + b) * N, nb), f1[i] + C1, R(wq(b)) * ref1);
+                    const double mag = isp ? (2.0 * ((double)f0[i] + (double)f1[i]) + ((double)C0 + (double)C1)) : 0.0;
 #pragma unroll
-                for (int k = 0; k < 3; k++) {
-                    const int q = pp[k];
-                    if (q == INT_MAX) {
-                        rr[k][0] = rr[k][1] = rr[k][2] = 0.0;
-                        uu[k][0] = uu[k][1] = uu[k][2] = 0.0;
-                        continue;
+                    for (int kk = 0; kk < 3; kk++) {
+                        const double g = (k == kk) ? mag : 0.0;
+                        F[kk][0] += g * cx(i);
+                        F[kk][1] += g * cy(i);
+                        F[kk][2] += g * cz(i);
                     }
-                    rr[k][0] = minimg((double)x - part[PX * cap + q], nx);
-                    rr[k][1] = minimg((double)y - part[PY * cap + q], ny);
-                    rr[k][2] = minimg((double)z - part[PZ * cap + q], nz);
-                    const double wx = part[WX * cap + q], wy = part[WY * cap + q], wz = part[WZ * cap + q];
-                    uu[k][0] = part[VX * cap + q] + (wy * rr[k][2] - wz * rr[k][1]);
-                    uu[k][1] = part[VY * cap + q] + (wz * rr[k][0] - wx * rr[k][2]);
-                    uu[k][2] = part[VZ * cap + q] + (wx * rr[k][1] - wy * rr[k][0]);
                 }
-                double F[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+            }
 #pragma unroll
-                for (int i = 1; i < Q; i++) {
-                    const uint32_t o = on[i];
-                    if (o == OWN_FLUID) {
-                        const int64_t m = LBE_NB(i);
-                        P::st(fd + (size_t)i * N + m, f0[i], R(wq(i)) * ref0);
-                        P::st(fd + (size_t)(Q + i) * N + m, f1[i], R(wq(i)) * ref1);
-                    } else {
-                        const bool isp = (o < OWN_WALL);
-                        const int k = (int)o == pp[1] ? 1 : ((int)o == pp[2] ? 2 : 0);
-                        const double Ux = isp ? (k == 1 ? uu[1][0] : (k == 2 ? uu[2][0] : uu[0][0])) : 0.0;
-                        const double Uy = isp ? (k == 1 ? uu[1][1] : (k == 2 ? uu[2][1] : uu[0][1])) : 0.0;
-                        const double Uz = isp ? (k == 1 ? uu[1][2] : (k == 2 ? uu[2][2] : uu[0][2])) : 0.0;
-                        // C = 6 w_i rho (u_b . c_ibar) = -6 w_i rho (U . c_i)
-                        const double cu = Ux * cx(i) + Uy * cy(i) + Uz * cz(i);
-                        const R C0 = R(-6.0 * wq(i) * cu) * r0;
-                        const R C1 = R(-6.0 * wq(i) * cu) * r1;
-                        const int b = opp(i);
-                        P::st(fd + (size_t)b * N + n, f0[i] + C0, R(wq(b)) * ref0);
-                        P::st(fd + (size_t)(Q + b) * N + n, f1[i] + C1, R(wq(b)) * ref1);
-                        const double mag = isp ? (2.0 * ((double)f0[i] + (double)f1[i]) + ((double)C0 + (double)C1)) : 0.0;
-#pragma unroll
-                        for (int kk = 0; kk < 3; kk++) {
-                            const double g = (k == kk) ? mag : 0.0;
-                            F[kk][0] += g * cx(i);
-                            F[kk][1] += g * cy(i);
-                            F[kk][2] += g * cz(i);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < 3; k++) {
-                    acc[k][0] = F[k][0];
-                    acc[k][1] = F[k][1];
-                    acc[k][2] = F[k][2];
-                    acc[k][3] = rr[k][1] * F[k][2] - rr[k][2] * F[k][1];
-                    acc[k][4] = rr[k][2] * F[k][0] - rr[k][0] * F[k][2];
-                    acc[k][5] = rr[k][0] * F[k][1] - rr[k][1] * F[k][0];
-                }
+            for (int k = 0; k < 3; k++) {
+                acc[k][0] = F[k][0];
+                acc[k][1] = F[k][1];
+                acc[k][2] = F[k][2];
+                acc[k][3] = rr[k][1] * F[k][2] - rr[k][2] * F[k][1];
+                acc[k][4] = rr[k][2] * F[k][0] - rr[k][0] * F[k][2];
+                acc[k][5] = rr[k][0] * F[k][1] - rr[k][1] * F[k][0];
             }
         }
 #undef LBE_NB
 #undef LBE_SEL
+#undef LBE_LS
     }
     if constexpr (SOLID) {
         // Per particle, in increasing index: block-wide deterministic sum of the
@@ -485,22 +501,29 @@ Tiles fused_tiles(int nx, int ny) {
     return t;
 }
 
+template <class P, bool SOLID>
+static void launch_fused_t(lb_handle* h, const Tiles& tl, unsigned grid) {
+    const int o = h->cur, d = 1 - h->cur;
+    auto fs = (const typename P::S*)h->b.f[o];
+    auto fd = (typename P::S*)h->b.f[d];
+    auto ps = (const typename P::R*)h->b.psi;
+    if (tl.BX == 64)
+        hipLaunchKernelGGL((k_fused<P, SOLID, 64, 4>), dim3(grid), dim3(256), 0, h->stream, h->box, fs, fd, ps,
+                           h->b.owner[h->ocur], h->b.part, h->cap, tl.tiles_x, tl.tiles_y, h->b.tcount, h->b.tslot,
+                           h->b.health);
+    else
+        hipLaunchKernelGGL((k_fused<P, SOLID, 32, 8>), dim3(grid), dim3(256), 0, h->stream, h->box, fs, fd, ps,
+                           h->b.owner[h->ocur], h->b.part, h->cap, tl.tiles_x, tl.tiles_y, h->b.tcount, h->b.tslot,
+                           h->b.health);
+}
+
 hipError_t launch_fused(lb_handle* h) {
     const Tiles tl = fused_tiles(h->box.nx, h->box.ny);
     const unsigned grid = (unsigned)(tl.tiles_x * tl.tiles_y * h->box.nz);
-    const int o = h->cur, d = 1 - h->cur;
     if (h->has_solid) {
-        LBE_DISPATCH(h->prm.precision,
-                     hipLaunchKernelGGL((k_fused<P, true>), dim3(grid), dim3(256), 0, h->stream, h->box,
-                                        (const typename P::S*)h->b.f[o], (typename P::S*)h->b.f[d],
-                                        (const typename P::R*)h->b.psi, h->b.owner[h->ocur], h->b.part, h->cap, tl,
-                                        h->b.tcount, h->b.tslot, h->b.health));
+        LBE_DISPATCH(h->prm.precision, (launch_fused_t<P, true>(h, tl, grid)));
     } else {
-        LBE_DISPATCH(h->prm.precision,
-                     hipLaunchKernelGGL((k_fused<P, false>), dim3(grid), dim3(256), 0, h->stream, h->box,
-                                        (const typename P::S*)h->b.f[o], (typename P::S*)h->b.f[d],
-                                        (const typename P::R*)h->b.psi, h->b.owner[h->ocur], h->b.part, h->cap, tl,
-                                        h->b.tcount, h->b.tslot, h->b.health));
+        LBE_DISPATCH(h->prm.precision, (launch_fused_t<P, false>(h, tl, grid)));
     }
     return hipGetLastError();
 }

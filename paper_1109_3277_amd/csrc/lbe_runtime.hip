@@ -33,7 +33,10 @@ int fail(lb_handle* h, int code, const std::string& msg) {
 bool params_ok(const lb_params* p, std::string* why) {
     if (!p) { *why = "params is NULL"; return false; }
     if (p->nx < 3 || p->ny < 3 || p->nz < 3) { *why = "each dimension must be >= 3"; return false; }
-    if ((int64_t)p->nx * p->ny * p->nz > ((int64_t)1 << 31) - 1) { *why = "too many nodes (limit 2^31 - 1)"; return false; }
+    if ((int64_t)p->nx * p->ny * p->nz * 8 >= ((int64_t)1 << 32)) {
+        *why = "too many nodes (one population plane must stay below 4 GiB: N < 2^29)";
+        return false;
+    }
     if (!(p->tau > 0.5) || !isfinite(p->tau)) { *why = "tau must be finite and > 1/2"; return false; }
     if (!isfinite(p->g_br)) { *why = "g_br must be finite"; return false; }
     if (p->psi_kind != 0 && p->psi_kind != 1) { *why = "psi_kind must be 0 or 1"; return false; }
@@ -156,6 +159,7 @@ int lb_create(const lb_params* prm, void* dev_ws, size_t ws_bytes, void* hip_str
     b.nz = prm->nz;
     b.N = (int64_t)prm->nx * prm->ny * prm->nz;
     b.tau = prm->tau;
+    b.omega = 1.0 / prm->tau;
     b.g = prm->g_br;
     b.psi_kind = prm->psi_kind;
     b.ax = b.ay = b.az = 0.0;
