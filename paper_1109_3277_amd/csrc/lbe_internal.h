@@ -64,7 +64,7 @@ hipError_t launch_density(lb_handle* h);
 hipError_t launch_shell(lb_handle* h);
 hipError_t launch_fused(lb_handle* h);
 hipError_t launch_forces(lb_handle* h);
-Tiles fused_tiles(int nx, int ny);
+Tiles fused_tiles(int nx, int ny, bool solids);
 hipError_t launch_fields(lb_handle* h, double* d_out);       // rho_a, rho_b, u (5 x N doubles)
 hipError_t launch_stats(lb_handle* h);                       // totals into b.red[kRedBlocks*8 ...]
 hipError_t launch_remove_covered(lb_handle* h);

@@ -450,7 +450,7 @@ hipError_t launch_shell(lb_handle* h) {
 hipError_t launch_forces(lb_handle* h) {
     if (h->np <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_forces, dim3(h->np), dim3(256), 0, h->stream, h->box, h->b.part, h->cap,
-                       fused_tiles(h->box.nx, h->box.ny), h->b.tcount, h->b.tslot);
+                       fused_tiles(h->box.nx, h->box.ny, true), h->b.tcount, h->b.tslot);
     return hipGetLastError();
 }
 

@@ -67,7 +67,7 @@ Layout layout_of(const lb_params* p) {
     L.part = align_up(NPFIELD * cap * sizeof(double));
     const double rmax = p->max_particles > 0 ? p->max_radius : 0.5;
     const Slab s2 = make_slab(killfill_extent(p->nx, p->ny, p->nz, rmax));
-    const Tiles tl = fused_tiles(p->nx, p->ny);
+    const Tiles tl = fused_tiles(p->nx, p->ny, true);
     const size_t ntiles = (size_t)tl.tiles_x * tl.tiles_y * p->nz;
     L.tcount = p->max_particles > 0 ? align_up(ntiles * sizeof(int)) : 0;
     L.tslot = p->max_particles > 0 ? align_up(ntiles * kTileSlots * 7 * sizeof(double)) : 0;

@@ -204,3 +204,40 @@ def test_node_touching_three_particles_fp64():
     assert own[12, 12, 12] == -1 and own[12, 12, 11] == 0 and own[12, 12, 13] == 1 and own[12, 13, 12] == 2
     _, _, res = _run(s, 20)
     _check_fp64(res)
+
+
+@pytest.mark.parametrize("nx", [64, 128, 256, 512])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("particles", [False, True])
+def test_row_kernel_widths(nx, prec, particles):
+    """Box widths whose x-rows fill whole blocks: without particles they run
+    the aligned-store row kernel (wave-edge exchange, periodic seam); with
+    small particles crossing wave boundaries and the seam, the tile kernel."""
+    from paper_1109_3277_amd.workloads import System, uniform_fields
+
+    dims = (nx, 16, 12)
+    ra, rb = uniform_fields(dims, 30 + nx, 0.7, 0.7, 0.01)
+    rng = np.random.default_rng(nx)
+    k = max(2, nx // 48)
+    pos = np.stack([np.linspace(0.5, nx - 0.5, k, endpoint=False) + 1.3, rng.uniform(4, 12, k),
+                    rng.uniform(3, 9, k)], 1)
+    pos[-1, 0] = nx - 0.6  # straddles the periodic seam in x
+    q = rng.normal(size=(k, 4))
+    if particles:
+        s = System(f"rows{nx}", dims, 1.0, 0.08, ra, rb, np.tile([3.5, 2.0], (k, 1)), pos, q,
+                   rng.uniform(-0.1, 0.1, k), np.full(k, 2.0))
+    else:
+        s = System(f"rows{nx}", dims, 1.0, 0.08, ra, rb)
+    o, g, res = _run(s, 40, prec)
+    if prec == "fp64":
+        _check_fp64(res)
+    else:
+        log(f"  fp32 {res}")
+        assert res["e_rho"] <= 1e-5 and res["owner_equal"], res
+
+
+def test_bijel_full_size_fp64():
+    """The full 256^3 bijel workload with its 4694 ellipsoids, a few steps."""
+    s = W.bijel_system()
+    _, _, res = _run(s, 3)
+    _check_fp64(res)
