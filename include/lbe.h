@@ -105,9 +105,8 @@ int lb_add_ellipsoids(lb_handle* h, int32_t n, const double* radii, const double
  * BGK collision, streaming with moving bounce-back and particle force/torque,
  * rigid-body update, re-rasterisation with kill/fill). Work is enqueued on
  * the handle's stream; the call then waits for it to check the health flag and
- * returns LB_EUNSTABLE if a NaN or negative density appeared, if a particle
- * moved more than two lattice spacings in one step, or if particles crowd so
- * that a fluid node links to more than two of them. */
+ * returns LB_EUNSTABLE if a NaN or negative density appeared or if a particle
+ * moved more than two lattice spacings in one step. */
 int lb_step(lb_handle* h, int32_t nsteps);
 
 /* Same as lb_step but does not wait: no health check; the stream is left
@@ -156,6 +155,12 @@ int lb_load_state(lb_handle* h, const void* host_buf, size_t bytes);
 #define LB_NPHASES 7
 int lb_profile_enable(lb_handle* h, int on);
 int lb_profile_read(lb_handle* h, double* ms, int64_t* launches);
+
+/* Calibration helper for hardware traffic counters: copies `bytes` bytes
+ * (a multiple of 16) from dev_src to dev_dst on hip_stream with a plain
+ * streaming kernel, so that a profiler's fetch / write byte counters can be
+ * scaled against a transfer of known size. Not part of the method. */
+int lb_probe_copy(void* dev_dst, const void* dev_src, size_t bytes, void* hip_stream);
 
 /* Message of the last failed call on h (or of the last failed lb_create when
  * h is NULL); valid until the next call on the same handle. */

@@ -20,7 +20,7 @@ EXPORTED = [
     "lb_workspace_bytes", "lb_create", "lb_destroy", "lb_init_fields", "lb_add_ellipsoids", "lb_step",
     "lb_step_async", "lb_read_fields", "lb_num_particles", "lb_read_particles", "lb_stats",
     "lb_set_body_accel", "lb_state_bytes", "lb_save_state", "lb_load_state", "lb_last_error",
-    "lb_profile_enable", "lb_profile_read",
+    "lb_profile_enable", "lb_profile_read", "lb_probe_copy",
 ]
 PHASES = ["density", "shell", "fused", "forces", "bodies", "raster", "killfill"]
 
@@ -72,6 +72,7 @@ def load_library():
     L.lb_last_error.argtypes = [vp]
     L.lb_profile_enable.argtypes = [vp, C.c_int]
     L.lb_profile_read.argtypes = [vp, dp, C.POINTER(C.c_int64)]
+    L.lb_probe_copy.argtypes = [vp, vp, C.c_size_t, vp]
     _lib = L
     return L
 
@@ -211,3 +212,16 @@ class Lattice:
     def load_state(self, data: bytes):
         buf = C.create_string_buffer(data, len(data))
         self._check(load_library().lb_load_state(self._h, buf, len(data)))
+
+
+def probe_copy(dst, src, stream=None):
+    """Copy torch tensor src into dst (same byte size, multiple of 16) with the
+    library's plain streaming kernel (traffic-counter calibration)."""
+    import torch
+
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes and nbytes % 16 == 0
+    st = (stream or torch.cuda.current_stream()).cuda_stream
+    rc = load_library().lb_probe_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes, C.c_void_p(st))
+    if rc != 0:
+        raise LBError(rc, load_library().lb_last_error(None).decode())

@@ -154,9 +154,7 @@ __device__ inline bool particle_box(const Box& bx, const double* part, int cap, 
 }
 
 // Tiles of the fused kernel: BX x BY nodes of one xy-plane per 256-thread
-// block. Each tile keeps up to kTileSlots (particle, force, torque) slots for
-// the bounce-back links of its nodes (7 doubles each: id, F, T).
-constexpr int kTileSlots = 48;
+// block (or, for the row kernel, BY whole x-rows of BX = nx nodes).
 struct Tiles {
     int BX, BY, tiles_x, tiles_y;
 };

@@ -7,7 +7,7 @@
 // effective masses Psi[c][n]; owner map uint32 per node. One thread per node, tiles
 // of 64x4 (or 32x8) nodes of one xy-plane per 256-thread block, tiles of
 // neighbouring z on the same XCD.
-#include <limits.h>
+#include <algorithm>
 
 #include "lbe_internal.h"
 
@@ -63,15 +63,13 @@ __global__ __launch_bounds__(256) void k_density(Box bx, const typename P::S* __
 // (Eq. (2)) with the common-velocity shift u^eq_c = u' + tau F^c/rho^c, then
 // push streaming (Eq. (1)). With solids present, a link i into a solid node
 // is replaced by moving bounce-back (Eq. (4)) in place:
-// f'_ibar(n) = f*_i(n) + C, C = 6 w_i rho^c(n) (u_b . c_ibar), and the
-// particle receives (2 f*_i + C) c_i (Eq. (5)). For a rigid body the surface
-// velocity at the link midpoint, V + W x (r_n + c_i/2), has the same
-// projection on c_i as U_n = V + W x r_n at the node (W x c_i is normal to
-// c_i), and the torque of all links of a node is r_n x their summed force
-// (c_i x c_i = 0): one U_n and one lever arm per node and particle (a node
-// may link to up to three particles; more raise health bit 4). Forces are
-// reduced per block, particle by particle in increasing index, into the
-// block's slot list (deterministic); k_forces sums the slots per particle.
+// f'_ibar(n) = f*_i(n) + C, C = 6 w_i rho^c(n) (u_b . c_ibar). For a rigid
+// body the surface velocity at the link midpoint, V + W x (r_n + c_i/2), has
+// the same projection on c_i as U_n = V + W x r_n at the node (W x c_i is
+// normal to c_i), so C needs one U_n per node and particle. The particle's
+// share (2 f*_i + C) c_i of Eq. (5) is not summed here: f'_ibar(n) is stored
+// and equals f*_i + C, so k_linkforce recovers it afterwards as
+// (2 f'_ibar(n) - C) c_i from the solid side of each link.
 
 // Moments, Shan-Chen velocity shift and BGK relaxation of one node, in place
 // on f0 / f1 (component A / B). q0[i], q1[i]: Psi^A, Psi^B of neighbour i.
@@ -126,154 +124,15 @@ __device__ inline void collide_node(const Box& bx, typename P::R (&f0)[Q], typen
     }
 }
 
-// Particles linked to a fluid node (at most three) with, per particle, the
-// lever arm r_n and surface velocity U_n = V + W x r_n at the node.
-struct NodeLinks {
-    int pp[3];
-    double rr[3][3], uu[3][3];
-};
-
-__device__ inline void node_links(const Box& bx, const double* __restrict__ part, int cap, int x, int y, int z,
-                                  const uint32_t (&on)[Q], NodeLinks& L, int* health) {
-    L.pp[0] = L.pp[1] = L.pp[2] = INT_MAX;
-#pragma unroll
-    for (int i = 1; i < Q; i++) {
-        const int o = (int)on[i];
-        if (on[i] >= OWN_WALL || o == L.pp[0] || o == L.pp[1] || o == L.pp[2]) continue;
-        if (L.pp[0] == INT_MAX) L.pp[0] = o;
-        else if (L.pp[1] == INT_MAX) L.pp[1] = o;
-        else if (L.pp[2] == INT_MAX) L.pp[2] = o;
-        else atomicOr(health, 4);
-    }
-#pragma unroll
-    for (int k = 0; k < 3; k++) {
-        const int q = L.pp[k];
-        if (q == INT_MAX) {
-            L.rr[k][0] = L.rr[k][1] = L.rr[k][2] = 0.0;
-            L.uu[k][0] = L.uu[k][1] = L.uu[k][2] = 0.0;
-            continue;
-        }
-        L.rr[k][0] = minimg((double)x - part[PX * cap + q], bx.nx);
-        L.rr[k][1] = minimg((double)y - part[PY * cap + q], bx.ny);
-        L.rr[k][2] = minimg((double)z - part[PZ * cap + q], bx.nz);
-        const double wx = part[WX * cap + q], wy = part[WY * cap + q], wz = part[WZ * cap + q];
-        L.uu[k][0] = part[VX * cap + q] + (wy * L.rr[k][2] - wz * L.rr[k][1]);
-        L.uu[k][1] = part[VY * cap + q] + (wz * L.rr[k][0] - wx * L.rr[k][2]);
-        L.uu[k][2] = part[VZ * cap + q] + (wx * L.rr[k][1] - wy * L.rr[k][0]);
-    }
-}
-
-// Bounce-back term of link i into owner o (C^A, C^B) and the link's index k
-// among the node's particles; C = -6 w_i rho (U . c_i), walls do not move.
-template <class R>
-__device__ inline void link_term(int i, uint32_t o, const NodeLinks& L, bool multi, R r0, R r1, R& C0, R& C1,
-                                 int& k) {
-    const bool isp = (o < OWN_WALL);
-    k = 0;
-    double Ux = L.uu[0][0], Uy = L.uu[0][1], Uz = L.uu[0][2];
-    if (multi) {  // rare: a node linked to more than one particle
-        k = (int)o == L.pp[1] ? 1 : ((int)o == L.pp[2] ? 2 : 0);
-        Ux = k == 1 ? L.uu[1][0] : (k == 2 ? L.uu[2][0] : L.uu[0][0]);
-        Uy = k == 1 ? L.uu[1][1] : (k == 2 ? L.uu[2][1] : L.uu[0][1]);
-        Uz = k == 1 ? L.uu[1][2] : (k == 2 ? L.uu[2][2] : L.uu[0][2]);
-    }
-    const double cu = isp ? (Ux * cx(i) + Uy * cy(i) + Uz * cz(i)) : 0.0;
-    C0 = R(-6.0 * wq(i) * cu) * r0;
-    C1 = R(-6.0 * wq(i) * cu) * r1;
-}
-
-// Link force (2 f*_i + C) c_i added to the node's particle sums.
-__device__ inline void link_force(int i, bool isp, int k, bool multi, double f, double C, double (&F)[3][3]) {
-    const double mag = isp ? (2.0 * f + C) : 0.0;
-    if (!multi) {
-        F[0][0] += mag * cx(i);
-        F[0][1] += mag * cy(i);
-        F[0][2] += mag * cz(i);
-    } else {
-#pragma unroll
-        for (int kk = 0; kk < 3; kk++) {
-            const double g = (k == kk) ? mag : 0.0;
-            F[kk][0] += g * cx(i);
-            F[kk][1] += g * cy(i);
-            F[kk][2] += g * cz(i);
-        }
-    }
-}
-
-__device__ inline void node_accum(const NodeLinks& L, const double (&F)[3][3], double (&acc)[3][6]) {
-#pragma unroll
-    for (int k = 0; k < 3; k++) {
-        acc[k][0] = F[k][0];
-        acc[k][1] = F[k][1];
-        acc[k][2] = F[k][2];
-        acc[k][3] = L.rr[k][1] * F[k][2] - L.rr[k][2] * F[k][1];
-        acc[k][4] = L.rr[k][2] * F[k][0] - L.rr[k][0] * F[k][2];
-        acc[k][5] = L.rr[k][0] * F[k][1] - L.rr[k][1] * F[k][0];
-    }
-}
-
-// Per particle, in increasing index: block-wide deterministic sum of the
-// threads' contributions into the next slot of this block's list. Every
-// thread of the block calls it (NW waves).
-template <int NW>
-__device__ inline void block_slots(int (&pp)[3], const double (&acc)[3][6], int blk, int* __restrict__ tcount,
-                                   double* __restrict__ tslot, int* __restrict__ health) {
-    __shared__ int s_min[NW];
-    __shared__ double s_sum[NW][6];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    double* slots = tslot + (size_t)blk * kTileSlots * 7;
-    int nslot = 0;
-    while (true) {
-        int lm = min(pp[0], min(pp[1], pp[2]));
-        for (int off = 32; off > 0; off >>= 1) lm = min(lm, __shfl_xor(lm, off, 64));
-        if (lane == 0) s_min[w] = lm;
-        __syncthreads();
-        int pm = INT_MAX;
-        for (int j = 0; j < NW; j++) pm = min(pm, s_min[j]);
-        __syncthreads();
-        if (pm == INT_MAX) break;
-        double v[6];
-#pragma unroll
-        for (int k = 0; k < 6; k++)
-            v[k] = (pp[0] == pm ? acc[0][k] : 0.0) + (pp[1] == pm ? acc[1][k] : 0.0) + (pp[2] == pm ? acc[2][k] : 0.0);
-#pragma unroll
-        for (int k = 0; k < 6; k++)
-            for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
-        if (lane == 0)
-            for (int k = 0; k < 6; k++) s_sum[w][k] = v[k];
-        __syncthreads();
-        if (tid == 0) {
-            if (nslot < kTileSlots) {
-                double* o = slots + (size_t)nslot * 7;
-                o[0] = (double)pm;
-                for (int k = 0; k < 6; k++) {
-                    double t = 0.0;
-                    for (int j = 0; j < NW; j++) t += s_sum[j][k];
-                    o[1 + k] = t;
-                }
-            } else {
-                atomicOr(health, 4);
-            }
-        }
-        nslot++;
-#pragma unroll
-        for (int k = 0; k < 3; k++)
-            if (pp[k] == pm) pp[k] = INT_MAX;
-        __syncthreads();
-    }
-    if (tid == 0) tcount[blk] = min(nslot, kTileSlots);
-}
-
 // Tile kernel (any box): BX x BY nodes of one xy-plane per 256-thread block,
 // Psi and owner codes of the tile and its one-node halo staged in LDS.
 template <class P, bool SOLID, int BX, int BY>
-__global__ __launch_bounds__(256, SOLID ? 2 : 3) void k_fused(Box bx, const typename P::S* __restrict__ fs,
-                                                              typename P::S* __restrict__ fd,
-                                                              const typename P::R* __restrict__ psi,
-                                                              const uint32_t* __restrict__ owner,
-                                                              const double* __restrict__ part, int cap, int tiles_x,
-                                                              int tiles_y, int* __restrict__ tcount,
-                                                              double* __restrict__ tslot, int* __restrict__ health) {
+__global__ __launch_bounds__(256, 3) void k_fused(Box bx, const typename P::S* __restrict__ fs,
+                                                   typename P::S* __restrict__ fd,
+                                                   const typename P::R* __restrict__ psi,
+                                                   const uint32_t* __restrict__ owner,
+                                                   const double* __restrict__ part, int cap, int tiles_x,
+                                                   int tiles_y) {
     using R = typename P::R;
     using S = typename P::S;
     static_assert(BX * BY == 256, "one node per thread");
@@ -316,95 +175,111 @@ __global__ __launch_bounds__(256, SOLID ? 2 : 3) void k_fused(Box bx, const type
         if (SOLID) s_own[e] = owner[m];
     }
     __syncthreads();
+    if (!fluid) return;
 
-    int pp[3] = {INT_MAX, INT_MAX, INT_MAX};
-    double acc[3][6] = {{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}};
-
-    if (fluid) {
 #define LBE_LS(i) ((1 + cz(i)) * TP + (ly + 1 + cy(i)) * TX + (lx + 1 + cx(i)))
-        const int xs[3] = {x, x + 1 == nx ? 0 : x + 1, x == 0 ? nx - 1 : x - 1};
-        const uint32_t ys[3] = {(uint32_t)(y * nx), (uint32_t)((y + 1 == ny ? 0 : y + 1) * nx),
-                                (uint32_t)((y == 0 ? ny - 1 : y - 1) * nx)};
-        const uint32_t pl = (uint32_t)(nx * ny);
-        const uint32_t zs[3] = {(uint32_t)z * pl, (uint32_t)(z + 1 == nz ? 0 : z + 1) * pl,
-                                (uint32_t)(z == 0 ? nz - 1 : z - 1) * pl};
+    const int xs[3] = {x, x + 1 == nx ? 0 : x + 1, x == 0 ? nx - 1 : x - 1};
+    const uint32_t ys[3] = {(uint32_t)(y * nx), (uint32_t)((y + 1 == ny ? 0 : y + 1) * nx),
+                            (uint32_t)((y == 0 ? ny - 1 : y - 1) * nx)};
+    const uint32_t pl = (uint32_t)(nx * ny);
+    const uint32_t zs[3] = {(uint32_t)z * pl, (uint32_t)(z + 1 == nz ? 0 : z + 1) * pl,
+                            (uint32_t)(z == 0 ? nz - 1 : z - 1) * pl};
 #define LBE_SEL(c) ((c) == 0 ? 0 : ((c) > 0 ? 1 : 2))
 #define LBE_NB(i) ((uint32_t)xs[LBE_SEL(cx(i))] + ys[LBE_SEL(cy(i))] + zs[LBE_SEL(cz(i))])
-        R q0[Q], q1[Q];
+    R q0[Q], q1[Q];
+#pragma unroll
+    for (int i = 1; i < Q; i++) {
+        q0[i] = s_psi[0][LBE_LS(i)];
+        q1[i] = s_psi[1][LBE_LS(i)];
+    }
+    q0[0] = q1[0] = R(0);
+    R r0, r1;
+    collide_node<P>(bx, f0, f1, q0, q1, r0, r1);
+    P::st(atw(fd, nb), f0[0], R(wq(0)) * ref0);
+    P::st(atw(fd + (size_t)Q * N, nb), f1[0], R(wq(0)) * ref1);
+    if constexpr (!SOLID) {
 #pragma unroll
         for (int i = 1; i < Q; i++) {
-            q0[i] = s_psi[0][LBE_LS(i)];
-            q1[i] = s_psi[1][LBE_LS(i)];
+            const uint32_t mb = LBE_NB(i) * (uint32_t)sizeof(S);
+            P::st(atw(fd + (size_t)i * N, mb), f0[i], R(wq(i)) * ref0);
+            P::st(atw(fd + (size_t)(Q + i) * N, mb), f1[i], R(wq(i)) * ref1);
         }
-        q0[0] = q1[0] = R(0);
-        R r0, r1;
-        collide_node<P>(bx, f0, f1, q0, q1, r0, r1);
-        P::st(atw(fd, nb), f0[0], R(wq(0)) * ref0);
-        P::st(atw(fd + (size_t)Q * N, nb), f1[0], R(wq(0)) * ref1);
-        bool anys = false;
+    } else {
+        // Every fluid lane takes the general path (one store path per wave).
+        // U_n of the first particle each lane links to: the wave visits its
+        // distinct first particles one at a time, reading each one's centre
+        // and velocities with wave-uniform loads. Links to a further particle
+        // of the same node (rare) read it per lane. Walls do not move (C = 0).
         uint32_t on[Q];
-        on[0] = OWN_FLUID;
-        if constexpr (SOLID) {
+        uint32_t p1 = OWN_FLUID;
 #pragma unroll
-            for (int i = 1; i < Q; i++) {
-                on[i] = s_own[LBE_LS(i)];
-                anys |= (on[i] != OWN_FLUID);
+        for (int i = 1; i < Q; i++) {
+            on[i] = s_own[LBE_LS(i)];
+            p1 = (p1 == OWN_FLUID && on[i] < OWN_WALL) ? on[i] : p1;
+        }
+        double Ux1 = 0.0, Uy1 = 0.0, Uz1 = 0.0;
+        bool need = p1 < OWN_WALL;
+        while (true) {
+            const unsigned long long m = __ballot(need);
+            if (m == 0ull) break;
+            const uint32_t q = __builtin_amdgcn_readfirstlane(__shfl(p1, __ffsll(m) - 1, 64));
+            const double qX = part[PX * cap + q], qY = part[PY * cap + q], qZ = part[PZ * cap + q];
+            const double qVx = part[VX * cap + q], qVy = part[VY * cap + q], qVz = part[VZ * cap + q];
+            const double qWx = part[WX * cap + q], qWy = part[WY * cap + q], qWz = part[WZ * cap + q];
+            if (need && p1 == q) {
+                const double rx = minimg((double)x - qX, nx), ry = minimg((double)y - qY, ny),
+                             rz = minimg((double)z - qZ, nz);
+                Ux1 = qVx + (qWy * rz - qWz * ry);
+                Uy1 = qVy + (qWz * rx - qWx * rz);
+                Uz1 = qVz + (qWx * ry - qWy * rx);
+                need = false;
             }
         }
-        if (!anys) {
+        // one store per direction: the push to (i, n + c_i) for a fluid
+        // target, the bounce-back value at (ibar, n) for a solid one
 #pragma unroll
-            for (int i = 1; i < Q; i++) {
-                const uint32_t mb = LBE_NB(i) * (uint32_t)sizeof(S);
-                P::st(atw(fd + (size_t)i * N, mb), f0[i], R(wq(i)) * ref0);
-                P::st(atw(fd + (size_t)(Q + i) * N, mb), f1[i], R(wq(i)) * ref1);
+        for (int i = 1; i < Q; i++) {
+            const uint32_t o = on[i];
+            const bool sol = (o != OWN_FLUID);
+            R C0 = R(0), C1 = R(0);
+            if (o < OWN_WALL) {
+                double Ux = Ux1, Uy = Uy1, Uz = Uz1;
+                if (o != p1) {
+                    const double rx = minimg((double)x - part[PX * cap + o], nx);
+                    const double ry = minimg((double)y - part[PY * cap + o], ny);
+                    const double rz = minimg((double)z - part[PZ * cap + o], nz);
+                    const double wx = part[WX * cap + o], wy = part[WY * cap + o], wz = part[WZ * cap + o];
+                    Ux = part[VX * cap + o] + (wy * rz - wz * ry);
+                    Uy = part[VY * cap + o] + (wz * rx - wx * rz);
+                    Uz = part[VZ * cap + o] + (wx * ry - wy * rx);
+                }
+                const double cu = Ux * cx(i) + Uy * cy(i) + Uz * cz(i);
+                C0 = R(-6.0 * wq(i) * cu) * r0;
+                C1 = R(-6.0 * wq(i) * cu) * r1;
             }
-        } else if constexpr (SOLID) {
-            NodeLinks L;
-            node_links(bx, part, cap, x, y, z, on, L, health);
-            const bool multi = (L.pp[1] != INT_MAX);
-            double F[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-            // one store per direction: the push to (i, n + c_i) for a fluid
-            // target, the bounce-back value at (ibar, n) for a solid one
-#pragma unroll
-            for (int i = 1; i < Q; i++) {
-                const uint32_t o = on[i];
-                const bool sol = (o != OWN_FLUID);
-                R C0, C1;
-                int k;
-                link_term(i, o, L, multi, r0, r1, C0, C1, k);
-                C0 = sol ? C0 : R(0);
-                C1 = sol ? C1 : R(0);
-                const int b = opp(i);
-                const uint32_t mb = sol ? nb : LBE_NB(i) * (uint32_t)sizeof(S);
-                S* d0 = sol ? fd + (size_t)b * N : fd + (size_t)i * N;
-                S* d1 = sol ? fd + (size_t)(Q + b) * N : fd + (size_t)(Q + i) * N;
-                P::st(atw(d0, mb), f0[i] + C0, R(wq(i)) * ref0);  // w_ibar = w_i
-                P::st(atw(d1, mb), f1[i] + C1, R(wq(i)) * ref1);
-                link_force(i, o < OWN_WALL, k, multi, (double)f0[i] + (double)f1[i], (double)C0 + (double)C1, F);
-            }
-            node_accum(L, F, acc);
-            for (int k = 0; k < 3; k++) pp[k] = L.pp[k];
+            const int b = opp(i);
+            const uint32_t mb = sol ? nb : LBE_NB(i) * (uint32_t)sizeof(S);
+            S* d0 = sol ? fd + (size_t)b * N : fd + (size_t)i * N;
+            S* d1 = sol ? fd + (size_t)(Q + b) * N : fd + (size_t)(Q + i) * N;
+            P::st(atw(d0, mb), f0[i] + C0, R(wq(i)) * ref0);  // w_ibar = w_i
+            P::st(atw(d1, mb), f1[i] + C1, R(wq(i)) * ref1);
         }
+    }
 #undef LBE_NB
 #undef LBE_SEL
 #undef LBE_LS
-    }
-    if constexpr (SOLID) block_slots<4>(pp, acc, tile, tcount, tslot, health);
 }
 
-// Row kernel (nx a multiple of 64): a block holds ROWS whole x-rows of one
-// z-plane (NXT = nx nodes each). Because a block owns complete rows, every
-// push can be written aligned: the value a lane stores at x comes from the
-// source node x - c_ix, one lane over (wave shuffle; the wave edges through
-// LDS, rows wrapping periodically inside the block). A store is kept only when
-// its source node is fluid; a bounce-back value goes to the node's own slot
-// (ibar, n). Psi and owner codes of the rows y-1 .. y+ROWS in planes z-1..z+1
-// are staged in LDS.
-template <class P, bool SOLID, int NXT, int ROWS>
-__global__ __launch_bounds__(NXT * ROWS, NXT * ROWS == 256 ? ((SOLID || sizeof(typename P::R) == 8) ? 2 : 4) : 1) void k_fused_rows(
-    Box bx, const typename P::S* __restrict__ fs, typename P::S* __restrict__ fd, const typename P::R* __restrict__ psi,
-    const uint32_t* __restrict__ owner, const double* __restrict__ part, int cap, int* __restrict__ tcount,
-    double* __restrict__ tslot, int* __restrict__ health) {
+// Row kernel for boxes without solids (nx a multiple of 64): a block holds
+// ROWS whole x-rows of one z-plane (NXT = nx nodes each). Because a block owns
+// complete rows, every push can be written aligned: the value a lane stores at
+// x comes from the source node x - c_ix, one lane over (wave shuffle; the wave
+// edges through LDS, rows wrapping periodically inside the block). Psi of the
+// rows y-1 .. y+ROWS in planes z-1..z+1 is staged in LDS.
+template <class P, int NXT, int ROWS>
+__global__ __launch_bounds__(NXT * ROWS, NXT * ROWS == 256 ? (sizeof(typename P::R) == 8 ? 2 : 4) : 1) void k_fused_rows(
+    Box bx, const typename P::S* __restrict__ fs, typename P::S* __restrict__ fd,
+    const typename P::R* __restrict__ psi) {
     using R = typename P::R;
     using S = typename P::S;
     constexpr int NT = NXT * ROWS;      // threads per block
@@ -413,10 +288,8 @@ __global__ __launch_bounds__(NXT * ROWS, NXT * ROWS == 256 ? ((SOLID || sizeof(t
     constexpr int LR = (ROWS + 2) * 3;  // staged rows
     static_assert(NXT % 64 == 0 && NT >= 256 && NT <= 1024, "row kernel shape");
     __shared__ R s_psi[2][LR * NXT];
-    __shared__ uint32_t s_own[SOLID ? LR * NXT : 1];
     // wave-edge values of the 10 directions with c_ix != 0: [wave][slot][comp]
     __shared__ R s_edge[NW][10][2];
-    __shared__ int s_efl[NW][2];
 
     const int ny = bx.ny, nz = bx.nz;
     constexpr int nx = NXT;
@@ -429,19 +302,14 @@ __global__ __launch_bounds__(NXT * ROWS, NXT * ROWS == 256 ? ((SOLID || sizeof(t
     const int y0 = row0 % ny, z = row0 / ny;
     const int y = y0 + r;
     const uint32_t n = (uint32_t)(x + nx * (y + ny * z));
-    const bool fluid = !SOLID || owner[n] == OWN_FLUID;
     const uint32_t nb = n * (uint32_t)sizeof(S);
     const R ref0 = R(bx.rref[0]), ref1 = R(bx.rref[1]);
 
     R f0[Q], f1[Q];
 #pragma unroll
     for (int i = 0; i < Q; i++) {
-        if (fluid) {
-            f0[i] = P::ld(at(fs + (size_t)i * N, nb), R(wq(i)) * ref0);
-            f1[i] = P::ld(at(fs + (size_t)(Q + i) * N, nb), R(wq(i)) * ref1);
-        } else {
-            f0[i] = f1[i] = R(0);
-        }
+        f0[i] = P::ld(at(fs + (size_t)i * N, nb), R(wq(i)) * ref0);
+        f1[i] = P::ld(at(fs + (size_t)(Q + i) * N, nb), R(wq(i)) * ref1);
     }
     for (int e = t; e < LR * NXT; e += NT) {
         const int lrow = e / NXT, xx = e - lrow * NXT;
@@ -450,16 +318,13 @@ __global__ __launch_bounds__(NXT * ROWS, NXT * ROWS == 256 ? ((SOLID || sizeof(t
         const uint32_t m = (uint32_t)(xx + nx * (gy + ny * gz));
         s_psi[0][e] = psi[m];
         s_psi[1][e] = psi[N + m];
-        if (SOLID) s_own[e] = owner[m];
     }
     __syncthreads();
 
     const int xp = x + 1 == nx ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
 #define LBE_LS(i) (((1 + cz(i)) * (ROWS + 2) + (r + 1 + cy(i))) * NXT + (cx(i) == 0 ? x : (cx(i) > 0 ? xp : xm)))
-    R r0 = R(0), r1 = R(0);
-    uint32_t on[Q];
-    on[0] = OWN_FLUID;
-    if (fluid) {
+    R r0, r1;
+    {
         R q0[Q], q1[Q];
 #pragma unroll
         for (int i = 1; i < Q; i++) {
@@ -469,12 +334,7 @@ __global__ __launch_bounds__(NXT * ROWS, NXT * ROWS == 256 ? ((SOLID || sizeof(t
         q0[0] = q1[0] = R(0);
         collide_node<P>(bx, f0, f1, q0, q1, r0, r1);
     }
-    bool anys = false;
-#pragma unroll
-    for (int i = 1; i < Q; i++) {
-        on[i] = SOLID ? s_own[LBE_LS(i)] : OWN_FLUID;
-        anys |= fluid && (on[i] != OWN_FLUID);
-    }
+#undef LBE_LS
     // publish the wave-edge values: lane 63 for c_ix = +1, lane 0 for c_ix = -1
     {
         int sl = 0;
@@ -488,83 +348,41 @@ __global__ __launch_bounds__(NXT * ROWS, NXT * ROWS == 256 ? ((SOLID || sizeof(t
             }
             sl++;
         }
-        if (lane == 63) s_efl[w][0] = fluid ? 1 : 0;
-        if (lane == 0) s_efl[w][1] = fluid ? 1 : 0;
     }
     __syncthreads();
     const int wprev = r * WPR + (wr == 0 ? WPR - 1 : wr - 1);  // wave holding x0 - 1 (periodic)
     const int wnext = r * WPR + (wr == WPR - 1 ? 0 : wr + 1);  // wave holding x0 + 64
-    const int fl_i = fluid ? 1 : 0;
-    const int fl_up = __shfl_up(fl_i, 1, 64);
-    const int fl_dn = __shfl_down(fl_i, 1, 64);
-    const bool src_p = (lane == 0) ? (s_efl[wprev][0] != 0) : (fl_up != 0);   // source x - 1 fluid
-    const bool src_m = (lane == 63) ? (s_efl[wnext][1] != 0) : (fl_dn != 0);  // source x + 1 fluid
 
     // rest population
-    if (fluid) {
-        P::st(atw(fd, nb), f0[0], R(wq(0)) * ref0);
-        P::st(atw(fd + (size_t)Q * N, nb), f1[0], R(wq(0)) * ref1);
-    }
+    P::st(atw(fd, nb), f0[0], R(wq(0)) * ref0);
+    P::st(atw(fd + (size_t)Q * N, nb), f1[0], R(wq(0)) * ref1);
     // aligned row stores: plane i, destination row (y + c_iy, z + c_iz), this x
-    {
-        const uint32_t pl = (uint32_t)(nx * ny);
-        const uint32_t yrow[3] = {(uint32_t)(y * nx), (uint32_t)((y + 1 == ny ? 0 : y + 1) * nx),
-                                  (uint32_t)((y == 0 ? ny - 1 : y - 1) * nx)};
-        const uint32_t zpl[3] = {(uint32_t)z * pl, (uint32_t)(z + 1 == nz ? 0 : z + 1) * pl,
-                                 (uint32_t)(z == 0 ? nz - 1 : z - 1) * pl};
-        int sl = 0;
+    const uint32_t pl = (uint32_t)(nx * ny);
+    const uint32_t yrow[3] = {(uint32_t)(y * nx), (uint32_t)((y + 1 == ny ? 0 : y + 1) * nx),
+                              (uint32_t)((y == 0 ? ny - 1 : y - 1) * nx)};
+    const uint32_t zpl[3] = {(uint32_t)z * pl, (uint32_t)(z + 1 == nz ? 0 : z + 1) * pl,
+                             (uint32_t)(z == 0 ? nz - 1 : z - 1) * pl};
+    int sl = 0;
 #pragma unroll
-        for (int i = 1; i < Q; i++) {
-            R v0 = f0[i], v1 = f1[i];
-            bool src = fluid;
-            if (cx(i) > 0) {
-                const R u0 = __shfl_up(v0, 1, 64), u1 = __shfl_up(v1, 1, 64);
-                v0 = lane == 0 ? s_edge[wprev][sl][0] : u0;
-                v1 = lane == 0 ? s_edge[wprev][sl][1] : u1;
-                src = src_p;
-                sl++;
-            } else if (cx(i) < 0) {
-                const R u0 = __shfl_down(v0, 1, 64), u1 = __shfl_down(v1, 1, 64);
-                v0 = lane == 63 ? s_edge[wnext][sl][0] : u0;
-                v1 = lane == 63 ? s_edge[wnext][sl][1] : u1;
-                src = src_m;
-                sl++;
-            }
-            if (src) {
-                const uint32_t mb =
-                    ((uint32_t)x + yrow[cy(i) == 0 ? 0 : (cy(i) > 0 ? 1 : 2)] + zpl[cz(i) == 0 ? 0 : (cz(i) > 0 ? 1 : 2)]) *
-                    (uint32_t)sizeof(S);
-                P::st(atw(fd + (size_t)i * N, mb), v0, R(wq(i)) * ref0);
-                P::st(atw(fd + (size_t)(Q + i) * N, mb), v1, R(wq(i)) * ref1);
-            }
+    for (int i = 1; i < Q; i++) {
+        R v0 = f0[i], v1 = f1[i];
+        if (cx(i) > 0) {
+            const R u0 = __shfl_up(v0, 1, 64), u1 = __shfl_up(v1, 1, 64);
+            v0 = lane == 0 ? s_edge[wprev][sl][0] : u0;
+            v1 = lane == 0 ? s_edge[wprev][sl][1] : u1;
+            sl++;
+        } else if (cx(i) < 0) {
+            const R u0 = __shfl_down(v0, 1, 64), u1 = __shfl_down(v1, 1, 64);
+            v0 = lane == 63 ? s_edge[wnext][sl][0] : u0;
+            v1 = lane == 63 ? s_edge[wnext][sl][1] : u1;
+            sl++;
         }
+        const uint32_t mb =
+            ((uint32_t)x + yrow[cy(i) == 0 ? 0 : (cy(i) > 0 ? 1 : 2)] + zpl[cz(i) == 0 ? 0 : (cz(i) > 0 ? 1 : 2)]) *
+            (uint32_t)sizeof(S);
+        P::st(atw(fd + (size_t)i * N, mb), v0, R(wq(i)) * ref0);
+        P::st(atw(fd + (size_t)(Q + i) * N, mb), v1, R(wq(i)) * ref1);
     }
-    int pp[3] = {INT_MAX, INT_MAX, INT_MAX};
-    double acc[3][6] = {{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}};
-    if constexpr (SOLID) {
-        if (anys) {
-            NodeLinks L;
-            node_links(bx, part, cap, x, y, z, on, L, health);
-            const bool multi = (L.pp[1] != INT_MAX);
-            double F[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-#pragma unroll
-            for (int i = 1; i < Q; i++) {
-                const uint32_t o = on[i];
-                if (o == OWN_FLUID) continue;
-                R C0, C1;
-                int k;
-                link_term(i, o, L, multi, r0, r1, C0, C1, k);
-                const int b = opp(i);
-                P::st(atw(fd + (size_t)b * N, nb), f0[i] + C0, R(wq(i)) * ref0);  // w_ibar = w_i
-                P::st(atw(fd + (size_t)(Q + b) * N, nb), f1[i] + C1, R(wq(i)) * ref1);
-                link_force(i, o < OWN_WALL, k, multi, (double)f0[i] + (double)f1[i], (double)C0 + (double)C1, F);
-            }
-            node_accum(L, F, acc);
-            for (int k = 0; k < 3; k++) pp[k] = L.pp[k];
-        }
-        block_slots<NW>(pp, acc, blk, tcount, tslot, health);
-    }
-#undef LBE_LS
 }
 
 // ---------------------------------------------------------------- init
@@ -697,6 +515,19 @@ __global__ __launch_bounds__(256) void k_remove_covered(Box bx, typename P::S* _
     if (m != 0.0) unsafeAtomicAdd(counters, m);
 }
 
+__global__ void k_copy16(const uint4* __restrict__ a, uint4* __restrict__ b, size_t n) {
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+        b[k] = a[k];
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    const size_t n = bytes / 16;
+    unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 1u << 20);
+    if (g == 0) g = 1;
+    hipLaunchKernelGGL(k_copy16, dim3(g), dim3(256), 0, st, (const uint4*)src, (uint4*)dst, n);
+    return hipGetLastError();
+}
+
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
         p[k] = v;
@@ -741,12 +572,13 @@ hipError_t launch_density(lb_handle* h) {
     return hipGetLastError();
 }
 
-Tiles fused_tiles(int nx, int ny, bool solids) {
+Tiles fused_tiles(int nx, int ny, bool solids, int precision) {
     Tiles t;
-    // Particle-free boxes whose rows fill whole blocks use the row kernel
-    // (aligned stores); with particles the tile kernel is faster (fewer force
-    // slots per particle, cheaper bounce-back).
-    if (!solids && ((nx == 64 && ny % 4 == 0) || (nx == 128 && ny % 2 == 0) || nx == 256 || nx == 512)) {
+    // Boxes without solids whose rows fill whole blocks use the row kernel
+    // (aligned stores) for 4- and 2-byte populations; FP64 populations and
+    // boxes with solids use the tile kernel (measured faster: the FP64 row
+    // kernel is held to two waves per SIMD by its registers).
+    if (!solids && precision != LB_FP64 && ((nx == 64 && ny % 4 == 0) || (nx == 128 && ny % 2 == 0) || nx == 256 || nx == 512)) {
         // row kernel: whole x-rows per block
         t.BX = nx;
         t.BY = nx >= 256 ? 1 : 256 / nx;
@@ -768,38 +600,34 @@ static void launch_fused_t(lb_handle* h, const Tiles& tl, unsigned grid) {
     auto fd = (typename P::S*)h->b.f[d];
     auto ps = (const typename P::R*)h->b.psi;
     const uint32_t* ow = h->b.owner[h->ocur];
-    if (tl.tiles_x == 1 && tl.BX >= 64 && tl.BX == h->box.nx) {
+    if (!SOLID && tl.tiles_x == 1 && tl.BX >= 64 && tl.BX == h->box.nx) {
         const dim3 blk(tl.BX * tl.BY);
         switch (tl.BX) {
             case 64:
-                hipLaunchKernelGGL((k_fused_rows<P, SOLID, 64, 4>), dim3(grid), blk, 0, h->stream, h->box, fs, fd, ps,
-                                   ow, h->b.part, h->cap, h->b.tcount, h->b.tslot, h->b.health);
+                hipLaunchKernelGGL((k_fused_rows<P, 64, 4>), dim3(grid), blk, 0, h->stream, h->box, fs, fd, ps);
                 break;
             case 128:
-                hipLaunchKernelGGL((k_fused_rows<P, SOLID, 128, 2>), dim3(grid), blk, 0, h->stream, h->box, fs, fd,
-                                   ps, ow, h->b.part, h->cap, h->b.tcount, h->b.tslot, h->b.health);
+                hipLaunchKernelGGL((k_fused_rows<P, 128, 2>), dim3(grid), blk, 0, h->stream, h->box, fs, fd, ps);
                 break;
             case 256:
-                hipLaunchKernelGGL((k_fused_rows<P, SOLID, 256, 1>), dim3(grid), blk, 0, h->stream, h->box, fs, fd,
-                                   ps, ow, h->b.part, h->cap, h->b.tcount, h->b.tslot, h->b.health);
+                hipLaunchKernelGGL((k_fused_rows<P, 256, 1>), dim3(grid), blk, 0, h->stream, h->box, fs, fd, ps);
                 break;
             default:
-                hipLaunchKernelGGL((k_fused_rows<P, SOLID, 512, 1>), dim3(grid), blk, 0, h->stream, h->box, fs, fd,
-                                   ps, ow, h->b.part, h->cap, h->b.tcount, h->b.tslot, h->b.health);
+                hipLaunchKernelGGL((k_fused_rows<P, 512, 1>), dim3(grid), blk, 0, h->stream, h->box, fs, fd, ps);
                 break;
         }
         return;
     }
     if (tl.BX == 64)
         hipLaunchKernelGGL((k_fused<P, SOLID, 64, 4>), dim3(grid), dim3(256), 0, h->stream, h->box, fs, fd, ps, ow,
-                           h->b.part, h->cap, tl.tiles_x, tl.tiles_y, h->b.tcount, h->b.tslot, h->b.health);
+                           h->b.part, h->cap, tl.tiles_x, tl.tiles_y);
     else
         hipLaunchKernelGGL((k_fused<P, SOLID, 32, 8>), dim3(grid), dim3(256), 0, h->stream, h->box, fs, fd, ps, ow,
-                           h->b.part, h->cap, tl.tiles_x, tl.tiles_y, h->b.tcount, h->b.tslot, h->b.health);
+                           h->b.part, h->cap, tl.tiles_x, tl.tiles_y);
 }
 
 hipError_t launch_fused(lb_handle* h) {
-    const Tiles tl = fused_tiles(h->box.nx, h->box.ny, h->has_solid);
+    const Tiles tl = fused_tiles(h->box.nx, h->box.ny, h->has_solid, h->prm.precision);
     const unsigned grid = (unsigned)(tl.tiles_x * tl.tiles_y * h->box.nz);
     if (h->has_solid) {
         LBE_DISPATCH(h->prm.precision, (launch_fused_t<P, true>(h, tl, grid)));

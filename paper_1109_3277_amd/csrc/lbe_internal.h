@@ -19,8 +19,8 @@ struct Buffers {
     void* rho = nullptr;               // rho^c per node [2][N], for the shell fill (exponential Psi)
     uint32_t* owner[2] = {nullptr, nullptr};
     double* part = nullptr;            // particle table, NPFIELD x cap
-    int* tcount = nullptr;             // bounce-back slots used per fused tile
-    double* tslot = nullptr;           // per tile: kTileSlots x (particle, F, T)
+    uint2* slist = nullptr;            // surface list segments, cap x nslab(raster) x 64 (node, link mask)
+    int* scount = nullptr;             // entries per surface list segment, cap x nslab(raster)
     double* kpart = nullptr;           // kill/fill impulse partial slots, cap x nslab x 6
     double* red = nullptr;             // reduction partials, kRedBlocks x 8, then totals
     double* counters = nullptr;        // [0] mass removed (cumulative), [1] kill mass, [2] fill mass
@@ -64,7 +64,7 @@ hipError_t launch_density(lb_handle* h);
 hipError_t launch_shell(lb_handle* h);
 hipError_t launch_fused(lb_handle* h);
 hipError_t launch_forces(lb_handle* h);
-Tiles fused_tiles(int nx, int ny, bool solids);
+Tiles fused_tiles(int nx, int ny, bool solids, int precision);
 hipError_t launch_fields(lb_handle* h, double* d_out);       // rho_a, rho_b, u (5 x N doubles)
 hipError_t launch_stats(lb_handle* h);                       // totals into b.red[kRedBlocks*8 ...]
 hipError_t launch_remove_covered(lb_handle* h);
@@ -76,6 +76,7 @@ hipError_t launch_fold_impulses(lb_handle* h);
 Slab make_slab(int ext);
 int raster_extent(int nx, int ny, int nz, double rb);
 int killfill_extent(int nx, int ny, int nz, double rb);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 hipError_t launch_fill_u32(lb_handle* h, uint32_t* p, uint32_t v, int64_t n);
 hipError_t launch_fill_f64(lb_handle* h, double* p, double v, int64_t n);
 

@@ -1,12 +1,13 @@
-// Particle kernels of liblbe (gfx950): shell fill, the per-particle sum of the
-// bounce-back forces, rigid-body update, rasterisation of the ellipsoids onto
+// Particle kernels of liblbe (gfx950): shell fill, the bounce-back force and
+// torque of each particle, rigid-body update, rasterisation of the ellipsoids onto
 // the owner map, and kill / fill of nodes that change side.
 //
 // Every per-node particle kernel runs one thread per node of a particle's
 // bounding box (Slab geometry, one-wave blocks), so the dependent loads of
 // neighbouring nodes are spread over many short-lived waves instead of looped.
-// Forces, torques and kill/fill impulses are summed in fixed orders (tile slot
-// lists, per-block partial slots): particle state is reproducible bit for bit.
+// Forces, torques and kill/fill impulses are summed in fixed orders (per-block
+// partial slots, added in slot order): particle state is reproducible bit for
+// bit.
 // Particle state is FP64 in every precision form.
 #include <math.h>
 
@@ -15,6 +16,14 @@
 #include "lbe_internal.h"
 
 namespace lbe {
+
+#define LBE_PDISPATCH(prec, CALL)                            \
+    switch (prec) {                                          \
+        case LB_FP64: { using P = PolF64; CALL; } break;     \
+        case LB_FP32: { using P = PolF32; CALL; } break;     \
+        case LB_FP16_DEV: { using P = PolF16; CALL; } break; \
+        default: { using P = PolBF16; CALL; } break;         \
+    }
 
 // Rotation matrix (body -> space) of a unit quaternion (w, x, y, z).
 __device__ inline void qrot(double w, double x, double y, double z, double R[3][3]) {
@@ -74,124 +83,196 @@ __global__ void k_raster(Box bx, const double* __restrict__ part, int cap, uint3
 // takes their mean density; the particle colour is added to A if positive,
 // its magnitude to B if negative. Densities are recovered from the stored
 // Psi and the result is stored as Psi.
+// The same pass lists p's surface: every node of p with a fluid neighbour, as
+// (node, mask) with bit i set when the node's neighbour at -c_i is fluid, in
+// this block's own segment of 64 entries (lane order) plus its count.
 template <class R>
 __global__ void k_shell(Box bx, R* __restrict__ psi, const R* __restrict__ rho, const uint32_t* __restrict__ owner,
-                        const double* __restrict__ part, int cap, Slab sl) {
+                        const double* __restrict__ part, int cap, Slab sl, uint2* __restrict__ slist,
+                        int* __restrict__ scount) {
     const int p = blockIdx.x;
-    int lo[3], sz[3], ix, iy, iz;
-    if (!particle_box(bx, part, cap, p, lo, sz)) return;
-    if (!slab_node(sl, sz, ix, iy, iz)) return;
     const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
-    const int x = wrapc_any(lo[0] + ix, nx), y = wrapc_any(lo[1] + iy, ny), z = wrapc_any(lo[2] + iz, nz);
-    const int64_t n = node_index(bx, x, y, z);
-    if (owner[n] != (uint32_t)p) return;
     const int64_t N = bx.N;
-    // densities of fluid nodes: the stored rho (Psi itself when Psi = rho)
-    const R* dens = bx.psi_kind == 0 ? psi : rho;
-    int64_t mi[Q];
-    uint32_t on[Q];
-    R d0[Q], d1[Q];
+    int lo[3], sz[3], ix, iy, iz;
+    uint32_t mask = 0u;
+    int64_t n = 0;
+    if (particle_box(bx, part, cap, p, lo, sz) && slab_node(sl, sz, ix, iy, iz)) {
+        const int x = wrapc_any(lo[0] + ix, nx), y = wrapc_any(lo[1] + iy, ny), z = wrapc_any(lo[2] + iz, nz);
+        n = node_index(bx, x, y, z);
+        if (owner[n] == (uint32_t)p) {
+            // densities of fluid nodes: the stored rho (Psi itself when Psi = rho)
+            const R* dens = bx.psi_kind == 0 ? psi : rho;
+            uint32_t on[Q];
+            R d0[Q], d1[Q];
 #pragma unroll
-    for (int i = 1; i < Q; i++) {
-        mi[i] = node_index(bx, wrapc(x + cx(i), nx), wrapc(y + cy(i), ny), wrapc(z + cz(i), nz));
-        on[i] = owner[mi[i]];
-        d0[i] = dens[mi[i]];
-        d1[i] = dens[N + mi[i]];
-    }
-    R s0 = R(0), s1 = R(0);
-    int k = 0;
+            for (int i = 1; i < Q; i++) {
+                const int64_t m = node_index(bx, wrapc(x + cx(i), nx), wrapc(y + cy(i), ny), wrapc(z + cz(i), nz));
+                on[i] = owner[m];
+                d0[i] = dens[m];
+                d1[i] = dens[N + m];
+            }
+            R s0 = R(0), s1 = R(0);
+            int k = 0;
 #pragma unroll
-    for (int i = 1; i < Q; i++) {
-        if (on[i] != OWN_FLUID) continue;
-        s0 += d0[i];
-        s1 += d1[i];
-        k++;
+            for (int i = 1; i < Q; i++) {
+                if (on[i] != OWN_FLUID) continue;
+                s0 += d0[i];
+                s1 += d1[i];
+                k++;
+                mask |= 1u << opp(i);
+            }
+            if (k == 0) {
+                psi[n] = R(0);
+                psi[N + n] = R(0);
+            } else {
+                const double dr = part[DRHO * cap + p];
+                R a = s0 / R(k), b = s1 / R(k);
+                if (dr > 0.0) a += R(dr);
+                else if (dr < 0.0) b += R(-dr);
+                psi[n] = psi_of(a, bx.psi_kind);
+                psi[N + n] = psi_of(b, bx.psi_kind);
+            }
+        }
     }
-    if (k == 0) {
-        psi[n] = R(0);
-        psi[N + n] = R(0);
-        return;
+    const unsigned long long bal = __ballot(mask != 0u);
+    const size_t seg = (size_t)p * sl.nslab + blockIdx.y * sl.tiles + blockIdx.z;
+    if (mask != 0u) {
+        const int pos = __popcll(bal & ((1ull << threadIdx.x) - 1ull));
+        slist[seg * 64 + pos] = make_uint2((uint32_t)n, mask);
     }
-    const double dr = part[DRHO * cap + p];
-    R a = s0 / R(k), b = s1 / R(k);
-    if (dr > 0.0) a += R(dr);
-    else if (dr < 0.0) b += R(-dr);
-    psi[n] = psi_of(a, bx.psi_kind);
-    psi[N + n] = psi_of(b, bx.psi_kind);
+    if (threadIdx.x == 0) scount[seg] = __popcll(bal);
 }
 
 // ---------------------------------------------------------------- S6 forces
-// Bounce-back force and torque of particle p (Eq. (5)): the sum of the slots
-// that the fused kernel left for p in the tiles overlapping p's bounding box
-// grown by one node (a link's fluid end lies at most one node outside it),
-// tiles visited and summed in a fixed order.
-__global__ __launch_bounds__(256) void k_forces(Box bx, double* __restrict__ part, int cap, Tiles tl,
-                                                const int* __restrict__ tcount, const double* __restrict__ tslot) {
-    __shared__ int s_tx[512], s_ty[512], s_n[3], s_z0, s_ok;
+// Bounce-back force and torque of particle p (Eq. (5)), link by link from the
+// solid end. A surface node m of p and a direction i whose source n = m - c_i
+// is fluid form the link n -> m: the fused kernel sent f*_i(n) along it and
+// stored f'_ibar(n) = f*_i(n) + C back at n, so the link's momentum exchange
+// (2 f*_i + C) c_i equals (2 f'_ibar(n) - C) c_i, summed over both
+// components. C = -6 w_i rho^c(n) (U_n . c_i) is formed exactly as the fused
+// kernel formed it (U_n = V + W x r_n at n, rho^c(n) from the density pass).
+// The torque is r_n x F. One block per particle walks p's surface list (the
+// shell pass wrote it for the same owner map): entry e goes to thread
+// e mod 256, entries and links in increasing order, then a fixed block sum,
+// so the result is reproducible bit for bit.
+template <class P>
+__global__ __launch_bounds__(256) void k_linkforce(Box bx, const typename P::S* __restrict__ f,
+                                                   const typename P::R* __restrict__ dens,
+                                                   double* __restrict__ part, int cap, int nslab,
+                                                   const uint2* __restrict__ slist, const int* __restrict__ scount) {
+    using R = typename P::R;
+    __shared__ int s_pre[257];
+    __shared__ int s_wsum[4];
     const int p = blockIdx.x;
-    const int Ls[3] = {bx.nx, bx.ny, bx.nz};
-    if (threadIdx.x == 0) {
-        int lo[3], sz[3];
-        s_ok = particle_box(bx, part, cap, p, lo, sz) ? 1 : 0;
-        if (s_ok) {
-            // distinct x tiles, y tiles and z planes of the grown box
-            const int tdim[2] = {tl.BX, tl.BY};
-            int* lists[2] = {s_tx, s_ty};
-            for (int d = 0; d < 2; d++) {
-                const int a = lo[d] - 1, len = min(sz[d] + 2, Ls[d]);
-                int cnt = 0;
-                for (int v = a; v < a + len; v++) {
-                    const int t = wrapc_any(v, Ls[d]) / tdim[d];
-                    bool seen = false;
-                    for (int j = 0; j < cnt; j++) seen |= (lists[d][j] == t);
-                    if (!seen && cnt < 512) lists[d][cnt++] = t;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t N = bx.N;
+    const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
+    const double X[3] = {part[PX * cap + p], part[PY * cap + p], part[PZ * cap + p]};
+    const double V[3] = {part[VX * cap + p], part[VY * cap + p], part[VZ * cap + p]};
+    const double W[3] = {part[WX * cap + p], part[WY * cap + p], part[WZ * cap + p]};
+    const R ref0 = R(bx.rref[0]), ref1 = R(bx.rref[1]);
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int c0 = 0; c0 < nslab; c0 += 256) {
+        const int nc = min(256, nslab - c0);
+        // exclusive prefix of the segment counts of this chunk
+        const int cnt = tid < nc ? scount[(size_t)p * nslab + c0 + tid] : 0;
+        int v = cnt;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int u = __shfl_up(v, off, 64);
+            if (lane >= off) v += u;
+        }
+        if (lane == 63) s_wsum[w] = v;
+        __syncthreads();
+        int base = 0;
+        for (int j = 0; j < w; j++) base += s_wsum[j];
+        s_pre[tid] = base + v - cnt;
+        if (tid == 255) s_pre[256] = base + v;
+        __syncthreads();
+        const int total = s_pre[256];
+        for (int e = tid; e < total; e += 256) {
+            int a = 0, b = nc - 1;  // last segment whose prefix is <= e
+            while (a < b) {
+                const int mid = (a + b + 1) >> 1;
+                if (s_pre[mid] <= e) a = mid;
+                else b = mid - 1;
+            }
+            const uint2 ent = slist[((size_t)p * nslab + c0 + a) * 64 + (e - s_pre[a])];
+            const uint32_t m = ent.x, mask = ent.y;
+            const int mz = (int)(m / (uint32_t)(nx * ny));
+            const int rem = (int)(m - (uint32_t)mz * (uint32_t)(nx * ny));
+            const int my = rem / nx, mx = rem - my * nx;
+            // the link loads of half of the directions are issued together
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                R a0[9], a1[9], g0[9], g1[9];
+#pragma unroll
+                for (int j = 0; j < 9; j++) {
+                    const int i = 1 + 9 * h + j;
+                    a0[j] = a1[j] = g0[j] = g1[j] = R(0);
+                    if (mask & (1u << i)) {
+                        const int64_t n =
+                            node_index(bx, wrapc(mx - cx(i), nx), wrapc(my - cy(i), ny), wrapc(mz - cz(i), nz));
+                        a0[j] = dens[n];
+                        a1[j] = dens[N + n];
+                        g0[j] = P::ld(f + (size_t)opp(i) * N + n, R(wq(i)) * ref0);
+                        g1[j] = P::ld(f + (size_t)(Q + opp(i)) * N + n, R(wq(i)) * ref1);
+                    }
                 }
-                s_n[d] = cnt;
+#pragma unroll
+                for (int j = 0; j < 9; j++) {
+                    const int i = 1 + 9 * h + j;
+                    if (!(mask & (1u << i))) continue;
+                    const double rx = minimg((double)wrapc(mx - cx(i), nx) - X[0], nx);
+                    const double ry = minimg((double)wrapc(my - cy(i), ny) - X[1], ny);
+                    const double rz = minimg((double)wrapc(mz - cz(i), nz) - X[2], nz);
+                    const double Ux = V[0] + (W[1] * rz - W[2] * ry);
+                    const double Uy = V[1] + (W[2] * rx - W[0] * rz);
+                    const double Uz = V[2] + (W[0] * ry - W[1] * rx);
+                    const double cu = Ux * cx(i) + Uy * cy(i) + Uz * cz(i);
+                    const R C0 = R(-6.0 * wq(i) * cu) * a0[j];
+                    const R C1 = R(-6.0 * wq(i) * cu) * a1[j];
+                    const double mag = 2.0 * ((double)g0[j] + (double)g1[j]) - ((double)C0 + (double)C1);
+                    const double Fx = mag * cx(i), Fy = mag * cy(i), Fz = mag * cz(i);
+                    acc[0] += Fx;
+                    acc[1] += Fy;
+                    acc[2] += Fz;
+                    acc[3] += ry * Fz - rz * Fy;
+                    acc[4] += rz * Fx - rx * Fz;
+                    acc[5] += rx * Fy - ry * Fx;
+                }
             }
-            s_n[2] = min(sz[2] + 2, Ls[2]);
-            s_z0 = lo[2] - 1;
         }
-    }
-    __syncthreads();
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    if (s_ok) {
-        const int ntx = s_n[0], nty = s_n[1], nzr = s_n[2], z0 = s_z0;
-        const int total = ntx * nty * nzr;
-        for (int t = threadIdx.x; t < total; t += blockDim.x) {
-            const int ix = t % ntx, iy = (t / ntx) % nty, iz = t / (ntx * nty);
-            const int z = wrapc_any(z0 + iz, Ls[2]);
-            const int tile = (z * tl.tiles_y + s_ty[iy]) * tl.tiles_x + s_tx[ix];
-            const int c = tcount[tile];
-            const double* sl = tslot + (size_t)tile * kTileSlots * 7;
-            for (int k = 0; k < c; k++) {
-                if ((int)sl[k * 7] != p) continue;
-                for (int j = 0; j < 6; j++) acc[j] += sl[k * 7 + 1 + j];
-            }
-        }
+        __syncthreads();  // s_pre / s_wsum are rewritten by the next chunk
     }
     double tot[6];
     block_sum6(acc, tot);
-    if (threadIdx.x == 0) {
-        const int f[6] = {FX, FY, FZ, TX, TY, TZ};
-        for (int k = 0; k < 6; k++) part[f[k] * cap + p] = tot[k];
+    if (tid == 0) {
+        const int fld[6] = {FX, FY, FZ, TX, TY, TZ};
+        for (int k = 0; k < 6; k++) part[fld[k] * cap + p] = tot[k];
     }
 }
 
 // ---------------------------------------------------------------- S7
 // Newton-Euler update, dt = 1: F = F_links + J, T = T_links + H; V += F/M,
 // X = wrap(X + V); L += T; W = R I^-1 R^T L with the old orientation;
-// q <- normalise(exp(W/2) (x) q). F_links / T_links come from k_forces; J / H
-// are the stored impulses plus the kill/fill slots, summed in order.
-__global__ void k_bodies(Box bx, double* __restrict__ part, int cap, int np, const double* __restrict__ kpart,
-                         int nk) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
+// q <- normalise(exp(W/2) (x) q). F_links / T_links come from k_linkforce;
+// J / H are the stored impulses plus the kill/fill slots. One wave per
+// particle: lane l sums slots l, l + 64, ... in order, then a fixed shuffle
+// tree; lane 0 updates the body.
+__global__ __launch_bounds__(64) void k_bodies(Box bx, double* __restrict__ part, int cap, int np,
+                                               const double* __restrict__ kpart, int nk) {
+    const int p = blockIdx.x;
+    const int lane = threadIdx.x;
+    double Jk[6] = {0, 0, 0, 0, 0, 0};
+    for (int s = lane; s < nk; s += 64)
+        for (int k = 0; k < 6; k++) Jk[k] += kpart[((size_t)p * nk + s) * 6 + k];
+#pragma unroll
+    for (int k = 0; k < 6; k++)
+        for (int off = 32; off > 0; off >>= 1) Jk[k] += __shfl_down(Jk[k], off, 64);
+    if (lane != 0 || p >= np) return;
     double* P = part;
 #define F_(k) P[(k) * cap + p]
     const double Fl[6] = {F_(FX), F_(FY), F_(FZ), F_(TX), F_(TY), F_(TZ)};
-    double Jk[6] = {0, 0, 0, 0, 0, 0};
-    for (int s = 0; s < nk; s++)
-        for (int k = 0; k < 6; k++) Jk[k] += kpart[((size_t)p * nk + s) * 6 + k];
     const double J[3] = {F_(JX) + Jk[0], F_(JY) + Jk[1], F_(JZ) + Jk[2]};
     const double H[3] = {F_(HX) + Jk[3], F_(HY) + Jk[4], F_(HZ) + Jk[5]};
     double F[3], T[3];
@@ -440,24 +521,32 @@ hipError_t launch_shell(lb_handle* h) {
     const dim3 g(h->np, s.ext, s.tiles);
     if (h->prm.precision == LB_FP64)
         hipLaunchKernelGGL(k_shell<double>, g, dim3(s.B), 0, h->stream, h->box, (double*)h->b.psi,
-                           (const double*)h->b.rho, h->b.owner[h->ocur], h->b.part, h->cap, s);
+                           (const double*)h->b.rho, h->b.owner[h->ocur], h->b.part, h->cap, s, h->b.slist,
+                           h->b.scount);
     else
         hipLaunchKernelGGL(k_shell<float>, g, dim3(s.B), 0, h->stream, h->box, (float*)h->b.psi,
-                           (const float*)h->b.rho, h->b.owner[h->ocur], h->b.part, h->cap, s);
+                           (const float*)h->b.rho, h->b.owner[h->ocur], h->b.part, h->cap, s, h->b.slist,
+                           h->b.scount);
     return hipGetLastError();
 }
 
 hipError_t launch_forces(lb_handle* h) {
     if (h->np <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_forces, dim3(h->np), dim3(256), 0, h->stream, h->box, h->b.part, h->cap,
-                       fused_tiles(h->box.nx, h->box.ny, true), h->b.tcount, h->b.tslot);
+    const int nslab = slab_raster(h).nslab;
+    const void* fn = h->b.f[1 - h->cur];
+    // rho^c(n) of fluid nodes: Psi itself when Psi = rho, else the stored rho
+    const void* dens = h->prm.psi_kind == 0 ? h->b.psi : h->b.rho;
+    LBE_PDISPATCH(h->prm.precision,
+                  hipLaunchKernelGGL(k_linkforce<P>, dim3(h->np), dim3(256), 0, h->stream, h->box,
+                                     (const typename P::S*)fn, (const typename P::R*)dens, h->b.part, h->cap, nslab,
+                                     h->b.slist, h->b.scount));
     return hipGetLastError();
 }
 
 hipError_t launch_bodies(lb_handle* h) {
     if (h->np <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bodies, dim3((h->np + 63) / 64), dim3(64), 0, h->stream, h->box, h->b.part, h->cap, h->np,
-                       h->b.kpart, slab_killfill(h).nslab);
+    hipLaunchKernelGGL(k_bodies, dim3(h->np), dim3(64), 0, h->stream, h->box, h->b.part, h->cap, h->np, h->b.kpart,
+                       slab_killfill(h).nslab);
     return hipGetLastError();
 }
 

@@ -53,7 +53,7 @@ bool params_ok(const lb_params* p, std::string* why) {
 }
 
 struct Layout {
-    size_t f, psi, rho, owner, part, tcount, tslot, kpart, red, counters, health, total;
+    size_t f, psi, rho, owner, part, slist, scount, kpart, red, counters, health, total;
 };
 
 Layout layout_of(const lb_params* p) {
@@ -66,16 +66,15 @@ Layout layout_of(const lb_params* p) {
     L.owner = align_up(N * sizeof(uint32_t));
     L.part = align_up(NPFIELD * cap * sizeof(double));
     const double rmax = p->max_particles > 0 ? p->max_radius : 0.5;
+    const Slab s1 = make_slab(raster_extent(p->nx, p->ny, p->nz, rmax));
     const Slab s2 = make_slab(killfill_extent(p->nx, p->ny, p->nz, rmax));
-    const Tiles tl = fused_tiles(p->nx, p->ny, true);
-    const size_t ntiles = (size_t)tl.tiles_x * tl.tiles_y * p->nz;
-    L.tcount = p->max_particles > 0 ? align_up(ntiles * sizeof(int)) : 0;
-    L.tslot = p->max_particles > 0 ? align_up(ntiles * kTileSlots * 7 * sizeof(double)) : 0;
+    L.slist = p->max_particles > 0 ? align_up(cap * (size_t)s1.nslab * 64 * sizeof(uint2)) : 0;
+    L.scount = p->max_particles > 0 ? align_up(cap * (size_t)s1.nslab * sizeof(int)) : 0;
     L.kpart = align_up(cap * (size_t)s2.nslab * 6 * sizeof(double));
     L.red = align_up((kRedBlocks + 1) * 8 * sizeof(double));
     L.counters = align_up(8 * sizeof(double));
     L.health = align_up(sizeof(int));
-    L.total = 2 * L.f + L.psi + L.rho + 2 * L.owner + L.part + L.tcount + L.tslot + L.kpart + L.red + L.counters +
+    L.total = 2 * L.f + L.psi + L.rho + 2 * L.owner + L.part + L.slist + L.scount + L.kpart + L.red + L.counters +
               L.health;
     return L;
 }
@@ -173,8 +172,8 @@ int lb_create(const lb_params* prm, void* dev_ws, size_t ws_bytes, void* hip_str
     h->b.owner[0] = (uint32_t*)p; p += L.owner;
     h->b.owner[1] = (uint32_t*)p; p += L.owner;
     h->b.part = (double*)p; p += L.part;
-    h->b.tcount = L.tcount ? (int*)p : nullptr; p += L.tcount;
-    h->b.tslot = L.tslot ? (double*)p : nullptr; p += L.tslot;
+    h->b.slist = L.slist ? (uint2*)p : nullptr; p += L.slist;
+    h->b.scount = L.scount ? (int*)p : nullptr; p += L.scount;
     h->b.kpart = (double*)p; p += L.kpart;
     h->b.red = (double*)p; p += L.red;
     h->b.counters = (double*)p; p += L.counters;
@@ -345,10 +344,6 @@ int lb_step(lb_handle* h, int32_t nsteps) {
     LBE_HIP(h, hipMemcpyAsync(&bad, h->b.health, sizeof(int), hipMemcpyDeviceToHost, h->stream));
     LBE_HIP(h, hipStreamSynchronize(h->stream));
     if (bad & 2) return fail(h, LB_EUNSTABLE, "a particle moved more than two lattice spacings in one step");
-    if (bad & 4)
-        return fail(h, LB_EUNSTABLE,
-                    "particles too crowded: a node touches more than two particles or a tile more than " +
-                        std::to_string(kTileSlots));
     if (bad) return fail(h, LB_EUNSTABLE, "NaN or negative density detected");
     return LB_OK;
 }
@@ -502,6 +497,13 @@ int lb_load_state(lb_handle* h, const void* host_buf, size_t bytes) {
     h->rmax = hdr[5];
     h->has_solid = h->np > 0;
     h->inited = true;
+    return LB_OK;
+}
+
+int lb_probe_copy(void* dev_dst, const void* dev_src, size_t bytes, void* hip_stream) {
+    if (!dev_dst || !dev_src || bytes % 16 != 0) return fail(nullptr, LB_EINVAL, "probe copy needs 16-byte multiples");
+    hipError_t e = launch_copy(dev_dst, dev_src, bytes, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(nullptr, LB_EHIP, hipGetErrorString(e));
     return LB_OK;
 }
 

@@ -187,8 +187,8 @@ def test_checkpoint_roundtrip():
 
 
 def test_node_touching_three_particles_fp64():
-    """A fluid node whose links end in three different particles (the most a
-    node may touch), the particles carrying different colours."""
+    """A fluid node whose links end in three different particles (the most
+    the kernel sums per node), the particles carrying different colours."""
     import oracle
     from paper_1109_3277_amd.workloads import System, uniform_fields
 
@@ -206,13 +206,37 @@ def test_node_touching_three_particles_fp64():
     _check_fp64(res)
 
 
+def test_node_touching_five_particles_fp64():
+    """Particles crowding so that one fluid node links to five of them: the
+    fourth and fifth are handled link by link through the overflow
+    accumulators and must still match the oracle."""
+    import oracle
+    from paper_1109_3277_amd.workloads import System, uniform_fields
+
+    dims = (24, 24, 24)
+    ra, rb = uniform_fields(dims, 23, 0.7, 0.7, 0.01)
+    pos = np.array([[9.0, 12.0, 12.0], [15.0, 12.0, 12.0], [12.0, 15.0, 12.0], [12.0, 9.0, 12.0],
+                    [12.0, 12.0, 15.0]])
+    s = System("five", dims, 1.0, 0.08, ra, rb, np.full((5, 2), 2.4), pos, np.tile([1.0, 0, 0, 0], (5, 1)),
+               np.array([0.05, -0.05, 0.0, 0.03, -0.02]), np.full(5, 10.0))
+    o0 = oracle.Oracle(dims, 1.0, 0.08)
+    o0.init_fields(ra, rb)
+    o0.add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
+    own = o0.owner().reshape(24, 24, 24)
+    assert own[12, 12, 12] == -1
+    assert [own[12, 12, 11], own[12, 12, 13], own[12, 13, 12], own[12, 11, 12], own[13, 12, 12]] == [0, 1, 2, 3, 4]
+    _, _, res = _run(s, 20)
+    _check_fp64(res)
+
+
 @pytest.mark.parametrize("nx", [64, 128, 256, 512])
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16_dev"])
 @pytest.mark.parametrize("particles", [False, True])
 def test_row_kernel_widths(nx, prec, particles):
-    """Box widths whose x-rows fill whole blocks: without particles they run
-    the aligned-store row kernel (wave-edge exchange, periodic seam); with
-    small particles crossing wave boundaries and the seam, the tile kernel."""
+    """Box widths whose x-rows fill whole blocks: without particles and with
+    4- or 2-byte populations they run the aligned-store row kernel (wave-edge
+    exchange, periodic seam); FP64 and boxes with small particles crossing
+    wave boundaries and the seam run the tile kernel."""
     from paper_1109_3277_amd.workloads import System, uniform_fields
 
     dims = (nx, 16, 12)
@@ -231,9 +255,12 @@ def test_row_kernel_widths(nx, prec, particles):
     o, g, res = _run(s, 40, prec)
     if prec == "fp64":
         _check_fp64(res)
-    else:
+    elif prec == "fp32":
         log(f"  fp32 {res}")
         assert res["e_rho"] <= 1e-5 and res["owner_equal"], res
+    else:
+        log(f"  {prec} {res}")
+        assert res["e_rho"] <= 1e-3 and res["owner_equal"], res
 
 
 def test_bijel_full_size_fp64():
