@@ -127,7 +127,7 @@ __device__ inline void collide_node(const Box& bx, typename P::R (&f0)[Q], typen
 // Tile kernel (any box): BX x BY nodes of one xy-plane per 256-thread block,
 // Psi and owner codes of the tile and its one-node halo staged in LDS.
 template <class P, bool SOLID, int BX, int BY>
-__global__ __launch_bounds__(256, 3) void k_fused(Box bx, const typename P::S* __restrict__ fs,
+__global__ __launch_bounds__(256, sizeof(typename P::R) == 8 ? 2 : 3) void k_fused(Box bx, const typename P::S* __restrict__ fs,
                                                    typename P::S* __restrict__ fd,
                                                    const typename P::R* __restrict__ psi,
                                                    const uint32_t* __restrict__ owner,
@@ -166,13 +166,37 @@ __global__ __launch_bounds__(256, 3) void k_fused(Box bx, const typename P::S* _
             f1[i] = P::ld(at(fs + (size_t)(Q + i) * N, nb), R(wq(i)) * ref1);
         }
     }
-    for (int e = threadIdx.x; e < 3 * TP; e += 256) {
-        const int lz = e / TP, r = e - lz * TP, yy = r / TX, xx = r - yy * TX;
-        const int gx = wrapc_any(x0 - 1 + xx, nx), gy = wrapc_any(y0 - 1 + yy, ny), gz = wrapc_any(z - 1 + lz, nz);
-        const uint32_t m = (uint32_t)(gx + nx * (gy + ny * gz));
-        s_psi[0][e] = psi[m];
-        s_psi[1][e] = psi[N + m];
-        if (SOLID) s_own[e] = owner[m];
+    // halo tile: every load of this thread issued before any is waited for
+    constexpr int NE = (3 * TP + 255) / 256;
+    R t0[NE], t1[NE];
+    uint32_t to[NE];
+#pragma unroll
+    for (int k = 0; k < NE; k++) {
+        const int e = threadIdx.x + 256 * k;
+        if (e < 3 * TP) {
+            const int lz = e / TP, r = e - lz * TP, yy = r / TX, xx = r - yy * TX;
+            // periodic wrap; positions past a ragged edge (only read by
+            // inactive threads) are clamped into the box
+            int gx = x0 - 1 + xx, gy = y0 - 1 + yy;
+            gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
+            gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
+            gx = gx < nx ? gx : 0;
+            gy = gy < ny ? gy : 0;
+            const int gz = wrapc(z - 1 + lz, nz);
+            const uint32_t m = (uint32_t)(gx + nx * (gy + ny * gz));
+            t0[k] = psi[m];
+            t1[k] = psi[N + m];
+            if (SOLID) to[k] = owner[m];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NE; k++) {
+        const int e = threadIdx.x + 256 * k;
+        if (e < 3 * TP) {
+            s_psi[0][e] = t0[k];
+            s_psi[1][e] = t1[k];
+            if (SOLID) s_own[e] = to[k];
+        }
     }
     __syncthreads();
     if (!fluid) return;
@@ -206,10 +230,11 @@ __global__ __launch_bounds__(256, 3) void k_fused(Box bx, const typename P::S* _
         }
     } else {
         // Every fluid lane takes the general path (one store path per wave).
-        // U_n of the first particle each lane links to: the wave visits its
-        // distinct first particles one at a time, reading each one's centre
-        // and velocities with wave-uniform loads. Links to a further particle
-        // of the same node (rare) read it per lane. Walls do not move (C = 0).
+        // U_n of the first two particles each lane links to: the wave visits
+        // the distinct particles among them one at a time, reading each one's
+        // centre and velocities with wave-uniform loads. Links to a third
+        // particle of the same node (rare) read it per lane. Walls do not
+        // move (C = 0).
         uint32_t on[Q];
         uint32_t p1 = OWN_FLUID;
 #pragma unroll
@@ -217,22 +242,37 @@ __global__ __launch_bounds__(256, 3) void k_fused(Box bx, const typename P::S* _
             on[i] = s_own[LBE_LS(i)];
             p1 = (p1 == OWN_FLUID && on[i] < OWN_WALL) ? on[i] : p1;
         }
+        uint32_t p2 = OWN_FLUID;
+#pragma unroll
+        for (int i = 1; i < Q; i++) p2 = (p2 == OWN_FLUID && on[i] < OWN_WALL && on[i] != p1) ? on[i] : p2;
+        double Ux2 = 0.0, Uy2 = 0.0, Uz2 = 0.0;
+        bool need2 = p2 < OWN_WALL;
         double Ux1 = 0.0, Uy1 = 0.0, Uz1 = 0.0;
         bool need = p1 < OWN_WALL;
         while (true) {
-            const unsigned long long m = __ballot(need);
+            const unsigned long long m = __ballot(need || need2);
             if (m == 0ull) break;
-            const uint32_t q = __builtin_amdgcn_readfirstlane(__shfl(p1, __ffsll(m) - 1, 64));
+            const int lead = __ffsll(m) - 1;
+            const uint32_t q = __builtin_amdgcn_readfirstlane(__shfl(need ? p1 : p2, lead, 64));
             const double qX = part[PX * cap + q], qY = part[PY * cap + q], qZ = part[PZ * cap + q];
             const double qVx = part[VX * cap + q], qVy = part[VY * cap + q], qVz = part[VZ * cap + q];
             const double qWx = part[WX * cap + q], qWy = part[WY * cap + q], qWz = part[WZ * cap + q];
+            const double rx = minimg((double)x - qX, nx), ry = minimg((double)y - qY, ny),
+                         rz = minimg((double)z - qZ, nz);
+            const double ux = qVx + (qWy * rz - qWz * ry);
+            const double uy = qVy + (qWz * rx - qWx * rz);
+            const double uz = qVz + (qWx * ry - qWy * rx);
             if (need && p1 == q) {
-                const double rx = minimg((double)x - qX, nx), ry = minimg((double)y - qY, ny),
-                             rz = minimg((double)z - qZ, nz);
-                Ux1 = qVx + (qWy * rz - qWz * ry);
-                Uy1 = qVy + (qWz * rx - qWx * rz);
-                Uz1 = qVz + (qWx * ry - qWy * rx);
+                Ux1 = ux;
+                Uy1 = uy;
+                Uz1 = uz;
                 need = false;
+            }
+            if (need2 && p2 == q) {
+                Ux2 = ux;
+                Uy2 = uy;
+                Uz2 = uz;
+                need2 = false;
             }
         }
         // one store per direction: the push to (i, n + c_i) for a fluid
@@ -243,8 +283,8 @@ __global__ __launch_bounds__(256, 3) void k_fused(Box bx, const typename P::S* _
             const bool sol = (o != OWN_FLUID);
             R C0 = R(0), C1 = R(0);
             if (o < OWN_WALL) {
-                double Ux = Ux1, Uy = Uy1, Uz = Uz1;
-                if (o != p1) {
+                double Ux = o == p1 ? Ux1 : Ux2, Uy = o == p1 ? Uy1 : Uy2, Uz = o == p1 ? Uz1 : Uz2;
+                if (o != p1 && o != p2) {
                     const double rx = minimg((double)x - part[PX * cap + o], nx);
                     const double ry = minimg((double)y - part[PY * cap + o], ny);
                     const double rz = minimg((double)z - part[PZ * cap + o], nz);
@@ -311,13 +351,28 @@ __global__ __launch_bounds__(NXT * ROWS, NXT * ROWS == 256 ? (sizeof(typename P:
         f0[i] = P::ld(at(fs + (size_t)i * N, nb), R(wq(i)) * ref0);
         f1[i] = P::ld(at(fs + (size_t)(Q + i) * N, nb), R(wq(i)) * ref1);
     }
-    for (int e = t; e < LR * NXT; e += NT) {
-        const int lrow = e / NXT, xx = e - lrow * NXT;
-        const int dz = lrow / (ROWS + 2) - 1, ry = lrow % (ROWS + 2) - 1;
-        const int gy = wrapc(y0 + ry, ny), gz = wrapc(z + dz, nz);
-        const uint32_t m = (uint32_t)(xx + nx * (gy + ny * gz));
-        s_psi[0][e] = psi[m];
-        s_psi[1][e] = psi[N + m];
+    // halo rows: every load of this thread issued before any is waited for
+    constexpr int NE = (LR * NXT + NT - 1) / NT;
+    R t0[NE], t1[NE];
+#pragma unroll
+    for (int k = 0; k < NE; k++) {
+        const int e = t + NT * k;
+        if (e < LR * NXT) {
+            const int lrow = e / NXT, xx = e - lrow * NXT;
+            const int dz = lrow / (ROWS + 2) - 1, ry = lrow % (ROWS + 2) - 1;
+            const int gy = wrapc(y0 + ry, ny), gz = wrapc(z + dz, nz);
+            const uint32_t m = (uint32_t)(xx + nx * (gy + ny * gz));
+            t0[k] = psi[m];
+            t1[k] = psi[N + m];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NE; k++) {
+        const int e = t + NT * k;
+        if (e < LR * NXT) {
+            s_psi[0][e] = t0[k];
+            s_psi[1][e] = t1[k];
+        }
     }
     __syncthreads();
 
