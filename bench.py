@@ -117,6 +117,57 @@ def measured_traffic(workload: str, prec: str):
     return rec.get("bytes_per_launch")
 
 
+def run_batch(steps, warmup):
+    """The 64-system interface ensemble (FP32 fluid, FP64 particles): batched
+    (one launch per phase over all systems, two-step HIP graphs, tuned tile
+    shape) against the same systems stepped one after another."""
+    import torch
+
+    from paper_1109_3277_amd import workloads as W
+    from paper_1109_3277_amd.binding import Batch, Lattice
+
+    systems = W.ensemble_systems()
+    n_nodes = sum(s.N for s in systems)
+    b = Batch([{"dims": s.dims, "tau": s.tau, "g_br": s.g_br, "psi_kind": s.psi_kind,
+                "max_particles": s.n_particles, "max_radius": s.max_radius} for s in systems], "fp32")
+    for k, s in enumerate(systems):
+        b[k].init_fields(s.rho_a, s.rho_b)
+        b[k].add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
+    bx = b.tune()
+    b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step_async(steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    b.step(0)
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    # one by one: every system on its own handle, all created first
+    lone = []
+    for s in systems:
+        g = Lattice(s.dims, s.tau, s.g_br, s.psi_kind, "fp32", max_particles=s.n_particles, max_radius=s.max_radius)
+        g.init_fields(s.rho_a, s.rho_b)
+        g.add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
+        g.step(warmup)
+        lone.append(g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in lone:
+        g.step_async(steps)
+    torch.cuda.synchronize()
+    t_lone = time.perf_counter() - t0
+    for g in lone:
+        g.step(0)
+    del lone
+    torch.cuda.empty_cache()
+    return {"systems": len(systems), "nodes": n_nodes, "steps": steps, "tile_width": bx,
+            "mlups_batched": round(n_nodes * steps / t_batch / 1e6, 1),
+            "mlups_one_by_one": round(n_nodes * steps / t_lone / 1e6, 1),
+            "speedup": round(t_lone / t_batch, 3), "precision": "fp32 fluid, fp64 particles"}
+
+
 def cpu_baseline(s, steps):
     import oracle
 
@@ -186,6 +237,12 @@ def main():
                 forms[f"spinodal128_{prec}"] = {"mlups": round(r["mlups"], 1),
                                                 "fused_roofline_frac": roofline_of(sp, prec, r, None)["frac"]}
 
+    batch = None
+    if not args.no_forms:
+        log("timing the 64-system batch")
+        batch = run_batch(args.steps, args.warmup)
+        log(f"  batch {batch}")
+
     cpu = None
     if not args.no_cpu:
         log(f"timing the CPU oracle ({args.cpu_steps} steps)")
@@ -207,6 +264,7 @@ def main():
         "phases_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in main_res["prof"].items()},
         "cpu_baseline": cpu,
         "forms": forms,
+        "batch": batch,
     }
     print(json.dumps(rec), flush=True)
 

@@ -162,8 +162,47 @@ int lb_profile_read(lb_handle* h, double* ms, int64_t* launches);
  * scaled against a transfer of known size. Not part of the method. */
 int lb_probe_copy(void* dev_dst, const void* dev_src, size_t bytes, void* hip_stream);
 
-/* Message of the last failed call on h (or of the last failed lb_create when
- * h is NULL); valid until the next call on the same handle. */
+/* ---- Batches: many independent periodic systems advanced together.
+ * The method per system is unchanged (same equations, same arithmetic: a
+ * system stepped in a batch ends bit for bit where a lone handle with the
+ * same parameters and inputs ends). Each kernel phase is one launch over all
+ * systems, and the step sequence runs as a HIP graph of two steps on the
+ * batch's own stream (ordered after and before the creation stream with
+ * events), so many small systems fill the GPU and launch cost is paid once
+ * per graph. All systems share one precision; dims, tau, g_br, psi_kind and
+ * particle capacity may differ per system. */
+
+/* Workspace bytes for nsys systems with parameters per_sys[0..nsys-1] (0 if
+ * any is invalid or the precisions differ). */
+size_t lb_batch_workspace_bytes(int32_t nsys, const lb_params* per_sys);
+
+/* Create a batch handle over one caller-owned workspace. The systems start
+ * empty: initialise each through its system handle. *out is NULL on failure. */
+int lb_batch_create(int32_t nsys, const lb_params* per_sys, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                    lb_handle** out);
+
+/* Number of systems of a batch handle (or a negative error code). */
+int lb_batch_size(const lb_handle* batch);
+
+/* The handle of system `sys`, owned by the batch (valid until the batch is
+ * destroyed; lb_destroy on it is a no-op). It takes every per-system call:
+ * lb_init_fields, lb_add_ellipsoids, lb_read_fields, lb_read_particles,
+ * lb_stats, lb_set_body_accel, lb_save_state / lb_load_state. lb_step on it
+ * returns LB_ESTATE: systems advance only with lb_step / lb_step_async on the
+ * batch handle, which every system must have fields for. Per-system calls on
+ * the batch handle itself return LB_ESTATE. */
+int lb_batch_system(lb_handle* batch, int32_t sys, lb_handle** out);
+
+/* Autotune the fused kernel's tile shape (64 x 4 or 32 x 8 nodes per block)
+ * for this batch by timing both on the current state (the timed launches only
+ * write the scratch population copy; the state does not change). Writes the
+ * chosen tile width (64 or 32) to *tile_width if not NULL. Results do not
+ * depend on the choice. Requires fields on every system. */
+int lb_batch_tune(lb_handle* batch, int32_t* tile_width);
+
+/* Message of the last failed call on h (or of the last failed lb_create or
+ * lb_batch_create when h is NULL); valid until the next call on the same
+ * handle. */
 const char* lb_last_error(const lb_handle* h);
 
 #ifdef __cplusplus

@@ -20,7 +20,8 @@ EXPORTED = [
     "lb_workspace_bytes", "lb_create", "lb_destroy", "lb_init_fields", "lb_add_ellipsoids", "lb_step",
     "lb_step_async", "lb_read_fields", "lb_num_particles", "lb_read_particles", "lb_stats",
     "lb_set_body_accel", "lb_state_bytes", "lb_save_state", "lb_load_state", "lb_last_error",
-    "lb_profile_enable", "lb_profile_read", "lb_probe_copy",
+    "lb_profile_enable", "lb_profile_read", "lb_probe_copy", "lb_batch_workspace_bytes", "lb_batch_create",
+    "lb_batch_size", "lb_batch_system", "lb_batch_tune",
 ]
 PHASES = ["density", "shell", "fused", "forces", "bodies", "raster", "killfill"]
 
@@ -73,6 +74,12 @@ def load_library():
     L.lb_profile_enable.argtypes = [vp, C.c_int]
     L.lb_profile_read.argtypes = [vp, dp, C.POINTER(C.c_int64)]
     L.lb_probe_copy.argtypes = [vp, vp, C.c_size_t, vp]
+    L.lb_batch_workspace_bytes.restype = C.c_size_t
+    L.lb_batch_workspace_bytes.argtypes = [C.c_int32, pp]
+    L.lb_batch_create.argtypes = [C.c_int32, pp, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.lb_batch_size.argtypes = [vp]
+    L.lb_batch_system.argtypes = [vp, C.c_int32, C.POINTER(vp)]
+    L.lb_batch_tune.argtypes = [vp, ip]
     _lib = L
     return L
 
@@ -104,10 +111,18 @@ class Lattice:
     """One periodic two-component system on the GPU (fields [z][y][x])."""
 
     def __init__(self, dims, tau, g_br, psi_kind=1, precision="fp64", max_particles=0, max_radius=0.0,
-                 device="cuda"):
+                 device="cuda", _borrowed=None):
         import torch
 
         L = load_library()
+        if _borrowed is not None:  # a system of a Batch: handle owned by the batch
+            owner, h, params = _borrowed
+            self._batch, self._h, self.params = owner, h, params
+            self.dims = (params.nx, params.ny, params.nz)
+            self.N = params.nx * params.ny * params.nz
+            self._borrowed = True
+            return
+        self._borrowed = False
         self.params = make_params(dims, tau, g_br, psi_kind, precision, max_particles, max_radius)
         self.dims = tuple(int(v) for v in dims)
         self.N = self.dims[0] * self.dims[1] * self.dims[2]
@@ -131,9 +146,9 @@ class Lattice:
             raise LBError(rc, load_library().lb_last_error(self._h).decode())
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and not getattr(self, "_borrowed", False):
             load_library().lb_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         try:
@@ -212,6 +227,72 @@ class Lattice:
     def load_state(self, data: bytes):
         buf = C.create_string_buffer(data, len(data))
         self._check(load_library().lb_load_state(self._h, buf, len(data)))
+
+
+class Batch:
+    """Independent periodic systems advanced together (one launch per phase
+    over all systems, steps replayed as a HIP graph). `params` is a list of
+    dicts with the Lattice arguments dims, tau, g_br and optionally psi_kind,
+    max_particles, max_radius; all systems share `precision`."""
+
+    def __init__(self, params, precision="fp64", device="cuda"):
+        import torch
+
+        L = load_library()
+        plist = [make_params(p["dims"], p["tau"], p["g_br"], p.get("psi_kind", 1), precision,
+                             p.get("max_particles", 0), p.get("max_radius", 0.0)) for p in params]
+        arr = (lb_params * len(plist))(*plist)
+        nbytes = L.lb_batch_workspace_bytes(len(plist), arr)
+        if nbytes == 0:
+            raise LBError(LB_EINVAL, "invalid batch parameters")
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        self._ws_ptr = (self._ws.data_ptr() + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self._ws.device)
+        h = C.c_void_p()
+        rc = L.lb_batch_create(len(plist), arr, C.c_void_p(self._ws_ptr), nbytes, C.c_void_p(self.stream.cuda_stream),
+                               C.byref(h))
+        if rc != 0:
+            raise LBError(rc, L.lb_last_error(None).decode())
+        self._h = h
+        self.systems = []
+        for k, prm in enumerate(plist):
+            sh = C.c_void_p()
+            self._check(L.lb_batch_system(self._h, k, C.byref(sh)))
+            self.systems.append(Lattice(None, None, None, _borrowed=(self, sh, prm)))
+
+    def _check(self, rc):
+        if rc != 0:
+            raise LBError(rc, load_library().lb_last_error(self._h).decode())
+
+    def __len__(self):
+        return len(self.systems)
+
+    def __getitem__(self, k) -> Lattice:
+        return self.systems[k]
+
+    def step(self, n=1):
+        self._check(load_library().lb_step(self._h, int(n)))
+
+    def step_async(self, n=1):
+        self._check(load_library().lb_step_async(self._h, int(n)))
+
+    def tune(self) -> int:
+        bx = C.c_int32(0)
+        self._check(load_library().lb_batch_tune(self._h, C.byref(bx)))
+        return int(bx.value)
+
+    def close(self):
+        for s in getattr(self, "systems", []):
+            s._h = None
+        if getattr(self, "_h", None):
+            load_library().lb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def probe_copy(dst, src, stream=None):

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbe.so")
-SOURCES = ["lbe_fluid.hip", "lbe_particles.hip", "lbe_runtime.hip"]
+SOURCES = ["lbe_fluid.hip", "lbe_particles.hip", "lbe_runtime.hip", "lbe_batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

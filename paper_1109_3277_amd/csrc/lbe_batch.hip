@@ -1,0 +1,408 @@
+// Batches of independent periodic systems advanced together: one launch per
+// phase covers every system (work items name the system and its local block),
+// and the step sequence runs as a captured HIP graph on the batch's own
+// stream. Each system keeps its own buffers, parameters and particles, and
+// its arithmetic is exactly that of a single-system run: a batch changes the
+// launch shape, never the result.
+#include <math.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "lbe_internal.h"
+
+namespace lbe {
+
+struct BatchState {
+    std::vector<lb_handle*> subs;
+    int precision = LB_FP64;
+    SysDev* d_sys = nullptr;
+    WorkItem* d_items[BI_COUNT] = {};
+    size_t cap_items[BI_COUNT] = {};
+    std::vector<SysDev> h_sys;
+    std::vector<WorkItem> h_items[BI_COUNT];
+    BatchLaunch bl;
+    bool dirty = true;
+    int bx = 64;      // fused tile width in use
+    int parity = 0;   // index of the current population and owner copies, shared by all systems
+    hipStream_t own = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+void tiles_for(const lb_params& p, int bx, int& tx, int& ty) {
+    const int by = 256 / bx;
+    tx = (p.nx + bx - 1) / bx;
+    ty = (p.ny + by - 1) / by;
+}
+
+// Most work items a system can ever need, per kind.
+void item_capacity(const lb_params& p, size_t cap[BI_COUNT]) {
+    const size_t N = (size_t)p.nx * p.ny * p.nz;
+    int tx, ty;
+    size_t tiles = 0;
+    for (int bx : {64, 32}) {
+        tiles_for(p, bx, tx, ty);
+        tiles = std::max(tiles, (size_t)tx * ty * p.nz);
+    }
+    const size_t np = (size_t)std::max(p.max_particles, 0);
+    const double rmax = p.max_particles > 0 ? p.max_radius : 0.5;
+    cap[BI_NODE] = (N + 255) / 256;
+    cap[BI_TILE] = tiles;
+    cap[BI_SLABR] = np * (size_t)make_slab(raster_extent(p.nx, p.ny, p.nz, rmax)).nslab;
+    cap[BI_SLABK] = np * (size_t)make_slab(killfill_extent(p.nx, p.ny, p.nz, rmax)).nslab;
+    cap[BI_PART] = np;
+}
+
+struct BatchLayout {
+    size_t sys = 0;
+    size_t items[BI_COUNT] = {};
+    size_t cap[BI_COUNT] = {};
+    std::vector<size_t> sub;  // workspace bytes of each system
+    size_t total = 0;
+};
+
+bool batch_layout(int nsys, const lb_params* prm, BatchLayout& L, std::string* why) {
+    if (nsys <= 0) {
+        *why = "a batch needs at least one system";
+        return false;
+    }
+    if (!prm) {
+        *why = "per-system parameters are NULL";
+        return false;
+    }
+    L.sub.resize(nsys);
+    for (int s = 0; s < nsys; s++) {
+        std::string w;
+        if (!params_ok(&prm[s], &w)) {
+            *why = "system " + std::to_string(s) + ": " + w;
+            return false;
+        }
+        if (prm[s].precision != prm[0].precision) {
+            *why = "all systems of a batch share one precision";
+            return false;
+        }
+        size_t c[BI_COUNT];
+        item_capacity(prm[s], c);
+        for (int k = 0; k < BI_COUNT; k++) L.cap[k] += c[k];
+        L.sub[s] = layout_of(&prm[s]).total;
+    }
+    for (int k = 0; k < BI_COUNT; k++) {
+        if (L.cap[k] > (size_t)INT32_MAX) {
+            *why = "batch too large for one launch";
+            return false;
+        }
+        L.items[k] = align_up(std::max<size_t>(L.cap[k], 1) * sizeof(WorkItem));
+    }
+    L.sys = align_up((size_t)nsys * sizeof(SysDev));
+    L.total = L.sys;
+    for (int k = 0; k < BI_COUNT; k++) L.total += L.items[k];
+    for (int s = 0; s < nsys; s++) L.total += L.sub[s];
+    return true;
+}
+
+void drop_graphs(BatchState* B) {
+    for (int k = 0; k < 2; k++) {
+        if (B->exec[k]) (void)hipGraphExecDestroy(B->exec[k]);
+        if (B->graph[k]) (void)hipGraphDestroy(B->graph[k]);
+        B->exec[k] = nullptr;
+        B->graph[k] = nullptr;
+    }
+}
+
+// Rebuild the device descriptors and work lists from the systems' state.
+int refresh(lb_handle* h) {
+    BatchState* B = h->batch;
+    const int nsys = (int)B->subs.size();
+    B->h_sys.resize(nsys);
+    for (int k = 0; k < BI_COUNT; k++) B->h_items[k].clear();
+    for (int s = 0; s < nsys; s++) {
+        lb_handle* q = B->subs[s];
+        SysDev& d = B->h_sys[s];
+        d.box = q->box;
+        d.f[0] = q->b.f[0];
+        d.f[1] = q->b.f[1];
+        d.psi = q->b.psi;
+        d.rho = q->b.rho;
+        d.owner[0] = q->b.owner[0];
+        d.owner[1] = q->b.owner[1];
+        d.part = q->b.part;
+        d.slist = q->b.slist;
+        d.scount = q->b.scount;
+        d.kpart = q->b.kpart;
+        d.counters = q->b.counters;
+        d.health = q->b.health;
+        d.cap = q->cap;
+        d.np = q->np;
+        tiles_for(q->prm, B->bx, d.tiles_x, d.tiles_y);
+        d.sr = slab_raster(q);
+        d.sk = slab_killfill(q);
+        const int nnode = (int)((q->box.N + 255) / 256);
+        const int ntile = d.tiles_x * d.tiles_y * q->box.nz;
+        for (int i = 0; i < nnode; i++) B->h_items[BI_NODE].push_back({s, i});
+        for (int i = 0; i < ntile; i++) B->h_items[BI_TILE].push_back({s, i});
+        for (int i = 0; i < q->np * d.sr.nslab; i++) B->h_items[BI_SLABR].push_back({s, i});
+        for (int i = 0; i < q->np * d.sk.nslab; i++) B->h_items[BI_SLABK].push_back({s, i});
+        for (int i = 0; i < q->np; i++) B->h_items[BI_PART].push_back({s, i});
+    }
+    for (int k = 0; k < BI_COUNT; k++)
+        if (B->h_items[k].size() > B->cap_items[k]) return fail(h, LB_EINVAL, "batch work list exceeds its capacity");
+    LBE_HIP_OR_FAIL(h, hipMemcpyAsync(B->d_sys, B->h_sys.data(), nsys * sizeof(SysDev), hipMemcpyHostToDevice, h->stream));
+    for (int k = 0; k < BI_COUNT; k++) {
+        if (!B->h_items[k].empty())
+            LBE_HIP_OR_FAIL(h, hipMemcpyAsync(B->d_items[k], B->h_items[k].data(),
+                                              B->h_items[k].size() * sizeof(WorkItem), hipMemcpyHostToDevice,
+                                              h->stream));
+        B->bl.items[k] = B->d_items[k];
+        B->bl.n[k] = (int)B->h_items[k].size();
+    }
+    B->bl.sys = B->d_sys;
+    B->bl.bx = B->bx;
+    LBE_HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    drop_graphs(B);
+    B->dirty = false;
+    return LB_OK;
+}
+
+// One step of every system, parity c (populations and owner maps at index c).
+hipError_t enqueue_batch_step(BatchState* B, hipStream_t st, int c) {
+    const BatchLaunch& bl = B->bl;
+    const int prec = B->precision;
+    hipError_t e;
+    if ((e = launch_batch_density(bl, prec, st, c, c)) != hipSuccess) return e;
+    if ((e = launch_batch_shell(bl, prec, st, c)) != hipSuccess) return e;
+    if ((e = launch_batch_fused(bl, prec, st, c, c)) != hipSuccess) return e;
+    if ((e = launch_batch_forces(bl, prec, st, 1 - c)) != hipSuccess) return e;
+    if ((e = launch_batch_bodies(bl, st)) != hipSuccess) return e;
+    if ((e = launch_batch_clear_owner(bl, st, 1 - c)) != hipSuccess) return e;
+    if ((e = launch_batch_raster(bl, st, 1 - c)) != hipSuccess) return e;
+    return launch_batch_killfill(bl, prec, st, c, 1 - c);
+}
+
+// Graph of two steps starting at parity c (it ends at parity c again).
+int capture(lb_handle* h, int c) {
+    BatchState* B = h->batch;
+    LBE_HIP_OR_FAIL(h, hipStreamBeginCapture(B->own, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_batch_step(B, B->own, c);
+    if (e == hipSuccess) e = enqueue_batch_step(B, B->own, 1 - c);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(B->own, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(h, LB_EHIP, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(h, LB_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    B->graph[c] = g;
+    B->exec[c] = x;
+    return LB_OK;
+}
+
+int check_ready(lb_handle* h) {
+    BatchState* B = h->batch;
+    for (size_t s = 0; s < B->subs.size(); s++)
+        if (!B->subs[s]->inited)
+            return fail(h, LB_ESTATE, "system " + std::to_string(s) + " has no fields (lb_init_fields)");
+    if (B->dirty) return refresh(h);
+    return LB_OK;
+}
+
+}  // namespace
+
+int batch_step_async(lb_handle* h, int nsteps) {
+    BatchState* B = h->batch;
+    int rc = check_ready(h);
+    if (rc != LB_OK) return rc;
+    if (nsteps == 0) return LB_OK;
+    LBE_HIP_OR_FAIL(h, hipEventRecord(B->ev_in, h->stream));
+    LBE_HIP_OR_FAIL(h, hipStreamWaitEvent(B->own, B->ev_in, 0));
+    const int pairs = nsteps / 2;
+    if (pairs > 0) {
+        if (!B->exec[B->parity]) {
+            rc = capture(h, B->parity);
+            if (rc != LB_OK) return rc;
+        }
+        for (int k = 0; k < pairs; k++) LBE_HIP_OR_FAIL(h, hipGraphLaunch(B->exec[B->parity], B->own));
+    }
+    if (nsteps & 1) {
+        LBE_HIP_OR_FAIL(h, enqueue_batch_step(B, B->own, B->parity));
+        B->parity = 1 - B->parity;
+    }
+    for (lb_handle* q : B->subs) q->cur = q->ocur = B->parity;
+    LBE_HIP_OR_FAIL(h, hipEventRecord(B->ev_out, B->own));
+    LBE_HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, B->ev_out, 0));
+    return LB_OK;
+}
+
+int batch_health(lb_handle* h) {
+    BatchState* B = h->batch;
+    const int nsys = (int)B->subs.size();
+    std::vector<int> bad(nsys, 0);
+    for (int s = 0; s < nsys; s++)
+        LBE_HIP_OR_FAIL(h, hipMemcpyAsync(&bad[s], B->subs[s]->b.health, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    LBE_HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    for (int s = 0; s < nsys; s++) {
+        if (bad[s] & 2)
+            return fail(h, LB_EUNSTABLE,
+                        "system " + std::to_string(s) + ": a particle moved more than two lattice spacings in one step");
+        if (bad[s]) return fail(h, LB_EUNSTABLE, "system " + std::to_string(s) + ": NaN or negative density detected");
+    }
+    return LB_OK;
+}
+
+void batch_destroy(lb_handle* h) {
+    BatchState* B = h->batch;
+    if (!B) return;
+    if (B->own) (void)hipStreamSynchronize(B->own);
+    drop_graphs(B);
+    if (B->ev_in) (void)hipEventDestroy(B->ev_in);
+    if (B->ev_out) (void)hipEventDestroy(B->ev_out);
+    if (B->own) (void)hipStreamDestroy(B->own);
+    for (lb_handle* q : B->subs) {
+        for (hipEvent_t e : q->ev_pool) (void)hipEventDestroy(e);
+        delete q;
+    }
+    delete B;
+    h->batch = nullptr;
+}
+
+void batch_touch(lb_handle* sub) {
+    if (sub && sub->parent && sub->parent->batch) sub->parent->batch->dirty = true;
+}
+
+}  // namespace lbe
+
+using namespace lbe;
+
+extern "C" {
+
+size_t lb_batch_workspace_bytes(int32_t nsys, const lb_params* per_sys) {
+    BatchLayout L;
+    std::string why;
+    if (!batch_layout(nsys, per_sys, L, &why)) return 0;
+    return L.total;
+}
+
+int lb_batch_create(int32_t nsys, const lb_params* per_sys, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                    lb_handle** out) {
+    if (!out) return fail(nullptr, LB_EINVAL, "out is NULL");
+    *out = nullptr;
+    BatchLayout L;
+    std::string why;
+    if (!batch_layout(nsys, per_sys, L, &why)) return fail(nullptr, LB_EINVAL, why);
+    if (!dev_ws) return fail(nullptr, LB_EINVAL, "workspace is NULL");
+    if (ws_bytes < L.total)
+        return fail(nullptr, LB_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+    if (((uintptr_t)dev_ws) % kAlign != 0) return fail(nullptr, LB_EINVAL, "workspace must be 256-byte aligned");
+    lb_handle* h = new lb_handle();
+    h->prm = per_sys[0];
+    h->stream = (hipStream_t)hip_stream;
+    h->ws = (char*)dev_ws;
+    h->ws_bytes = ws_bytes;
+    h->batch = new BatchState();
+    BatchState* B = h->batch;
+    B->precision = per_sys[0].precision;
+    char* p = (char*)dev_ws;
+    B->d_sys = (SysDev*)p;
+    p += L.sys;
+    for (int k = 0; k < BI_COUNT; k++) {
+        B->d_items[k] = (WorkItem*)p;
+        B->cap_items[k] = L.cap[k];
+        p += L.items[k];
+    }
+    // default tile: 64 x 4 when every system is at least 64 wide
+    B->bx = 64;
+    for (int s = 0; s < nsys; s++)
+        if (per_sys[s].nx < 64) B->bx = 32;
+    int rc = LB_OK;
+    for (int s = 0; s < nsys && rc == LB_OK; s++) {
+        lb_handle* q = new lb_handle();
+        q->parent = h;
+        rc = setup_handle(q, &per_sys[s], p, L.sub[s], h->stream);
+        p += L.sub[s];
+        if (rc != LB_OK) {
+            delete q;
+            break;
+        }
+        B->subs.push_back(q);
+    }
+    if (rc == LB_OK && hipStreamCreateWithFlags(&B->own, hipStreamNonBlocking) != hipSuccess)
+        rc = fail(nullptr, LB_EHIP, "stream creation failed");
+    if (rc == LB_OK && (hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming) != hipSuccess ||
+                        hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming) != hipSuccess))
+        rc = fail(nullptr, LB_EHIP, "event creation failed");
+    if (rc != LB_OK) {
+        batch_destroy(h);
+        delete h;
+        return rc;
+    }
+    h->inited = true;
+    *out = h;
+    return LB_OK;
+}
+
+int lb_batch_size(const lb_handle* h) {
+    if (!h || !h->batch) return LB_EINVAL;
+    return (int)h->batch->subs.size();
+}
+
+int lb_batch_system(lb_handle* h, int32_t sys, lb_handle** out) {
+    if (!h || !out) return LB_EINVAL;
+    *out = nullptr;
+    if (!h->batch) return fail(h, LB_EINVAL, "not a batch handle");
+    if (sys < 0 || sys >= (int)h->batch->subs.size()) return fail(h, LB_EINVAL, "system index out of range");
+    *out = h->batch->subs[sys];
+    return LB_OK;
+}
+
+int lb_batch_tune(lb_handle* h, int32_t* tile_width) {
+    if (!h) return LB_EINVAL;
+    if (!h->batch) return fail(h, LB_EINVAL, "not a batch handle");
+    BatchState* B = h->batch;
+    int rc = check_ready(h);
+    if (rc != LB_OK) return rc;
+    // the fused launch only writes the next population copy, which the next
+    // step rewrites whole: timing it leaves the state untouched
+    const int c = B->parity;
+    hipEvent_t e0, e1;
+    LBE_HIP_OR_FAIL(h, hipEventCreate(&e0));
+    LBE_HIP_OR_FAIL(h, hipEventCreate(&e1));
+    float best = 0.0f;
+    int best_bx = B->bx;
+    for (int bx : {64, 32}) {
+        B->bx = bx;
+        rc = refresh(h);
+        if (rc != LB_OK) break;
+        LBE_HIP_OR_FAIL(h, launch_batch_density(B->bl, B->precision, h->stream, c, c));
+        LBE_HIP_OR_FAIL(h, launch_batch_shell(B->bl, B->precision, h->stream, c));
+        LBE_HIP_OR_FAIL(h, launch_batch_fused(B->bl, B->precision, h->stream, c, c));
+        LBE_HIP_OR_FAIL(h, hipEventRecord(e0, h->stream));
+        for (int k = 0; k < 3; k++) LBE_HIP_OR_FAIL(h, launch_batch_fused(B->bl, B->precision, h->stream, c, c));
+        LBE_HIP_OR_FAIL(h, hipEventRecord(e1, h->stream));
+        LBE_HIP_OR_FAIL(h, hipEventSynchronize(e1));
+        float ms = 0.0f;
+        LBE_HIP_OR_FAIL(h, hipEventElapsedTime(&ms, e0, e1));
+        if (best == 0.0f || ms < best) {
+            best = ms;
+            best_bx = bx;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != LB_OK) return rc;
+    B->bx = best_bx;
+    rc = refresh(h);
+    if (rc != LB_OK) return rc;
+    if (tile_width) *tile_width = best_bx;
+    return LB_OK;
+}
+
+}  // extern "C"

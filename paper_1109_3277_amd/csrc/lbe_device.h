@@ -160,10 +160,11 @@ struct Tiles {
 };
 
 // Launch geometry of the per-particle kernels: one thread per node of a
-// particle's bounding box. grid = (particles, ext z-slices, tiles per slice),
-// flat one-wave blocks of B = 64 threads covering the ext x ext nodes of a
-// slice in `tiles` pieces. Each block owns one partial-sum slot
-// s = slice * tiles + tile, nslab slots per particle.
+// particle's bounding box. One-wave blocks of B = 64 threads; block (slice,
+// tile) covers part of the ext x ext nodes of z-slice `slice`. A single
+// system launches grid = (particles, ext, tiles); a batch flattens
+// (particle, slice, tile) into its work items. Each block owns one
+// partial-sum slot s = slice * tiles + tile, nslab slots per particle.
 struct Slab {
     int ext;
     int B;
@@ -173,14 +174,40 @@ struct Slab {
 
 // Node (ix, iy, iz) of the box this thread covers; false if none or outside
 // the particle's own extent sz.
-__device__ inline bool slab_node(const Slab& sl, const int sz[3], int& ix, int& iy, int& iz) {
-    const int t = blockIdx.z * sl.B + threadIdx.x;
-    iz = blockIdx.y;
+__device__ inline bool slab_node(const Slab& sl, int slice, int tile, const int sz[3], int& ix, int& iy, int& iz) {
+    const int t = tile * sl.B + threadIdx.x;
+    iz = slice;
     if (t >= sl.ext * sl.ext) return false;
     ix = t % sl.ext;
     iy = t / sl.ext;
     return ix < sz[0] && iy < sz[1] && iz < sz[2];
 }
+
+// One system as the batched kernels see it: its box, its buffers (both
+// population and owner copies; the launch names the current ones), its
+// particle table and its launch geometry.
+struct SysDev {
+    Box box;
+    void* f[2];
+    void* psi;
+    void* rho;
+    uint32_t* owner[2];
+    double* part;
+    uint2* slist;
+    int* scount;
+    double* kpart;
+    double* counters;
+    int* health;
+    int cap, np;
+    int tiles_x, tiles_y;
+    Slab sr, sk;  // raster and kill/fill slabs
+};
+
+// A batched launch: block b works on item items[b] = (system, local block).
+struct WorkItem {
+    int sys;
+    int local;
+};
 
 // Deterministic block sum of 6 doubles (every thread of the block calls it;
 // blockDim.x is a multiple of 64). The result is valid in thread 0.

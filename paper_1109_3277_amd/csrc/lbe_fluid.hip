@@ -33,12 +33,12 @@ __device__ inline R feq_i(int i, R rho, R ux, R uy, R uz, R uu) {
 // Psi^c(n) of Eq. (3) (what the force stencil reads) and, when the shell fill
 // needs it, as rho^c(n); health flag on NaN / rho < 0.
 template <class P, bool SOLID>
-__global__ __launch_bounds__(256) void k_density(Box bx, const typename P::S* __restrict__ f,
-                                                 typename P::R* __restrict__ psi, typename P::R* __restrict__ rho,
-                                                 const uint32_t* __restrict__ owner, int* __restrict__ health) {
+__device__ inline void density_body(const Box& bx, const typename P::S* __restrict__ f,
+                                    typename P::R* __restrict__ psi, typename P::R* __restrict__ rho,
+                                    const uint32_t* __restrict__ owner, int* __restrict__ health, int blk) {
     using R = typename P::R;
     const uint32_t N = (uint32_t)bx.N;
-    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t n = (uint32_t)blk * 256u + threadIdx.x;
     if (n >= N) return;
     if (SOLID && owner[n] != OWN_FLUID) return;
     const uint32_t nb = n * (uint32_t)sizeof(typename P::S);
@@ -56,6 +56,23 @@ __global__ __launch_bounds__(256) void k_density(Box bx, const typename P::S* __
         rho[N + n] = r1;
     }
     if (!(r0 >= R(0)) || !(r1 >= R(0))) atomicOr(health, 1);
+}
+template <class P, bool SOLID>
+__global__ __launch_bounds__(256) void k_density(Box bx, const typename P::S* __restrict__ f,
+                                                 typename P::R* __restrict__ psi, typename P::R* __restrict__ rho,
+                                                 const uint32_t* __restrict__ owner, int* __restrict__ health) {
+    density_body<P, SOLID>(bx, f, psi, rho, owner, health, blockIdx.x);
+}
+// Batched: item = (system, block of 256 nodes); populations copy `c`, owner
+// copy `o`; rho is written where the system keeps it (particles present).
+template <class P>
+__global__ __launch_bounds__(256) void k_density_batch(const SysDev* __restrict__ sd,
+                                                       const WorkItem* __restrict__ items, int c, int o) {
+    const WorkItem w = items[blockIdx.x];
+    const SysDev& d = sd[w.sys];
+    typename P::R* rho = (d.np > 0 && d.box.psi_kind != 0) ? (typename P::R*)d.rho : nullptr;
+    density_body<P, true>(d.box, (const typename P::S*)d.f[c], (typename P::R*)d.psi, rho, d.owner[o], d.health,
+                          w.local);
 }
 
 // ---------------------------------------------------------------- S3-S6
@@ -127,12 +144,9 @@ __device__ inline void collide_node(const Box& bx, typename P::R (&f0)[Q], typen
 // Tile kernel (any box): BX x BY nodes of one xy-plane per 256-thread block,
 // Psi and owner codes of the tile and its one-node halo staged in LDS.
 template <class P, bool SOLID, int BX, int BY>
-__global__ __launch_bounds__(256, sizeof(typename P::R) == 8 ? 2 : 3) void k_fused(Box bx, const typename P::S* __restrict__ fs,
-                                                   typename P::S* __restrict__ fd,
-                                                   const typename P::R* __restrict__ psi,
-                                                   const uint32_t* __restrict__ owner,
-                                                   const double* __restrict__ part, int cap, int tiles_x,
-                                                   int tiles_y) {
+__device__ inline void fused_body(const Box& bx, const typename P::S* __restrict__ fs, typename P::S* __restrict__ fd,
+                                  const typename P::R* __restrict__ psi, const uint32_t* __restrict__ owner,
+                                  const double* __restrict__ part, int cap, int tiles_x, int tiles_y, int tile) {
     using R = typename P::R;
     using S = typename P::S;
     static_assert(BX * BY == 256, "one node per thread");
@@ -142,7 +156,6 @@ __global__ __launch_bounds__(256, sizeof(typename P::R) == 8 ? 2 : 3) void k_fus
 
     const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
     const uint32_t N = (uint32_t)bx.N;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int txy = tiles_x * tiles_y;
     const int z = tile / txy;
     const int rem = tile - z * txy;
@@ -308,6 +321,23 @@ __global__ __launch_bounds__(256, sizeof(typename P::R) == 8 ? 2 : 3) void k_fus
 #undef LBE_NB
 #undef LBE_SEL
 #undef LBE_LS
+}
+template <class P, bool SOLID, int BX, int BY>
+__global__ __launch_bounds__(256, sizeof(typename P::R) == 8 ? 2 : 3) void k_fused(
+    Box bx, const typename P::S* __restrict__ fs, typename P::S* __restrict__ fd, const typename P::R* __restrict__ psi,
+    const uint32_t* __restrict__ owner, const double* __restrict__ part, int cap, int tiles_x, int tiles_y) {
+    fused_body<P, SOLID, BX, BY>(bx, fs, fd, psi, owner, part, cap, tiles_x, tiles_y,
+                                 xcd_remap(blockIdx.x, gridDim.x));
+}
+// Batched: item = (system, tile); every system has solids. Items of one
+// system are contiguous, so the XCD remap keeps neighbouring tiles together.
+template <class P, int BX, int BY>
+__global__ __launch_bounds__(256, sizeof(typename P::R) == 8 ? 2 : 3) void k_fused_batch(
+    const SysDev* __restrict__ sd, const WorkItem* __restrict__ items, int c, int o) {
+    const WorkItem w = items[xcd_remap(blockIdx.x, gridDim.x)];
+    const SysDev& d = sd[w.sys];
+    fused_body<P, true, BX, BY>(d.box, (const typename P::S*)d.f[c], (typename P::S*)d.f[1 - c],
+                                (const typename P::R*)d.psi, d.owner[o], d.part, d.cap, d.tiles_x, d.tiles_y, w.local);
 }
 
 // Row kernel for boxes without solids (nx a multiple of 64): a block holds
@@ -587,6 +617,14 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
         p[k] = v;
 }
+// Batched clear of owner copy `o`: item = (system, block of 256 nodes).
+__global__ __launch_bounds__(256) void k_clear_owner_batch(const SysDev* __restrict__ sd,
+                                                           const WorkItem* __restrict__ items, int o) {
+    const WorkItem w = items[blockIdx.x];
+    const SysDev& d = sd[w.sys];
+    const int64_t n = (int64_t)w.local * 256 + threadIdx.x;
+    if (n < d.box.N) d.owner[o][n] = OWN_FLUID;
+}
 __global__ void k_fill_f64(double* __restrict__ p, double v, int64_t n) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
         p[k] = v;
@@ -737,5 +775,36 @@ size_t elem_bytes(int precision) {
     }
 }
 size_t rho_elem_bytes(int precision) { return precision == LB_FP64 ? 8 : 4; }
+
+// ---------------------------------------------------------------- batched launchers
+
+hipError_t launch_batch_density(const BatchLaunch& bl, int precision, hipStream_t st, int c, int o) {
+    if (bl.n[BI_NODE] == 0) return hipSuccess;
+    LBE_DISPATCH(precision, hipLaunchKernelGGL(k_density_batch<P>, dim3(bl.n[BI_NODE]), dim3(256), 0, st, bl.sys,
+                                               bl.items[BI_NODE], c, o));
+    return hipGetLastError();
+}
+
+template <class P>
+static void launch_batch_fused_t(const BatchLaunch& bl, hipStream_t st, int c, int o) {
+    if (bl.bx == 64)
+        hipLaunchKernelGGL((k_fused_batch<P, 64, 4>), dim3(bl.n[BI_TILE]), dim3(256), 0, st, bl.sys, bl.items[BI_TILE],
+                           c, o);
+    else
+        hipLaunchKernelGGL((k_fused_batch<P, 32, 8>), dim3(bl.n[BI_TILE]), dim3(256), 0, st, bl.sys, bl.items[BI_TILE],
+                           c, o);
+}
+
+hipError_t launch_batch_fused(const BatchLaunch& bl, int precision, hipStream_t st, int c, int o) {
+    if (bl.n[BI_TILE] == 0) return hipSuccess;
+    LBE_DISPATCH(precision, (launch_batch_fused_t<P>(bl, st, c, o)));
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_clear_owner(const BatchLaunch& bl, hipStream_t st, int o) {
+    if (bl.n[BI_NODE] == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_clear_owner_batch, dim3(bl.n[BI_NODE]), dim3(256), 0, st, bl.sys, bl.items[BI_NODE], o);
+    return hipGetLastError();
+}
 
 }  // namespace lbe

@@ -29,6 +29,17 @@ struct Buffers {
 
 constexpr int kRedBlocks = 1024;       // fixed grid of the deterministic reductions
 
+struct BatchState;
+
+// Work-item lists of a batched launch, one per kind of block.
+enum BatchItems { BI_NODE = 0, BI_TILE, BI_SLABR, BI_SLABK, BI_PART, BI_COUNT };
+struct BatchLaunch {
+    const SysDev* sys = nullptr;
+    const WorkItem* items[BI_COUNT] = {};
+    int n[BI_COUNT] = {};
+    int bx = 64;  // fused tile width: 64 (64x4) or 32 (32x8)
+};
+
 }  // namespace lbe
 
 struct lb_handle {
@@ -51,9 +62,51 @@ struct lb_handle {
     std::vector<hipEvent_t> ev_pool;      // created lazily, reused
     std::vector<std::pair<int, int>> ev_marks;  // (phase, index of start event); end = start + 1
     size_t ev_used = 0;
+    // batches: a batch handle owns its systems' handles; a system handle
+    // points back at its batch
+    lb_handle* parent = nullptr;
+    lbe::BatchState* batch = nullptr;
 };
 
 namespace lbe {
+
+// Return LB_EHIP from the calling API function when a HIP call fails.
+#define LBE_HIP_OR_FAIL(h, call)                                                                           \
+    do {                                                                                                   \
+        hipError_t e_ = (call);                                                                            \
+        if (e_ != hipSuccess)                                                                              \
+            return ::lbe::fail((h), LB_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));           \
+    } while (0)
+
+// Shared host helpers (lbe_runtime.hip).
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+struct Layout {
+    size_t f, psi, rho, owner, part, slist, scount, kpart, red, counters, health, total;
+};
+bool params_ok(const lb_params* p, std::string* why);
+Layout layout_of(const lb_params* p);
+int fail(lb_handle* h, int code, const std::string& msg);
+// Carve one system's buffers from ws and clear them (synchronizes stream).
+int setup_handle(lb_handle* h, const lb_params* prm, char* ws, size_t ws_bytes, hipStream_t stream);
+
+// Batches (lbe_batch.hip).
+int batch_step_async(lb_handle* h, int nsteps);
+int batch_health(lb_handle* h);
+void batch_destroy(lb_handle* h);
+void batch_touch(lb_handle* sub);  // a system changed: its batch refreshes its tables before stepping
+
+// Batched launchers (one launch per phase over every system).
+hipError_t launch_batch_density(const BatchLaunch& bl, int precision, hipStream_t st, int c, int o);
+hipError_t launch_batch_fused(const BatchLaunch& bl, int precision, hipStream_t st, int c, int o);
+hipError_t launch_batch_clear_owner(const BatchLaunch& bl, hipStream_t st, int o);
+hipError_t launch_batch_shell(const BatchLaunch& bl, int precision, hipStream_t st, int o);
+hipError_t launch_batch_forces(const BatchLaunch& bl, int precision, hipStream_t st, int d);
+hipError_t launch_batch_bodies(const BatchLaunch& bl, hipStream_t st);
+hipError_t launch_batch_raster(const BatchLaunch& bl, hipStream_t st, int o);
+hipError_t launch_batch_killfill(const BatchLaunch& bl, int precision, hipStream_t st, int oo, int fd);
+Slab slab_raster(const lb_handle* h);
+Slab slab_killfill(const lb_handle* h);
 
 size_t elem_bytes(int precision);
 size_t rho_elem_bytes(int precision);

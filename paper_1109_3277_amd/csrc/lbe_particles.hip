@@ -59,12 +59,11 @@ __device__ inline int64_t node_index(const Box& bx, int x, int y, int z) {
 // ---------------------------------------------------------------- raster
 // Rasterise particles [first, first + gridDim.x) into owner with atomicMin:
 // the smallest index owns a node covered by several particles.
-__global__ void k_raster(Box bx, const double* __restrict__ part, int cap, uint32_t* __restrict__ owner, int first,
-                         Slab sl) {
-    const int p = first + blockIdx.x;
+__device__ inline void raster_body(const Box& bx, const double* __restrict__ part, int cap,
+                                   uint32_t* __restrict__ owner, const Slab& sl, int p, int slice, int tile) {
     int lo[3], sz[3], ix, iy, iz;
     if (!particle_box(bx, part, cap, p, lo, sz)) return;  // invalid state: touch nothing
-    if (!slab_node(sl, sz, ix, iy, iz)) return;
+    if (!slab_node(sl, slice, tile, sz, ix, iy, iz)) return;
     const int x = wrapc_any(lo[0] + ix, bx.nx), y = wrapc_any(lo[1] + iy, bx.ny), z = wrapc_any(lo[2] + iz, bx.nz);
     const double X[3] = {part[PX * cap + p], part[PY * cap + p], part[PZ * cap + p]};
     double R[3][3];
@@ -77,6 +76,18 @@ __global__ void k_raster(Box bx, const double* __restrict__ part, int cap, uint3
     if (owner[n] == OWN_WALL) return;
     atomicMin(owner + n, (uint32_t)p);
 }
+__global__ void k_raster(Box bx, const double* __restrict__ part, int cap, uint32_t* __restrict__ owner, int first,
+                         Slab sl) {
+    raster_body(bx, part, cap, owner, sl, first + blockIdx.x, blockIdx.y, blockIdx.z);
+}
+// Batched: item = (system, particle * nslab + slice * tiles + tile) into the
+// owner copy `o` of every system.
+__global__ void k_raster_batch(const SysDev* __restrict__ sd, const WorkItem* __restrict__ items, int o) {
+    const WorkItem w = items[blockIdx.x];
+    const SysDev& d = sd[w.sys];
+    const int p = w.local / d.sr.nslab, r = w.local - p * d.sr.nslab;
+    raster_body(d.box, d.part, d.cap, d.owner[o], d.sr, p, r / d.sr.tiles, r % d.sr.tiles);
+}
 
 // ---------------------------------------------------------------- S2
 // Eq. (10): a node of particle p with fluid neighbours (over the 18 links)
@@ -87,16 +98,16 @@ __global__ void k_raster(Box bx, const double* __restrict__ part, int cap, uint3
 // (node, mask) with bit i set when the node's neighbour at -c_i is fluid, in
 // this block's own segment of 64 entries (lane order) plus its count.
 template <class R>
-__global__ void k_shell(Box bx, R* __restrict__ psi, const R* __restrict__ rho, const uint32_t* __restrict__ owner,
-                        const double* __restrict__ part, int cap, Slab sl, uint2* __restrict__ slist,
-                        int* __restrict__ scount) {
-    const int p = blockIdx.x;
+__device__ inline void shell_body(const Box& bx, R* __restrict__ psi, const R* __restrict__ rho,
+                                  const uint32_t* __restrict__ owner, const double* __restrict__ part, int cap,
+                                  const Slab& sl, uint2* __restrict__ slist, int* __restrict__ scount, int p, int slice,
+                                  int tile) {
     const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
     const int64_t N = bx.N;
     int lo[3], sz[3], ix, iy, iz;
     uint32_t mask = 0u;
     int64_t n = 0;
-    if (particle_box(bx, part, cap, p, lo, sz) && slab_node(sl, sz, ix, iy, iz)) {
+    if (particle_box(bx, part, cap, p, lo, sz) && slab_node(sl, slice, tile, sz, ix, iy, iz)) {
         const int x = wrapc_any(lo[0] + ix, nx), y = wrapc_any(lo[1] + iy, ny), z = wrapc_any(lo[2] + iz, nz);
         n = node_index(bx, x, y, z);
         if (owner[n] == (uint32_t)p) {
@@ -135,12 +146,26 @@ __global__ void k_shell(Box bx, R* __restrict__ psi, const R* __restrict__ rho, 
         }
     }
     const unsigned long long bal = __ballot(mask != 0u);
-    const size_t seg = (size_t)p * sl.nslab + blockIdx.y * sl.tiles + blockIdx.z;
+    const size_t seg = (size_t)p * sl.nslab + slice * sl.tiles + tile;
     if (mask != 0u) {
         const int pos = __popcll(bal & ((1ull << threadIdx.x) - 1ull));
         slist[seg * 64 + pos] = make_uint2((uint32_t)n, mask);
     }
     if (threadIdx.x == 0) scount[seg] = __popcll(bal);
+}
+template <class R>
+__global__ void k_shell(Box bx, R* __restrict__ psi, const R* __restrict__ rho, const uint32_t* __restrict__ owner,
+                        const double* __restrict__ part, int cap, Slab sl, uint2* __restrict__ slist,
+                        int* __restrict__ scount) {
+    shell_body<R>(bx, psi, rho, owner, part, cap, sl, slist, scount, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+template <class R>
+__global__ void k_shell_batch(const SysDev* __restrict__ sd, const WorkItem* __restrict__ items, int o) {
+    const WorkItem w = items[blockIdx.x];
+    const SysDev& d = sd[w.sys];
+    const int p = w.local / d.sr.nslab, r = w.local - p * d.sr.nslab;
+    shell_body<R>(d.box, (R*)d.psi, (const R*)d.rho, d.owner[o], d.part, d.cap, d.sr, d.slist, d.scount, p,
+                  r / d.sr.tiles, r % d.sr.tiles);
 }
 
 // ---------------------------------------------------------------- S6 forces
@@ -156,14 +181,13 @@ __global__ void k_shell(Box bx, R* __restrict__ psi, const R* __restrict__ rho, 
 // e mod 256, entries and links in increasing order, then a fixed block sum,
 // so the result is reproducible bit for bit.
 template <class P>
-__global__ __launch_bounds__(256) void k_linkforce(Box bx, const typename P::S* __restrict__ f,
-                                                   const typename P::R* __restrict__ dens,
-                                                   double* __restrict__ part, int cap, int nslab,
-                                                   const uint2* __restrict__ slist, const int* __restrict__ scount) {
+__device__ inline void linkforce_body(const Box& bx, const typename P::S* __restrict__ f,
+                                      const typename P::R* __restrict__ dens, double* __restrict__ part, int cap,
+                                      int nslab, const uint2* __restrict__ slist, const int* __restrict__ scount,
+                                      int p) {
     using R = typename P::R;
     __shared__ int s_pre[257];
     __shared__ int s_wsum[4];
-    const int p = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t N = bx.N;
     const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
@@ -251,6 +275,23 @@ __global__ __launch_bounds__(256) void k_linkforce(Box bx, const typename P::S* 
         for (int k = 0; k < 6; k++) part[fld[k] * cap + p] = tot[k];
     }
 }
+template <class P>
+__global__ __launch_bounds__(256) void k_linkforce(Box bx, const typename P::S* __restrict__ f,
+                                                   const typename P::R* __restrict__ dens,
+                                                   double* __restrict__ part, int cap, int nslab,
+                                                   const uint2* __restrict__ slist, const int* __restrict__ scount) {
+    linkforce_body<P>(bx, f, dens, part, cap, nslab, slist, scount, blockIdx.x);
+}
+// Batched: item = (system, particle); `d` is the post-streaming population copy.
+template <class P>
+__global__ __launch_bounds__(256) void k_linkforce_batch(const SysDev* __restrict__ sd,
+                                                         const WorkItem* __restrict__ items, int d_) {
+    const WorkItem w = items[blockIdx.x];
+    const SysDev& d = sd[w.sys];
+    const void* dens = d.box.psi_kind == 0 ? d.psi : d.rho;
+    linkforce_body<P>(d.box, (const typename P::S*)d.f[d_], (const typename P::R*)dens, d.part, d.cap, d.sr.nslab,
+                      d.slist, d.scount, w.local);
+}
 
 // ---------------------------------------------------------------- S7
 // Newton-Euler update, dt = 1: F = F_links + J, T = T_links + H; V += F/M,
@@ -259,9 +300,8 @@ __global__ __launch_bounds__(256) void k_linkforce(Box bx, const typename P::S* 
 // J / H are the stored impulses plus the kill/fill slots. One wave per
 // particle: lane l sums slots l, l + 64, ... in order, then a fixed shuffle
 // tree; lane 0 updates the body.
-__global__ __launch_bounds__(64) void k_bodies(Box bx, double* __restrict__ part, int cap, int np,
-                                               const double* __restrict__ kpart, int nk) {
-    const int p = blockIdx.x;
+__device__ inline void bodies_body(const Box& bx, double* __restrict__ part, int cap,
+                                   const double* __restrict__ kpart, int nk, int p) {
     const int lane = threadIdx.x;
     double Jk[6] = {0, 0, 0, 0, 0, 0};
     for (int s = lane; s < nk; s += 64)
@@ -269,7 +309,7 @@ __global__ __launch_bounds__(64) void k_bodies(Box bx, double* __restrict__ part
 #pragma unroll
     for (int k = 0; k < 6; k++)
         for (int off = 32; off > 0; off >>= 1) Jk[k] += __shfl_down(Jk[k], off, 64);
-    if (lane != 0 || p >= np) return;
+    if (lane != 0) return;
     double* P = part;
 #define F_(k) P[(k) * cap + p]
     const double Fl[6] = {F_(FX), F_(FY), F_(FZ), F_(TX), F_(TY), F_(TZ)};
@@ -347,6 +387,16 @@ __global__ __launch_bounds__(64) void k_bodies(Box bx, double* __restrict__ part
     F_(QZ) = nzq / nn;
 #undef F_
 }
+__global__ __launch_bounds__(64) void k_bodies(Box bx, double* __restrict__ part, int cap,
+                                               const double* __restrict__ kpart, int nk) {
+    bodies_body(bx, part, cap, kpart, nk, blockIdx.x);
+}
+__global__ __launch_bounds__(64) void k_bodies_batch(const SysDev* __restrict__ sd,
+                                                     const WorkItem* __restrict__ items) {
+    const WorkItem w = items[blockIdx.x];
+    const SysDev& d = sd[w.sys];
+    bodies_body(d.box, d.part, d.cap, d.kpart, d.sk.nslab, w.local);
+}
 
 // Pending kill/fill impulses: add the partial slots into the particle's J, H
 // and clear the slots (before the slot layout changes or the state is saved).
@@ -381,12 +431,13 @@ __device__ inline R feq_p(int i, R rho, R ux, R uy, R uz) {
 // Impulses go to the block's partial slot; a move the union box cannot cover
 // raises health bit 2.
 template <class P>
-__global__ void k_killfill(Box bx, typename P::S* __restrict__ f, const uint32_t* __restrict__ own_old,
-                           const uint32_t* __restrict__ own_new, const double* __restrict__ part, int cap, Slab sl,
-                           double* __restrict__ kpart, double* __restrict__ counters, int* __restrict__ health) {
+__device__ inline void killfill_body(const Box& bx, typename P::S* __restrict__ f,
+                                     const uint32_t* __restrict__ own_old, const uint32_t* __restrict__ own_new,
+                                     const double* __restrict__ part, int cap, const Slab& sl,
+                                     double* __restrict__ kpart, double* __restrict__ counters,
+                                     int* __restrict__ health, int p, int slice, int tile) {
     using R = typename P::R;
     const int64_t N = bx.N;
-    const int p = blockIdx.x;
     const int Ls[3] = {bx.nx, bx.ny, bx.nz};
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int lo[3] = {0, 0, 0}, sz[3] = {0, 0, 0}, ix = 0, iy = 0, iz = 0;
@@ -405,9 +456,9 @@ __global__ void k_killfill(Box bx, typename P::S* __restrict__ f, const uint32_t
         const int b = max((int)floor(Xo[d] + rb), (int)floor(xn + rb));
         lo[d] = a;
         sz[d] = max(0, min(b - a + 1, Ls[d]));
-        if (sz[d] > sl.ext && threadIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) atomicOr(health, 2);
+        if (sz[d] > sl.ext && threadIdx.x == 0 && slice == 0 && tile == 0) atomicOr(health, 2);
     }
-    if (ok) ok = slab_node(sl, sz, ix, iy, iz);
+    if (ok) ok = slab_node(sl, slice, tile, sz, ix, iy, iz);
     if (ok) {
         const int x = wrapc_any(lo[0] + ix, Ls[0]), y = wrapc_any(lo[1] + iy, Ls[1]), z = wrapc_any(lo[2] + iz, Ls[2]);
         const int64_t n = node_index(bx, x, y, z);
@@ -484,9 +535,26 @@ __global__ void k_killfill(Box bx, typename P::S* __restrict__ f, const uint32_t
     double tot[6];
     block_sum6(acc, tot);
     if (threadIdx.x == 0) {
-        double* o = kpart + ((size_t)p * sl.nslab + blockIdx.y * sl.tiles + blockIdx.z) * 6;
+        double* o = kpart + ((size_t)p * sl.nslab + slice * sl.tiles + tile) * 6;
         for (int k = 0; k < 6; k++) o[k] = tot[k];
     }
+}
+template <class P>
+__global__ void k_killfill(Box bx, typename P::S* __restrict__ f, const uint32_t* __restrict__ own_old,
+                           const uint32_t* __restrict__ own_new, const double* __restrict__ part, int cap, Slab sl,
+                           double* __restrict__ kpart, double* __restrict__ counters, int* __restrict__ health) {
+    killfill_body<P>(bx, f, own_old, own_new, part, cap, sl, kpart, counters, health, blockIdx.x, blockIdx.y,
+                     blockIdx.z);
+}
+// Batched: item = (system, particle * nslab + slice * tiles + tile); owner
+// copy `oo` is the old map, 1 - oo the new one; populations copy `fd`.
+template <class P>
+__global__ void k_killfill_batch(const SysDev* __restrict__ sd, const WorkItem* __restrict__ items, int oo, int fd) {
+    const WorkItem w = items[blockIdx.x];
+    const SysDev& d = sd[w.sys];
+    const int p = w.local / d.sk.nslab, r = w.local - p * d.sk.nslab;
+    killfill_body<P>(d.box, (typename P::S*)d.f[fd], d.owner[oo], d.owner[1 - oo], d.part, d.cap, d.sk, d.kpart,
+                     d.counters, d.health, p, r / d.sk.tiles, r % d.sk.tiles);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -545,7 +613,7 @@ hipError_t launch_forces(lb_handle* h) {
 
 hipError_t launch_bodies(lb_handle* h) {
     if (h->np <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bodies, dim3(h->np), dim3(64), 0, h->stream, h->box, h->b.part, h->cap, h->np, h->b.kpart,
+    hipLaunchKernelGGL(k_bodies, dim3(h->np), dim3(64), 0, h->stream, h->box, h->b.part, h->cap, h->b.kpart,
                        slab_killfill(h).nslab);
     return hipGetLastError();
 }
@@ -592,6 +660,43 @@ hipError_t launch_killfill(lb_handle* h) {
                                h->b.part, h->cap, s, h->b.kpart, h->b.counters, h->b.health);
             break;
     }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- batched launchers
+
+hipError_t launch_batch_shell(const BatchLaunch& bl, int precision, hipStream_t st, int o) {
+    if (bl.n[BI_SLABR] == 0) return hipSuccess;
+    if (precision == LB_FP64)
+        hipLaunchKernelGGL(k_shell_batch<double>, dim3(bl.n[BI_SLABR]), dim3(64), 0, st, bl.sys, bl.items[BI_SLABR], o);
+    else
+        hipLaunchKernelGGL(k_shell_batch<float>, dim3(bl.n[BI_SLABR]), dim3(64), 0, st, bl.sys, bl.items[BI_SLABR], o);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_forces(const BatchLaunch& bl, int precision, hipStream_t st, int d) {
+    if (bl.n[BI_PART] == 0) return hipSuccess;
+    LBE_PDISPATCH(precision, hipLaunchKernelGGL(k_linkforce_batch<P>, dim3(bl.n[BI_PART]), dim3(256), 0, st, bl.sys,
+                                                bl.items[BI_PART], d));
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_bodies(const BatchLaunch& bl, hipStream_t st) {
+    if (bl.n[BI_PART] == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bodies_batch, dim3(bl.n[BI_PART]), dim3(64), 0, st, bl.sys, bl.items[BI_PART]);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_raster(const BatchLaunch& bl, hipStream_t st, int o) {
+    if (bl.n[BI_SLABR] == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_raster_batch, dim3(bl.n[BI_SLABR]), dim3(64), 0, st, bl.sys, bl.items[BI_SLABR], o);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_killfill(const BatchLaunch& bl, int precision, hipStream_t st, int oo, int fd) {
+    if (bl.n[BI_SLABK] == 0) return hipSuccess;
+    LBE_PDISPATCH(precision, hipLaunchKernelGGL(k_killfill_batch<P>, dim3(bl.n[BI_SLABK]), dim3(64), 0, st, bl.sys,
+                                                bl.items[BI_SLABK], oo, fd));
     return hipGetLastError();
 }
 

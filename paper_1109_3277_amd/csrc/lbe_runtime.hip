@@ -12,11 +12,10 @@
 using namespace lbe;
 
 namespace {
-
 thread_local std::string g_create_err;
+}  // namespace
 
-constexpr size_t kAlign = 256;
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+namespace lbe {
 
 int fail(lb_handle* h, int code, const std::string& msg) {
     if (h) h->err = msg;
@@ -24,11 +23,7 @@ int fail(lb_handle* h, int code, const std::string& msg) {
     return code;
 }
 
-#define LBE_HIP(h, call)                                                                        \
-    do {                                                                                        \
-        hipError_t e_ = (call);                                                                 \
-        if (e_ != hipSuccess) return fail((h), LB_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
-    } while (0)
+#define LBE_HIP(h, call) LBE_HIP_OR_FAIL(h, call)
 
 bool params_ok(const lb_params* p, std::string* why) {
     if (!p) { *why = "params is NULL"; return false; }
@@ -51,10 +46,6 @@ bool params_ok(const lb_params* p, std::string* why) {
     }
     return true;
 }
-
-struct Layout {
-    size_t f, psi, rho, owner, part, slist, scount, kpart, red, counters, health, total;
-};
 
 Layout layout_of(const lb_params* p) {
     const size_t N = (size_t)p->nx * p->ny * p->nz;
@@ -79,6 +70,58 @@ Layout layout_of(const lb_params* p) {
     return L;
 }
 
+int setup_handle(lb_handle* h, const lb_params* prm, char* ws, size_t ws_bytes, hipStream_t stream) {
+    const Layout L = layout_of(prm);
+    h->prm = *prm;
+    h->stream = stream;
+    h->ws = ws;
+    h->ws_bytes = ws_bytes;
+    h->cap = std::max(prm->max_particles, 1);
+    Box& b = h->box;
+    b.nx = prm->nx;
+    b.ny = prm->ny;
+    b.nz = prm->nz;
+    b.N = (int64_t)prm->nx * prm->ny * prm->nz;
+    b.tau = prm->tau;
+    b.omega = 1.0 / prm->tau;
+    b.g = prm->g_br;
+    b.psi_kind = prm->psi_kind;
+    b.ax = b.ay = b.az = 0.0;
+    b.rref[0] = b.rref[1] = 0.0;
+    b.rmean0[0] = b.rmean0[1] = 0.0;
+    char* p = h->ws;
+    h->b.f[0] = p; p += L.f;
+    h->b.f[1] = p; p += L.f;
+    h->b.psi = p; p += L.psi;
+    h->b.rho = L.rho ? p : nullptr; p += L.rho;
+    h->b.owner[0] = (uint32_t*)p; p += L.owner;
+    h->b.owner[1] = (uint32_t*)p; p += L.owner;
+    h->b.part = (double*)p; p += L.part;
+    h->b.slist = L.slist ? (uint2*)p : nullptr; p += L.slist;
+    h->b.scount = L.scount ? (int*)p : nullptr; p += L.scount;
+    h->b.kpart = (double*)p; p += L.kpart;
+    h->b.red = (double*)p; p += L.red;
+    h->b.counters = (double*)p; p += L.counters;
+    h->b.health = (int*)p; p += L.health;
+    int rc = LB_OK;
+    auto chk = [&](hipError_t e, const char* what) {
+        if (e != hipSuccess && rc == LB_OK) rc = fail(nullptr, LB_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    chk(launch_fill_u32(h, h->b.owner[0], OWN_FLUID, b.N), "clear owner");
+    chk(launch_fill_u32(h, h->b.owner[1], OWN_FLUID, b.N), "clear owner");
+    chk(launch_fill_f64(h, h->b.part, 0.0, (int64_t)NPFIELD * h->cap), "clear particles");
+    chk(launch_fill_f64(h, h->b.kpart, 0.0, (int64_t)(L.kpart / sizeof(double))), "clear impulse slots");
+    h->kpart_len = (int64_t)(L.kpart / sizeof(double));
+    chk(launch_fill_f64(h, h->b.counters, 0.0, 8), "clear counters");
+    chk(launch_fill_u32(h, (uint32_t*)h->b.health, 0u, 1), "clear health");
+    chk(hipStreamSynchronize(h->stream), "synchronize");
+    return rc;
+}
+
+}  // namespace lbe
+
+namespace {
+
 // Staging for host transfers: the population copy that is not current (its
 // contents are dead between steps). Large enough for 5N doubles in every form.
 void* staging(lb_handle* h) { return h->b.f[1 - h->cur]; }
@@ -99,6 +142,10 @@ hipError_t mark(lb_handle* h, int phase, bool start) {
     }
     return hipEventRecord(h->ev_pool[h->ev_used - 1], h->stream);
 }
+
+// Per-system calls on a batch handle are refused (they go to lb_batch_system).
+#define LBE_NOT_BATCH(h) \
+    if ((h)->batch) return fail((h), LB_ESTATE, "per-system call on a batch handle: use lb_batch_system")
 
 #define LBE_PHASE(h, ph, call)                  \
     do {                                        \
@@ -147,49 +194,7 @@ int lb_create(const lb_params* prm, void* dev_ws, size_t ws_bytes, void* hip_str
         return fail(nullptr, LB_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
     if (((uintptr_t)dev_ws) % kAlign != 0) return fail(nullptr, LB_EINVAL, "workspace must be 256-byte aligned");
     lb_handle* h = new lb_handle();
-    h->prm = *prm;
-    h->stream = (hipStream_t)hip_stream;
-    h->ws = (char*)dev_ws;
-    h->ws_bytes = ws_bytes;
-    h->cap = std::max(prm->max_particles, 1);
-    Box& b = h->box;
-    b.nx = prm->nx;
-    b.ny = prm->ny;
-    b.nz = prm->nz;
-    b.N = (int64_t)prm->nx * prm->ny * prm->nz;
-    b.tau = prm->tau;
-    b.omega = 1.0 / prm->tau;
-    b.g = prm->g_br;
-    b.psi_kind = prm->psi_kind;
-    b.ax = b.ay = b.az = 0.0;
-    b.rref[0] = b.rref[1] = 0.0;
-    b.rmean0[0] = b.rmean0[1] = 0.0;
-    char* p = h->ws;
-    h->b.f[0] = p; p += L.f;
-    h->b.f[1] = p; p += L.f;
-    h->b.psi = p; p += L.psi;
-    h->b.rho = L.rho ? p : nullptr; p += L.rho;
-    h->b.owner[0] = (uint32_t*)p; p += L.owner;
-    h->b.owner[1] = (uint32_t*)p; p += L.owner;
-    h->b.part = (double*)p; p += L.part;
-    h->b.slist = L.slist ? (uint2*)p : nullptr; p += L.slist;
-    h->b.scount = L.scount ? (int*)p : nullptr; p += L.scount;
-    h->b.kpart = (double*)p; p += L.kpart;
-    h->b.red = (double*)p; p += L.red;
-    h->b.counters = (double*)p; p += L.counters;
-    h->b.health = (int*)p; p += L.health;
-    int rc = LB_OK;
-    auto chk = [&](hipError_t e, const char* what) {
-        if (e != hipSuccess && rc == LB_OK) rc = fail(nullptr, LB_EHIP, std::string(what) + ": " + hipGetErrorString(e));
-    };
-    chk(launch_fill_u32(h, h->b.owner[0], OWN_FLUID, b.N), "clear owner");
-    chk(launch_fill_u32(h, h->b.owner[1], OWN_FLUID, b.N), "clear owner");
-    chk(launch_fill_f64(h, h->b.part, 0.0, (int64_t)NPFIELD * h->cap), "clear particles");
-    chk(launch_fill_f64(h, h->b.kpart, 0.0, (int64_t)(L.kpart / sizeof(double))), "clear impulse slots");
-    h->kpart_len = (int64_t)(L.kpart / sizeof(double));
-    chk(launch_fill_f64(h, h->b.counters, 0.0, 8), "clear counters");
-    chk(launch_fill_u32(h, (uint32_t*)h->b.health, 0u, 1), "clear health");
-    chk(hipStreamSynchronize(h->stream), "synchronize");
+    const int rc = setup_handle(h, prm, (char*)dev_ws, ws_bytes, (hipStream_t)hip_stream);
     if (rc != LB_OK) {
         delete h;
         return rc;
@@ -199,13 +204,15 @@ int lb_create(const lb_params* prm, void* dev_ws, size_t ws_bytes, void* hip_str
 }
 
 void lb_destroy(lb_handle* h) {
-    if (!h) return;
+    if (!h || h->parent) return;  // a batch's system handles go with the batch
+    if (h->batch) batch_destroy(h);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     delete h;
 }
 
 int lb_profile_enable(lb_handle* h, int on) {
     if (!h) return LB_EINVAL;
+    LBE_NOT_BATCH(h);
     if (on) {
         h->ev_marks.clear();
         h->ev_used = 0;
@@ -232,6 +239,7 @@ int lb_profile_read(lb_handle* h, double* ms, int64_t* launches) {
 
 int lb_init_fields(lb_handle* h, const double* rho_a, const double* rho_b, const double* u) {
     if (!h) return LB_EINVAL;
+    if (h->batch) return fail(h, LB_ESTATE, "initialise each system of a batch through lb_batch_system");
     if (!rho_a || !rho_b) return fail(h, LB_EINVAL, "rho_a and rho_b are required");
     const int64_t N = h->box.N;
     double s[2] = {0.0, 0.0};
@@ -251,12 +259,14 @@ int lb_init_fields(lb_handle* h, const double* rho_a, const double* rho_b, const
     LBE_HIP(h, launch_init(h, d_ra, d_rb, d_u));
     LBE_HIP(h, hipStreamSynchronize(h->stream));
     h->inited = true;
+    batch_touch(h);
     return LB_OK;
 }
 
 int lb_add_ellipsoids(lb_handle* h, int32_t n, const double* radii, const double* pos, const double* quat,
                       const double* delta_rho, const double* density) {
     if (!h) return LB_EINVAL;
+    if (h->batch) return fail(h, LB_ESTATE, "add particles to each system of a batch through lb_batch_system");
     if (!h->inited) return fail(h, LB_ESTATE, "lb_init_fields must come before lb_add_ellipsoids");
     if (n < 0) return fail(h, LB_EINVAL, "n must be >= 0");
     if (n == 0) return LB_OK;
@@ -323,13 +333,16 @@ int lb_add_ellipsoids(lb_handle* h, int32_t n, const double* radii, const double
     LBE_HIP(h, launch_raster(h, h->b.owner[h->ocur], first, n));
     LBE_HIP(h, launch_remove_covered(h));
     LBE_HIP(h, hipStreamSynchronize(h->stream));
+    batch_touch(h);
     return LB_OK;
 }
 
 int lb_step_async(lb_handle* h, int32_t nsteps) {
     if (!h) return LB_EINVAL;
-    if (!h->inited) return fail(h, LB_ESTATE, "lb_init_fields must come before lb_step");
     if (nsteps < 0) return fail(h, LB_EINVAL, "nsteps must be >= 0");
+    if (h->parent) return fail(h, LB_ESTATE, "a system of a batch advances only with its batch (step the batch handle)");
+    if (h->batch) return batch_step_async(h, nsteps);
+    if (!h->inited) return fail(h, LB_ESTATE, "lb_init_fields must come before lb_step");
     for (int s = 0; s < nsteps; s++) {
         int rc = enqueue_step(h);
         if (rc != LB_OK) return rc;
@@ -340,6 +353,7 @@ int lb_step_async(lb_handle* h, int32_t nsteps) {
 int lb_step(lb_handle* h, int32_t nsteps) {
     int rc = lb_step_async(h, nsteps);
     if (rc != LB_OK) return rc;
+    if (h->batch) return batch_health(h);
     int bad = 0;
     LBE_HIP(h, hipMemcpyAsync(&bad, h->b.health, sizeof(int), hipMemcpyDeviceToHost, h->stream));
     LBE_HIP(h, hipStreamSynchronize(h->stream));
@@ -350,6 +364,7 @@ int lb_step(lb_handle* h, int32_t nsteps) {
 
 int lb_read_fields(lb_handle* h, double* rho_a, double* rho_b, double* u, int32_t* owner) {
     if (!h) return LB_EINVAL;
+    LBE_NOT_BATCH(h);
     if (!h->inited) return fail(h, LB_ESTATE, "fields not initialised");
     const int64_t N = h->box.N;
     double* st = (double*)staging(h);
@@ -377,6 +392,7 @@ int lb_num_particles(const lb_handle* h) { return h ? h->np : LB_EINVAL; }
 int lb_read_particles(lb_handle* h, double* pos, double* quat, double* vel, double* omega, double* force,
                       double* torque) {
     if (!h) return LB_EINVAL;
+    LBE_NOT_BATCH(h);
     const int np = h->np;
     if (np == 0) return LB_OK;
     std::vector<double> t((size_t)NPFIELD * h->cap);
@@ -399,6 +415,7 @@ int lb_read_particles(lb_handle* h, double* pos, double* quat, double* vel, doub
 
 int lb_stats(lb_handle* h, double out[8]) {
     if (!h || !out) return LB_EINVAL;
+    LBE_NOT_BATCH(h);
     if (!h->inited) return fail(h, LB_ESTATE, "fields not initialised");
     LBE_HIP(h, launch_stats(h));
     double t[7], c[3];
@@ -418,11 +435,13 @@ int lb_stats(lb_handle* h, double out[8]) {
 
 int lb_set_body_accel(lb_handle* h, const double a[3]) {
     if (!h || !a) return LB_EINVAL;
+    LBE_NOT_BATCH(h);
     for (int d = 0; d < 3; d++)
         if (!isfinite(a[d])) return fail(h, LB_EINVAL, "non-finite acceleration");
     h->box.ax = a[0];
     h->box.ay = a[1];
     h->box.az = a[2];
+    batch_touch(h);
     return LB_OK;
 }
 
@@ -436,6 +455,7 @@ size_t lb_state_bytes(const lb_handle* h) {
 
 int lb_save_state(lb_handle* h, void* host_buf, size_t bytes) {
     if (!h || !host_buf) return LB_EINVAL;
+    LBE_NOT_BATCH(h);
     if (!h->inited) return fail(h, LB_ESTATE, "fields not initialised");
     if (bytes < lb_state_bytes(h)) return fail(h, LB_EINVAL, "buffer too small");
     LBE_HIP(h, launch_fold_impulses(h));
@@ -460,6 +480,7 @@ int lb_save_state(lb_handle* h, void* host_buf, size_t bytes) {
 
 int lb_load_state(lb_handle* h, const void* host_buf, size_t bytes) {
     if (!h || !host_buf) return LB_EINVAL;
+    LBE_NOT_BATCH(h);
     if (bytes < lb_state_bytes(h)) return fail(h, LB_EINVAL, "buffer too small");
     const size_t N = (size_t)h->box.N;
     const char* p = (const char*)host_buf;
@@ -497,6 +518,7 @@ int lb_load_state(lb_handle* h, const void* host_buf, size_t bytes) {
     h->rmax = hdr[5];
     h->has_solid = h->np > 0;
     h->inited = true;
+    batch_touch(h);
     return LB_OK;
 }
 

@@ -79,3 +79,27 @@ def test_null_handle_calls_are_rejected(lib):
     assert lib.lb_init_fields(None, None, None, None) == B.LB_EINVAL
     assert lib.lb_num_particles(None) == B.LB_EINVAL
     lib.lb_destroy(None)
+
+
+def test_batch_workspace_and_create_validate(lib):
+    from paper_1109_3277_amd import binding as B
+    a = B.make_params((32, 32, 64), 1.0, 0.08, precision="fp32", max_particles=1, max_radius=8.0)
+    b = B.make_params((40, 48, 96), 1.0, 0.08, precision="fp32", max_particles=1, max_radius=12.0)
+    arr = (B.lb_params * 2)(a, b)
+    n = lib.lb_batch_workspace_bytes(2, arr)
+    assert n >= lib.lb_workspace_bytes(C.byref(a)) + lib.lb_workspace_bytes(C.byref(b))
+    assert lib.lb_batch_workspace_bytes(0, arr) == 0
+    assert lib.lb_batch_workspace_bytes(2, None) == 0
+    mixed = (B.lb_params * 2)(a, B.make_params((32, 32, 64), 1.0, 0.08, precision="fp64"))
+    assert lib.lb_batch_workspace_bytes(2, mixed) == 0
+    bad = (B.lb_params * 2)(a, B.make_params((32, 32, 2), 1.0, 0.08, precision="fp32"))
+    assert lib.lb_batch_workspace_bytes(2, bad) == 0
+    h = C.c_void_p()
+    assert lib.lb_batch_create(2, arr, None, n, None, C.byref(h)) == B.LB_EINVAL
+    assert lib.lb_batch_create(2, arr, C.c_void_p(256), n - 1, None, C.byref(h)) == B.LB_ENOMEM
+    assert lib.lb_batch_create(2, arr, C.c_void_p(256 + 8), n, None, C.byref(h)) == B.LB_EINVAL
+    assert lib.lb_batch_create(2, mixed, C.c_void_p(256), n, None, C.byref(h)) == B.LB_EINVAL
+    assert b"precision" in lib.lb_last_error(None)
+    assert lib.lb_batch_size(None) == B.LB_EINVAL
+    assert lib.lb_batch_system(None, 0, C.byref(h)) == B.LB_EINVAL
+    assert lib.lb_batch_tune(None, None) == B.LB_EINVAL

@@ -1,0 +1,133 @@
+"""Batched systems (many independent periodic systems, one launch per phase,
+steps replayed as a HIP graph) against lone handles and the oracle."""
+import numpy as np
+import pytest
+
+from paper_1109_3277_amd import workloads as W
+from tests.parity_util import compare, log, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+FP64_GATE = 1e-12
+
+
+def _small_ensemble(k):
+    """The k smallest systems of the 64-system interface ensemble (uneven
+    dims, one tilted ellipsoid each)."""
+    ens = W.ensemble_systems()
+    ens.sort(key=lambda s: s.N)
+    return ens[:k]
+
+
+def _batch(systems, precision):
+    from paper_1109_3277_amd.binding import Batch
+
+    b = Batch([{"dims": s.dims, "tau": s.tau, "g_br": s.g_br, "psi_kind": s.psi_kind,
+                "max_particles": s.n_particles, "max_radius": s.max_radius} for s in systems], precision)
+    for k, s in enumerate(systems):
+        b[k].init_fields(s.rho_a, s.rho_b)
+        if s.n_particles:
+            b[k].add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
+    return b
+
+
+def _same(a, b):
+    """Bitwise equality of two handles' fields, owners and particles."""
+    fa, fb = a.read_fields(), b.read_fields()
+    for x, y in zip(fa, fb):
+        if not np.array_equal(x, y):
+            return False
+    pa, pb = a.read_particles(), b.read_particles()
+    return all(np.array_equal(pa[k], pb[k]) for k in pa)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_equals_lone_handles_bitwise(prec):
+    """Each system of a batch ends bit for bit where a lone handle ends; the
+    two-step graph is replayed several times with reads (eager work and
+    synchronisation) between replays, and an odd count takes the direct path."""
+    from paper_1109_3277_amd.binding import Lattice
+
+    systems = _small_ensemble(6)
+    log(f"case batch bitwise {prec}: dims {[s.dims for s in systems]}")
+    b = _batch(systems, prec)
+    lone = []
+    for s in systems:
+        g = Lattice(s.dims, s.tau, s.g_br, s.psi_kind, prec, max_particles=s.n_particles, max_radius=s.max_radius)
+        g.init_fields(s.rho_a, s.rho_b)
+        g.add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
+        lone.append(g)
+    done = 0
+    for n in (2, 4, 1, 6, 3):
+        b.step(n)
+        for g in lone:
+            g.step(n)
+        done += n
+        for k in range(len(systems)):
+            assert _same(b[k], lone[k]), f"system {k} differs after {done} steps"
+    log(f"  {len(systems)} systems equal after {done} steps")
+
+
+def test_batch_parity_vs_oracle_fp64():
+    """Three systems of different sizes, 100 batched steps, against the oracle."""
+    systems = _small_ensemble(3)
+    b = _batch(systems, "fp64")
+    b.step(100)
+    for k, s in enumerate(systems):
+        o = run_oracle(s, 100)
+        res = compare(o, b[k], s.dims)
+        log(f"  system {k} {s.dims}: {res}")
+        assert res["e_rho"] <= FP64_GATE and res["e_u"] <= FP64_GATE, res
+        assert res["owner_equal"] and res["n_fluid_equal"], res
+        assert res["e_pos"] <= 1e-12 and res["e_quat"] <= 1e-12, res
+        assert res["e_vel"] <= 1e-10 and res["e_omega"] <= 1e-10, res
+
+
+def test_batch_tune_keeps_state_and_results():
+    """The autotuner times both tile shapes without changing the state, and
+    the tuned batch still matches lone handles."""
+    from paper_1109_3277_amd.binding import Lattice
+
+    systems = _small_ensemble(4)
+    b = _batch(systems, "fp32")
+    b.step(3)
+    before = [b[k].read_fields() for k in range(len(systems))]
+    bx = b.tune()
+    assert bx in (32, 64)
+    for k in range(len(systems)):
+        after = b[k].read_fields()
+        assert all(np.array_equal(x, y) for x, y in zip(before[k], after))
+    b.step(5)
+    for k, s in enumerate(systems):
+        g = run_gpu(s, 8, "fp32")
+        assert _same(b[k], g), f"system {k} differs after tuning (tile width {bx})"
+
+
+def test_batch_misuse_is_refused():
+    from paper_1109_3277_amd.binding import LB_ESTATE, LBError, load_library
+
+    systems = _small_ensemble(2)
+    b = _batch(systems, "fp32")
+    L = load_library()
+    assert L.lb_step(b[0].handle, 1) == LB_ESTATE
+    assert L.lb_step_async(b[1].handle, 1) == LB_ESTATE
+    assert L.lb_read_fields(b._h, None, None, None, None) == LB_ESTATE
+    assert L.lb_batch_size(b._h) == 2
+    assert L.lb_batch_size(b[0].handle) < 0
+    L.lb_destroy(b[0].handle)  # no-op: owned by the batch
+    b.step(2)
+    b[0].read_fields()
+
+
+def test_full_ensemble_64_systems_equals_lone_handles():
+    """The full 64-system ensemble (FP32 fluid, FP64 particles), 20 batched
+    steps after tuning, against each system run alone."""
+    systems = W.ensemble_systems()
+    log(f"case ensemble 64: {sum(s.N for s in systems)} nodes")
+    b = _batch(systems, "fp32")
+    b.tune()
+    b.step(20)
+    for k, s in enumerate(systems):
+        g = run_gpu(s, 20, "fp32")
+        assert _same(b[k], g), f"system {k} {s.dims} differs"
+        del g
