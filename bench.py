@@ -168,6 +168,22 @@ def run_batch(steps, warmup):
             "speedup": round(t_lone / t_batch, 3), "precision": "fp32 fluid, fp64 particles"}
 
 
+def run_forms512(steps, warmup):
+    """The 512^3 domain with 41,802 ellipsoids in each precision form (ms per
+    step and MLUPS; errors against FP64 are checked by the test suite)."""
+    from paper_1109_3277_amd import workloads as W
+
+    s = W.mixed_system()
+    out = {}
+    for prec in ("fp64", "fp32", "fp16_dev", "bf16_dev"):
+        log(f"timing 512^3 {prec}")
+        r = run_gpu(s, prec, steps, warmup, profile=False)
+        out[prec] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 3)}
+    for prec in out:
+        out[prec]["speedup_vs_fp64"] = round(out[prec]["mlups"] / out["fp64"]["mlups"], 3)
+    return {"dims": list(s.dims), "n_particles": s.n_particles, "steps": steps, "forms": out}
+
+
 def cpu_baseline(s, steps):
     import oracle
 
@@ -237,8 +253,10 @@ def main():
                 forms[f"spinodal128_{prec}"] = {"mlups": round(r["mlups"], 1),
                                                 "fused_roofline_frac": roofline_of(sp, prec, r, None)["frac"]}
 
-    batch = None
+    batch = forms512 = None
     if not args.no_forms:
+        forms512 = run_forms512(50, 5)
+        log(f"  512^3 forms {forms512}")
         log("timing the 64-system batch")
         batch = run_batch(args.steps, args.warmup)
         log(f"  batch {batch}")
@@ -264,6 +282,7 @@ def main():
         "phases_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in main_res["prof"].items()},
         "cpu_baseline": cpu,
         "forms": forms,
+        "forms_512": forms512,
         "batch": batch,
     }
     print(json.dumps(rec), flush=True)

@@ -219,7 +219,12 @@ def bijel_system(n: int = 256, seed: int = 3, ratio: str = "50/50", phi: float =
 
 
 def mixed_system(n: int = 512, seed: int = 4, phi: float = 0.1, g_br: float = 0.08, tau: float = 1.0,
-                 dims=None) -> System:
+                 dims=None, density: float = 8.0) -> System:
+    """Large mixed-precision domain: noise-initialised 50/50 mixture with
+    ellipsoids of aspect ratio in [0.5, 2], R_perp = 4, colour in [-0.3, 0.3],
+    volume fraction phi. Particle density 8 (the thinnest bodies, R_par = 2,
+    run away under explicit momentum-exchange coupling when lighter than a
+    few times the fluid density 1.4)."""
     dims = (n, n, n) if dims is None else tuple(dims)
     ra, rb = uniform_fields(dims, seed, 0.7, 0.7, 0.01)
     N = int(np.prod(dims))
@@ -230,12 +235,14 @@ def mixed_system(n: int = 512, seed: int = 4, phi: float = 0.1, g_br: float = 0.
         return 4.0 * m, 4.0, r.uniform(-0.3, 0.3)
 
     radii, pos, quat, dr = place_particles(dims, rng, 0, shape, volume_target=phi * N, max_tries=10 ** 7)
-    return System("mixed", dims, tau, g_br, ra, rb, radii, pos, quat, dr, np.ones(len(dr)), seed=seed)
+    return System("mixed", dims, tau, g_br, ra, rb, radii, pos, quat, dr, np.full(len(dr), float(density)), seed=seed)
 
 
 def ensemble_systems(n_sys: int = 64, seed: int = 5, g_br: float = 0.08, tau: float = 1.0,
-                     max_side: int = 96) -> list:
-    """Uneven flat-interface systems with one ellipsoid each."""
+                     max_side: int = 96, density: float = 8.0) -> list:
+    """Uneven flat-interface systems with one ellipsoid each. Particle density
+    8: the thinnest bodies (R_par down to 0.75) run away under explicit
+    momentum-exchange coupling at density 1 (lighter than the fluid)."""
     rng = np.random.default_rng(seed)
     out = []
     for s in range(n_sys):
@@ -256,5 +263,5 @@ def ensemble_systems(n_sys: int = 64, seed: int = 5, g_br: float = 0.08, tau: fl
         pos = np.array([[nx / 2.0, ny / 2.0, nz / 2.0 - 0.5]])
         q = tilt_quaternion(theta, phi)[None, :]
         out.append(System(f"ensemble{s}", dims, tau, g_br, ra, rb, np.array([[rpar, rperp]]), pos, q,
-                          np.array([dr]), np.array([1.0]), seed=seed * 1000 + s))
+                          np.array([dr]), np.array([float(density)]), seed=seed * 1000 + s))
     return out
