@@ -88,6 +88,10 @@ def run_gpu(s, prec, steps, warmup, profile=True):
     g.step(0)  # health check of the timed steps
     sec = t1 - t0
     out = {"mlups": s.N * steps / sec / 1e6, "ms_per_step": 1e3 * sec / steps, "prof": prof, "stats": st}
+    if profile:  # one host readout of rho_a, rho_b, u and the owner map (PCIe-inclusive figure)
+        t2 = time.perf_counter()
+        g.read_fields()
+        out["readout_ms"] = 1e3 * (time.perf_counter() - t2)
     del g
     torch.cuda.empty_cache()
     return out
@@ -280,6 +284,9 @@ def main():
         "roofline": roof,
         "step_hbm_frac_alg": round(value * 1e6 * step_bytes_per_node(args.precision) / 1e9 / HBM_PEAK_GBS, 4),
         "phases_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in main_res["prof"].items()},
+        "host_readout_ms": round(main_res.get("readout_ms", 0.0), 1),
+        "mlups_with_one_readout": round(s.N * args.steps / (1e-3 * (main_res["ms_per_step"] * args.steps +
+                                                                     main_res.get("readout_ms", 0.0))) / 1e6, 1),
         "cpu_baseline": cpu,
         "forms": forms,
         "forms_512": forms512,
