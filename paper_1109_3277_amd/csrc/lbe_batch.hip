@@ -49,13 +49,9 @@ void item_capacity(const lb_params& p, size_t cap[BI_COUNT]) {
         tiles_for(p, bx, tx, ty);
         tiles = std::max(tiles, (size_t)tx * ty * p.nz);
     }
-    const size_t np = (size_t)std::max(p.max_particles, 0);
-    const double rmax = p.max_particles > 0 ? p.max_radius : 0.5;
     cap[BI_NODE] = (N + 255) / 256;
     cap[BI_TILE] = tiles;
-    cap[BI_SLABR] = np * (size_t)make_slab(raster_extent(p.nx, p.ny, p.nz, rmax)).nslab;
-    cap[BI_SLABK] = np * (size_t)make_slab(killfill_extent(p.nx, p.ny, p.nz, rmax)).nslab;
-    cap[BI_PART] = np;
+    cap[BI_PART] = (size_t)std::max(p.max_particles, 0);
 }
 
 struct BatchLayout {
@@ -139,14 +135,12 @@ int refresh(lb_handle* h) {
         d.cap = q->cap;
         d.np = q->np;
         tiles_for(q->prm, B->bx, d.tiles_x, d.tiles_y);
-        d.sr = slab_raster(q);
-        d.sk = slab_killfill(q);
+        d.nseg = surf_nseg(q);
+        d.kext = kill_ext(q);
         const int nnode = (int)((q->box.N + 255) / 256);
         const int ntile = d.tiles_x * d.tiles_y * q->box.nz;
         for (int i = 0; i < nnode; i++) B->h_items[BI_NODE].push_back({s, i});
         for (int i = 0; i < ntile; i++) B->h_items[BI_TILE].push_back({s, i});
-        for (int i = 0; i < q->np * d.sr.nslab; i++) B->h_items[BI_SLABR].push_back({s, i});
-        for (int i = 0; i < q->np * d.sk.nslab; i++) B->h_items[BI_SLABK].push_back({s, i});
         for (int i = 0; i < q->np; i++) B->h_items[BI_PART].push_back({s, i});
     }
     for (int k = 0; k < BI_COUNT; k++)

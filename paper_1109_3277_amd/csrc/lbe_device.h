@@ -159,28 +159,22 @@ struct Tiles {
     int BX, BY, tiles_x, tiles_y;
 };
 
-// Launch geometry of the per-particle kernels: one thread per node of a
-// particle's bounding box. One-wave blocks of B = 64 threads; block (slice,
-// tile) covers part of the ext x ext nodes of z-slice `slice`. A single
-// system launches grid = (particles, ext, tiles); a batch flattens
-// (particle, slice, tile) into its work items. Each block owns one
-// partial-sum slot s = slice * tiles + tile, nslab slots per particle.
-struct Slab {
-    int ext;
-    int B;
-    int tiles;
-    int nslab;
-};
+// Per-particle kernels run one block of kPB threads per particle, looping
+// over the nodes of the particle's box in chunks of kPB nodes. The surface
+// list of a particle is split into segments of 64 entries, one per (chunk,
+// wave); a box of edge at most `ext` needs surf_segments(ext) segments.
+constexpr int kPB = 256;
+__host__ __device__ inline int surf_segments(int ext) {
+    const int cells = ext * ext * ext;
+    return (kPB / 64) * ((cells + kPB - 1) / kPB);
+}
 
-// Node (ix, iy, iz) of the box this thread covers; false if none or outside
-// the particle's own extent sz.
-__device__ inline bool slab_node(const Slab& sl, int slice, int tile, const int sz[3], int& ix, int& iy, int& iz) {
-    const int t = tile * sl.B + threadIdx.x;
-    iz = slice;
-    if (t >= sl.ext * sl.ext) return false;
-    ix = t % sl.ext;
-    iy = t / sl.ext;
-    return ix < sz[0] && iy < sz[1] && iz < sz[2];
+// Node (ix, iy, iz) of box index t in a box of sz[0] x sz[1] x sz[2].
+__device__ inline void box_node(int t, const int sz[3], int& ix, int& iy, int& iz) {
+    ix = t % sz[0];
+    const int r = t / sz[0];
+    iy = r % sz[1];
+    iz = r / sz[1];
 }
 
 // One system as the batched kernels see it: its box, its buffers (both
@@ -200,7 +194,8 @@ struct SysDev {
     int* health;
     int cap, np;
     int tiles_x, tiles_y;
-    Slab sr, sk;  // raster and kill/fill slabs
+    int nseg;  // surface-list segments per particle
+    int kext;  // largest kill/fill box edge of a normal step
 };
 
 // A batched launch: block b works on item items[b] = (system, local block).

@@ -19,9 +19,9 @@ struct Buffers {
     void* rho = nullptr;               // rho^c per node [2][N], for the shell fill (exponential Psi)
     uint32_t* owner[2] = {nullptr, nullptr};
     double* part = nullptr;            // particle table, NPFIELD x cap
-    uint2* slist = nullptr;            // surface list segments, cap x nslab(raster) x 64 (node, link mask)
-    int* scount = nullptr;             // entries per surface list segment, cap x nslab(raster)
-    double* kpart = nullptr;           // kill/fill impulse partial slots, cap x nslab x 6
+    uint2* slist = nullptr;            // surface list segments, cap x nseg x 64 (node, link mask)
+    int* scount = nullptr;             // entries per surface list segment, cap x nseg
+    double* kpart = nullptr;           // kill/fill impulse of the last step, cap x 6
     double* red = nullptr;             // reduction partials, kRedBlocks x 8, then totals
     double* counters = nullptr;        // [0] mass removed (cumulative), [1] kill mass, [2] fill mass
     int* health = nullptr;             // nonzero once a NaN / negative density was seen
@@ -32,7 +32,7 @@ constexpr int kRedBlocks = 1024;       // fixed grid of the deterministic reduct
 struct BatchState;
 
 // Work-item lists of a batched launch, one per kind of block.
-enum BatchItems { BI_NODE = 0, BI_TILE, BI_SLABR, BI_SLABK, BI_PART, BI_COUNT };
+enum BatchItems { BI_NODE = 0, BI_TILE, BI_PART, BI_COUNT };
 struct BatchLaunch {
     const SysDev* sys = nullptr;
     const WorkItem* items[BI_COUNT] = {};
@@ -105,8 +105,8 @@ hipError_t launch_batch_forces(const BatchLaunch& bl, int precision, hipStream_t
 hipError_t launch_batch_bodies(const BatchLaunch& bl, hipStream_t st);
 hipError_t launch_batch_raster(const BatchLaunch& bl, hipStream_t st, int o);
 hipError_t launch_batch_killfill(const BatchLaunch& bl, int precision, hipStream_t st, int oo, int fd);
-Slab slab_raster(const lb_handle* h);
-Slab slab_killfill(const lb_handle* h);
+int surf_nseg(const lb_handle* h);    // surface-list segments per particle at the current largest radius
+int kill_ext(const lb_handle* h);     // kill/fill box edge bound at the current largest radius
 
 size_t elem_bytes(int precision);
 size_t rho_elem_bytes(int precision);
@@ -126,7 +126,6 @@ hipError_t launch_raster(lb_handle* h, uint32_t* owner, int first, int count);
 hipError_t launch_clear_owner(lb_handle* h, uint32_t* owner);
 hipError_t launch_killfill(lb_handle* h);
 hipError_t launch_fold_impulses(lb_handle* h);
-Slab make_slab(int ext);
 int raster_extent(int nx, int ny, int nz, double rb);
 int killfill_extent(int nx, int ny, int nz, double rb);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);

@@ -2,9 +2,8 @@
 // torque of each particle, rigid-body update, rasterisation of the ellipsoids onto
 // the owner map, and kill / fill of nodes that change side.
 //
-// Every per-node particle kernel runs one thread per node of a particle's
-// bounding box (Slab geometry, one-wave blocks), so the dependent loads of
-// neighbouring nodes are spread over many short-lived waves instead of looped.
+// The per-node particle kernels run one block per particle that loops over the
+// nodes of the particle's box (several nodes' loads in flight per thread).
 // Forces, torques and kill/fill impulses are summed in fixed orders (per-block
 // partial slots, added in slot order): particle state is reproducible bit for
 // bit.
@@ -57,36 +56,40 @@ __device__ inline int64_t node_index(const Box& bx, int x, int y, int z) {
 }
 
 // ---------------------------------------------------------------- raster
-// Rasterise particles [first, first + gridDim.x) into owner with atomicMin:
-// the smallest index owns a node covered by several particles.
+// Rasterise particle p into owner with atomicMin (the smallest index owns a
+// node covered by several particles): one block loops over p's box.
 __device__ inline void raster_body(const Box& bx, const double* __restrict__ part, int cap,
-                                   uint32_t* __restrict__ owner, const Slab& sl, int p, int slice, int tile) {
-    int lo[3], sz[3], ix, iy, iz;
+                                   uint32_t* __restrict__ owner, int p) {
+    int lo[3], sz[3];
     if (!particle_box(bx, part, cap, p, lo, sz)) return;  // invalid state: touch nothing
-    if (!slab_node(sl, slice, tile, sz, ix, iy, iz)) return;
-    const int x = wrapc_any(lo[0] + ix, bx.nx), y = wrapc_any(lo[1] + iy, bx.ny), z = wrapc_any(lo[2] + iz, bx.nz);
     const double X[3] = {part[PX * cap + p], part[PY * cap + p], part[PZ * cap + p]};
     double R[3][3];
     qrot(part[QW * cap + p], part[QX * cap + p], part[QY * cap + p], part[QZ * cap + p], R);
-    const double dx = minimg((double)x - X[0], bx.nx);
-    const double dy = minimg((double)y - X[1], bx.ny);
-    const double dz = minimg((double)z - X[2], bx.nz);
-    if (!inside_test(R, dx, dy, dz, part[RPAR * cap + p], part[RPERP * cap + p])) return;
-    const int64_t n = node_index(bx, x, y, z);
-    if (owner[n] == OWN_WALL) return;
-    atomicMin(owner + n, (uint32_t)p);
+    const double rpar = part[RPAR * cap + p], rperp = part[RPERP * cap + p];
+    const int total = sz[0] * sz[1] * sz[2];
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        int ix, iy, iz;
+        box_node(t, sz, ix, iy, iz);
+        const int x = wrapc_any(lo[0] + ix, bx.nx), y = wrapc_any(lo[1] + iy, bx.ny), z = wrapc_any(lo[2] + iz, bx.nz);
+        const double dx = minimg((double)x - X[0], bx.nx);
+        const double dy = minimg((double)y - X[1], bx.ny);
+        const double dz = minimg((double)z - X[2], bx.nz);
+        if (!inside_test(R, dx, dy, dz, rpar, rperp)) continue;
+        const int64_t n = node_index(bx, x, y, z);
+        if (owner[n] == OWN_WALL) continue;
+        atomicMin(owner + n, (uint32_t)p);
+    }
 }
-__global__ void k_raster(Box bx, const double* __restrict__ part, int cap, uint32_t* __restrict__ owner, int first,
-                         Slab sl) {
-    raster_body(bx, part, cap, owner, sl, first + blockIdx.x, blockIdx.y, blockIdx.z);
+__global__ __launch_bounds__(kPB) void k_raster(Box bx, const double* __restrict__ part, int cap,
+                                                uint32_t* __restrict__ owner, int first) {
+    raster_body(bx, part, cap, owner, first + blockIdx.x);
 }
-// Batched: item = (system, particle * nslab + slice * tiles + tile) into the
-// owner copy `o` of every system.
-__global__ void k_raster_batch(const SysDev* __restrict__ sd, const WorkItem* __restrict__ items, int o) {
+// Batched: item = (system, particle), into the owner copy `o` of every system.
+__global__ __launch_bounds__(kPB) void k_raster_batch(const SysDev* __restrict__ sd,
+                                                      const WorkItem* __restrict__ items, int o) {
     const WorkItem w = items[blockIdx.x];
     const SysDev& d = sd[w.sys];
-    const int p = w.local / d.sr.nslab, r = w.local - p * d.sr.nslab;
-    raster_body(d.box, d.part, d.cap, d.owner[o], d.sr, p, r / d.sr.tiles, r % d.sr.tiles);
+    raster_body(d.box, d.part, d.cap, d.owner[o], w.local);
 }
 
 // ---------------------------------------------------------------- S2
@@ -95,77 +98,87 @@ __global__ void k_raster_batch(const SysDev* __restrict__ sd, const WorkItem* __
 // its magnitude to B if negative. Densities are recovered from the stored
 // Psi and the result is stored as Psi.
 // The same pass lists p's surface: every node of p with a fluid neighbour, as
-// (node, mask) with bit i set when the node's neighbour at -c_i is fluid, in
-// this block's own segment of 64 entries (lane order) plus its count.
+// (node, mask) with bit i set when the node's neighbour at -c_i is fluid.
+// One block loops over p's box in chunks of kPB nodes; each wave of a chunk
+// writes its own segment of 64 entries (lane order) and its count, for every
+// one of the nseg segments (so stale segments read as empty).
 template <class R>
 __device__ inline void shell_body(const Box& bx, R* __restrict__ psi, const R* __restrict__ rho,
                                   const uint32_t* __restrict__ owner, const double* __restrict__ part, int cap,
-                                  const Slab& sl, uint2* __restrict__ slist, int* __restrict__ scount, int p, int slice,
-                                  int tile) {
+                                  int nseg, uint2* __restrict__ slist, int* __restrict__ scount, int p) {
     const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
     const int64_t N = bx.N;
-    int lo[3], sz[3], ix, iy, iz;
-    uint32_t mask = 0u;
-    int64_t n = 0;
-    if (particle_box(bx, part, cap, p, lo, sz) && slab_node(sl, slice, tile, sz, ix, iy, iz)) {
-        const int x = wrapc_any(lo[0] + ix, nx), y = wrapc_any(lo[1] + iy, ny), z = wrapc_any(lo[2] + iz, nz);
-        n = node_index(bx, x, y, z);
-        if (owner[n] == (uint32_t)p) {
-            // densities of fluid nodes: the stored rho (Psi itself when Psi = rho)
-            const R* dens = bx.psi_kind == 0 ? psi : rho;
-            uint32_t on[Q];
-            R d0[Q], d1[Q];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int lo[3], sz[3];
+    const int total = particle_box(bx, part, cap, p, lo, sz) ? sz[0] * sz[1] * sz[2] : 0;
+    // densities of fluid nodes: the stored rho (Psi itself when Psi = rho)
+    const R* dens = bx.psi_kind == 0 ? psi : rho;
+    const double dr = part[DRHO * cap + p];
+    const int nchunk = nseg / (kPB / 64);
+    for (int c = 0; c < nchunk; c++) {
+        const int t = c * kPB + threadIdx.x;
+        uint32_t mask = 0u;
+        int64_t n = 0;
+        if (t < total) {
+            int ix, iy, iz;
+            box_node(t, sz, ix, iy, iz);
+            const int x = wrapc_any(lo[0] + ix, nx), y = wrapc_any(lo[1] + iy, ny), z = wrapc_any(lo[2] + iz, nz);
+            n = node_index(bx, x, y, z);
+            if (owner[n] == (uint32_t)p) {
+                uint32_t on[Q];
+                R d0[Q], d1[Q];
 #pragma unroll
-            for (int i = 1; i < Q; i++) {
-                const int64_t m = node_index(bx, wrapc(x + cx(i), nx), wrapc(y + cy(i), ny), wrapc(z + cz(i), nz));
-                on[i] = owner[m];
-                d0[i] = dens[m];
-                d1[i] = dens[N + m];
-            }
-            R s0 = R(0), s1 = R(0);
-            int k = 0;
+                for (int i = 1; i < Q; i++) {
+                    const int64_t m =
+                        node_index(bx, wrapc(x + cx(i), nx), wrapc(y + cy(i), ny), wrapc(z + cz(i), nz));
+                    on[i] = owner[m];
+                    d0[i] = dens[m];
+                    d1[i] = dens[N + m];
+                }
+                R s0 = R(0), s1 = R(0);
+                int k = 0;
 #pragma unroll
-            for (int i = 1; i < Q; i++) {
-                if (on[i] != OWN_FLUID) continue;
-                s0 += d0[i];
-                s1 += d1[i];
-                k++;
-                mask |= 1u << opp(i);
-            }
-            if (k == 0) {
-                psi[n] = R(0);
-                psi[N + n] = R(0);
-            } else {
-                const double dr = part[DRHO * cap + p];
-                R a = s0 / R(k), b = s1 / R(k);
-                if (dr > 0.0) a += R(dr);
-                else if (dr < 0.0) b += R(-dr);
-                psi[n] = psi_of(a, bx.psi_kind);
-                psi[N + n] = psi_of(b, bx.psi_kind);
+                for (int i = 1; i < Q; i++) {
+                    if (on[i] != OWN_FLUID) continue;
+                    s0 += d0[i];
+                    s1 += d1[i];
+                    k++;
+                    mask |= 1u << opp(i);
+                }
+                if (k == 0) {
+                    psi[n] = R(0);
+                    psi[N + n] = R(0);
+                } else {
+                    R a = s0 / R(k), b = s1 / R(k);
+                    if (dr > 0.0) a += R(dr);
+                    else if (dr < 0.0) b += R(-dr);
+                    psi[n] = psi_of(a, bx.psi_kind);
+                    psi[N + n] = psi_of(b, bx.psi_kind);
+                }
             }
         }
+        const unsigned long long bal = __ballot(mask != 0u);
+        const size_t seg = (size_t)p * nseg + c * (kPB / 64) + w;
+        if (mask != 0u) {
+            const int pos = __popcll(bal & ((1ull << lane) - 1ull));
+            slist[seg * 64 + pos] = make_uint2((uint32_t)n, mask);
+        }
+        if (lane == 0) scount[seg] = __popcll(bal);
     }
-    const unsigned long long bal = __ballot(mask != 0u);
-    const size_t seg = (size_t)p * sl.nslab + slice * sl.tiles + tile;
-    if (mask != 0u) {
-        const int pos = __popcll(bal & ((1ull << threadIdx.x) - 1ull));
-        slist[seg * 64 + pos] = make_uint2((uint32_t)n, mask);
-    }
-    if (threadIdx.x == 0) scount[seg] = __popcll(bal);
 }
 template <class R>
-__global__ void k_shell(Box bx, R* __restrict__ psi, const R* __restrict__ rho, const uint32_t* __restrict__ owner,
-                        const double* __restrict__ part, int cap, Slab sl, uint2* __restrict__ slist,
-                        int* __restrict__ scount) {
-    shell_body<R>(bx, psi, rho, owner, part, cap, sl, slist, scount, blockIdx.x, blockIdx.y, blockIdx.z);
+__global__ __launch_bounds__(kPB) void k_shell(Box bx, R* __restrict__ psi, const R* __restrict__ rho,
+                                               const uint32_t* __restrict__ owner, const double* __restrict__ part,
+                                               int cap, int nseg, uint2* __restrict__ slist,
+                                               int* __restrict__ scount) {
+    shell_body<R>(bx, psi, rho, owner, part, cap, nseg, slist, scount, blockIdx.x);
 }
 template <class R>
-__global__ void k_shell_batch(const SysDev* __restrict__ sd, const WorkItem* __restrict__ items, int o) {
+__global__ __launch_bounds__(kPB) void k_shell_batch(const SysDev* __restrict__ sd, const WorkItem* __restrict__ items,
+                                                     int o) {
     const WorkItem w = items[blockIdx.x];
     const SysDev& d = sd[w.sys];
-    const int p = w.local / d.sr.nslab, r = w.local - p * d.sr.nslab;
-    shell_body<R>(d.box, (R*)d.psi, (const R*)d.rho, d.owner[o], d.part, d.cap, d.sr, d.slist, d.scount, p,
-                  r / d.sr.tiles, r % d.sr.tiles);
+    shell_body<R>(d.box, (R*)d.psi, (const R*)d.rho, d.owner[o], d.part, d.cap, d.nseg, d.slist, d.scount, w.local);
 }
 
 // ---------------------------------------------------------------- S6 forces
@@ -183,7 +196,7 @@ __global__ void k_shell_batch(const SysDev* __restrict__ sd, const WorkItem* __r
 template <class P>
 __device__ inline void linkforce_body(const Box& bx, const typename P::S* __restrict__ f,
                                       const typename P::R* __restrict__ dens, double* __restrict__ part, int cap,
-                                      int nslab, const uint2* __restrict__ slist, const int* __restrict__ scount,
+                                      int nseg, const uint2* __restrict__ slist, const int* __restrict__ scount,
                                       int p) {
     using R = typename P::R;
     __shared__ int s_pre[257];
@@ -196,10 +209,10 @@ __device__ inline void linkforce_body(const Box& bx, const typename P::S* __rest
     const double W[3] = {part[WX * cap + p], part[WY * cap + p], part[WZ * cap + p]};
     const R ref0 = R(bx.rref[0]), ref1 = R(bx.rref[1]);
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int c0 = 0; c0 < nslab; c0 += 256) {
-        const int nc = min(256, nslab - c0);
+    for (int c0 = 0; c0 < nseg; c0 += 256) {
+        const int nc = min(256, nseg - c0);
         // exclusive prefix of the segment counts of this chunk
-        const int cnt = tid < nc ? scount[(size_t)p * nslab + c0 + tid] : 0;
+        const int cnt = tid < nc ? scount[(size_t)p * nseg + c0 + tid] : 0;
         int v = cnt;
         for (int off = 1; off < 64; off <<= 1) {
             const int u = __shfl_up(v, off, 64);
@@ -220,7 +233,7 @@ __device__ inline void linkforce_body(const Box& bx, const typename P::S* __rest
                 if (s_pre[mid] <= e) a = mid;
                 else b = mid - 1;
             }
-            const uint2 ent = slist[((size_t)p * nslab + c0 + a) * 64 + (e - s_pre[a])];
+            const uint2 ent = slist[((size_t)p * nseg + c0 + a) * 64 + (e - s_pre[a])];
             const uint32_t m = ent.x, mask = ent.y;
             const int mz = (int)(m / (uint32_t)(nx * ny));
             const int rem = (int)(m - (uint32_t)mz * (uint32_t)(nx * ny));
@@ -278,9 +291,9 @@ __device__ inline void linkforce_body(const Box& bx, const typename P::S* __rest
 template <class P>
 __global__ __launch_bounds__(256) void k_linkforce(Box bx, const typename P::S* __restrict__ f,
                                                    const typename P::R* __restrict__ dens,
-                                                   double* __restrict__ part, int cap, int nslab,
+                                                   double* __restrict__ part, int cap, int nseg,
                                                    const uint2* __restrict__ slist, const int* __restrict__ scount) {
-    linkforce_body<P>(bx, f, dens, part, cap, nslab, slist, scount, blockIdx.x);
+    linkforce_body<P>(bx, f, dens, part, cap, nseg, slist, scount, blockIdx.x);
 }
 // Batched: item = (system, particle); `d` is the post-streaming population copy.
 template <class P>
@@ -289,7 +302,7 @@ __global__ __launch_bounds__(256) void k_linkforce_batch(const SysDev* __restric
     const WorkItem w = items[blockIdx.x];
     const SysDev& d = sd[w.sys];
     const void* dens = d.box.psi_kind == 0 ? d.psi : d.rho;
-    linkforce_body<P>(d.box, (const typename P::S*)d.f[d_], (const typename P::R*)dens, d.part, d.cap, d.sr.nslab,
+    linkforce_body<P>(d.box, (const typename P::S*)d.f[d_], (const typename P::R*)dens, d.part, d.cap, d.nseg,
                       d.slist, d.scount, w.local);
 }
 
@@ -395,7 +408,7 @@ __global__ __launch_bounds__(64) void k_bodies_batch(const SysDev* __restrict__ 
                                                      const WorkItem* __restrict__ items) {
     const WorkItem w = items[blockIdx.x];
     const SysDev& d = sd[w.sys];
-    bodies_body(d.box, d.part, d.cap, d.kpart, d.sk.nslab, w.local);
+    bodies_body(d.box, d.part, d.cap, d.kpart, 1, w.local);
 }
 
 // Pending kill/fill impulses: add the partial slots into the particle's J, H
@@ -427,20 +440,93 @@ __device__ inline R feq_p(int i, R rho, R ux, R uy, R uz) {
 //   o == p, o2 fluid : fill  -> rho_new^c = mean rho^c of neighbours fluid
 //                      before and after (initial mean if none), u = V + W x r,
 //                      f = f^eq(rho_new^c, u), J_p -= sum_c rho_new^c u, H_p -= r x that.
-// Each changing node is handled by exactly one thread (of its owner's grid).
-// Impulses go to the block's partial slot; a move the union box cannot cover
-// raises health bit 2.
+// Each changing node is handled by exactly one thread (of its owner's block).
+// One block loops over the union box, four nodes per thread in flight; the
+// block's fixed-order sum is the particle's impulse of this step. A union box
+// wider than kext (a move of more than two spacings) raises health bit 2.
 template <class P>
-__device__ inline void killfill_body(const Box& bx, typename P::S* __restrict__ f,
+__device__ inline void killfill_node(const Box& bx, typename P::S* __restrict__ f,
                                      const uint32_t* __restrict__ own_old, const uint32_t* __restrict__ own_new,
-                                     const double* __restrict__ part, int cap, const Slab& sl,
-                                     double* __restrict__ kpart, double* __restrict__ counters,
-                                     int* __restrict__ health, int p, int slice, int tile) {
+                                     const double* __restrict__ part, int cap, double* __restrict__ counters, int p,
+                                     bool kill, int x, int y, int z, int64_t n, const double (&Xn)[3],
+                                     double (&acc)[6]) {
     using R = typename P::R;
     const int64_t N = bx.N;
     const int Ls[3] = {bx.nx, bx.ny, bx.nz};
+    const double r[3] = {minimg((double)x - Xn[0], Ls[0]), minimg((double)y - Xn[1], Ls[1]),
+                         minimg((double)z - Xn[2], Ls[2])};
+    if (kill) {
+        double j[3] = {0.0, 0.0, 0.0}, m = 0.0;
+        for (int cc = 0; cc < 2; cc++) {
+            const R ref = R(bx.rref[cc]);
+#pragma unroll
+            for (int i = 0; i < Q; i++) {
+                typename P::S* ptr = f + (size_t)(cc * Q + i) * N + n;
+                const double v = (double)P::ld(ptr, R(wq(i)) * ref);
+                m += v;
+                j[0] += v * cx(i);
+                j[1] += v * cy(i);
+                j[2] += v * cz(i);
+                P::st(ptr, R(0), R(wq(i)) * ref);
+            }
+        }
+        acc[0] += j[0];
+        acc[1] += j[1];
+        acc[2] += j[2];
+        acc[3] += r[1] * j[2] - r[2] * j[1];
+        acc[4] += r[2] * j[0] - r[0] * j[2];
+        acc[5] += r[0] * j[1] - r[1] * j[0];
+        unsafeAtomicAdd(counters + 0, m);
+        unsafeAtomicAdd(counters + 1, m);
+    } else {
+        const double V[3] = {part[VX * cap + p], part[VY * cap + p], part[VZ * cap + p]};
+        const double W[3] = {part[WX * cap + p], part[WY * cap + p], part[WZ * cap + p]};
+        double rn[2] = {0.0, 0.0};
+        int cnt = 0;
+        // neighbours one at a time (each one's 2 x 19 loads in flight together)
+#pragma unroll 1
+        for (int i = 1; i < Q; i++) {
+            const int64_t m = node_index(bx, wrapc(x + cx(i), Ls[0]), wrapc(y + cy(i), Ls[1]), wrapc(z + cz(i), Ls[2]));
+            if (own_old[m] != OWN_FLUID || own_new[m] != OWN_FLUID) continue;
+            for (int cc = 0; cc < 2; cc++) {
+                const R ref = R(bx.rref[cc]);
+                double s = 0.0;
+#pragma unroll
+                for (int q = 0; q < Q; q++) s += (double)P::ld(f + (size_t)(cc * Q + q) * N + m, R(wq(q)) * ref);
+                rn[cc] += s;
+            }
+            cnt++;
+        }
+        for (int cc = 0; cc < 2; cc++) rn[cc] = cnt > 0 ? rn[cc] / (double)cnt : bx.rmean0[cc];
+        const double ub[3] = {V[0] + (W[1] * r[2] - W[2] * r[1]), V[1] + (W[2] * r[0] - W[0] * r[2]),
+                              V[2] + (W[0] * r[1] - W[1] * r[0])};
+        double jm[3] = {0.0, 0.0, 0.0};
+        for (int cc = 0; cc < 2; cc++) {
+            const R ref = R(bx.rref[cc]);
+#pragma unroll
+            for (int i = 0; i < Q; i++)
+                P::st(f + (size_t)(cc * Q + i) * N + n, R(feq_p<double>(i, rn[cc], ub[0], ub[1], ub[2])), R(wq(i)) * ref);
+            for (int d = 0; d < 3; d++) jm[d] += rn[cc] * ub[d];
+        }
+        acc[0] -= jm[0];
+        acc[1] -= jm[1];
+        acc[2] -= jm[2];
+        acc[3] -= r[1] * jm[2] - r[2] * jm[1];
+        acc[4] -= r[2] * jm[0] - r[0] * jm[2];
+        acc[5] -= r[0] * jm[1] - r[1] * jm[0];
+        unsafeAtomicAdd(counters + 0, -(rn[0] + rn[1]));
+        unsafeAtomicAdd(counters + 2, rn[0] + rn[1]);
+    }
+}
+
+template <class P>
+__device__ inline void killfill_body(const Box& bx, typename P::S* __restrict__ f,
+                                     const uint32_t* __restrict__ own_old, const uint32_t* __restrict__ own_new,
+                                     const double* __restrict__ part, int cap, int kext, double* __restrict__ kpart,
+                                     double* __restrict__ counters, int* __restrict__ health, int p) {
+    const int Ls[3] = {bx.nx, bx.ny, bx.nz};
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    int lo[3] = {0, 0, 0}, sz[3] = {0, 0, 0}, ix = 0, iy = 0, iz = 0;
+    int lo[3] = {0, 0, 0}, sz[3] = {0, 0, 0};
     bool ok = true;
     const double Xn[3] = {part[PX * cap + p], part[PY * cap + p], part[PZ * cap + p]};
     const double Xo[3] = {part[OX * cap + p], part[OY * cap + p], part[OZ * cap + p]};
@@ -456,120 +542,70 @@ __device__ inline void killfill_body(const Box& bx, typename P::S* __restrict__ 
         const int b = max((int)floor(Xo[d] + rb), (int)floor(xn + rb));
         lo[d] = a;
         sz[d] = max(0, min(b - a + 1, Ls[d]));
-        if (sz[d] > sl.ext && threadIdx.x == 0 && slice == 0 && tile == 0) atomicOr(health, 2);
+        if (sz[d] > kext && threadIdx.x == 0) atomicOr(health, 2);
     }
-    if (ok) ok = slab_node(sl, slice, tile, sz, ix, iy, iz);
-    if (ok) {
-        const int x = wrapc_any(lo[0] + ix, Ls[0]), y = wrapc_any(lo[1] + iy, Ls[1]), z = wrapc_any(lo[2] + iz, Ls[2]);
-        const int64_t n = node_index(bx, x, y, z);
-        const uint32_t o = own_old[n], o2 = own_new[n];
-        const bool kill = (o == OWN_FLUID && o2 == (uint32_t)p);
-        const bool fill = (o == (uint32_t)p && o2 == OWN_FLUID);
-        if (kill || fill) {
-            const double r[3] = {minimg((double)x - Xn[0], Ls[0]), minimg((double)y - Xn[1], Ls[1]),
-                                 minimg((double)z - Xn[2], Ls[2])};
-            if (kill) {
-                double j[3] = {0.0, 0.0, 0.0}, m = 0.0;
-                for (int cc = 0; cc < 2; cc++) {
-                    const R ref = R(bx.rref[cc]);
+    const int total = ok ? sz[0] * sz[1] * sz[2] : 0;
+    constexpr int U = 4;
+    for (int base = 0; base < total; base += U * kPB) {
+        uint32_t oo[U], on[U];
+        int64_t nn[U];
+        int xs[U], ys[U], zs[U];
 #pragma unroll
-                    for (int i = 0; i < Q; i++) {
-                        typename P::S* ptr = f + (size_t)(cc * Q + i) * N + n;
-                        const double v = (double)P::ld(ptr, R(wq(i)) * ref);
-                        m += v;
-                        j[0] += v * cx(i);
-                        j[1] += v * cy(i);
-                        j[2] += v * cz(i);
-                        P::st(ptr, R(0), R(wq(i)) * ref);
-                    }
-                }
-                acc[0] = j[0];
-                acc[1] = j[1];
-                acc[2] = j[2];
-                acc[3] = r[1] * j[2] - r[2] * j[1];
-                acc[4] = r[2] * j[0] - r[0] * j[2];
-                acc[5] = r[0] * j[1] - r[1] * j[0];
-                unsafeAtomicAdd(counters + 0, m);
-                unsafeAtomicAdd(counters + 1, m);
-            } else {
-                const double V[3] = {part[VX * cap + p], part[VY * cap + p], part[VZ * cap + p]};
-                const double W[3] = {part[WX * cap + p], part[WY * cap + p], part[WZ * cap + p]};
-                double rn[2] = {0.0, 0.0};
-                int cnt = 0;
-#pragma unroll
-                for (int i = 1; i < Q; i++) {
-                    const int64_t m =
-                        node_index(bx, wrapc(x + cx(i), Ls[0]), wrapc(y + cy(i), Ls[1]), wrapc(z + cz(i), Ls[2]));
-                    if (own_old[m] != OWN_FLUID || own_new[m] != OWN_FLUID) continue;
-                    for (int cc = 0; cc < 2; cc++) {
-                        const R ref = R(bx.rref[cc]);
-                        double s = 0.0;
-                        for (int q = 0; q < Q; q++) s += (double)P::ld(f + (size_t)(cc * Q + q) * N + m, R(wq(q)) * ref);
-                        rn[cc] += s;
-                    }
-                    cnt++;
-                }
-                for (int cc = 0; cc < 2; cc++) rn[cc] = cnt > 0 ? rn[cc] / (double)cnt : bx.rmean0[cc];
-                const double ub[3] = {V[0] + (W[1] * r[2] - W[2] * r[1]), V[1] + (W[2] * r[0] - W[0] * r[2]),
-                                      V[2] + (W[0] * r[1] - W[1] * r[0])};
-                double jm[3] = {0.0, 0.0, 0.0};
-                for (int cc = 0; cc < 2; cc++) {
-                    const R ref = R(bx.rref[cc]);
-#pragma unroll
-                    for (int i = 0; i < Q; i++)
-                        P::st(f + (size_t)(cc * Q + i) * N + n, R(feq_p<double>(i, rn[cc], ub[0], ub[1], ub[2])),
-                              R(wq(i)) * ref);
-                    for (int d = 0; d < 3; d++) jm[d] += rn[cc] * ub[d];
-                }
-                acc[0] = -jm[0];
-                acc[1] = -jm[1];
-                acc[2] = -jm[2];
-                acc[3] = -(r[1] * jm[2] - r[2] * jm[1]);
-                acc[4] = -(r[2] * jm[0] - r[0] * jm[2]);
-                acc[5] = -(r[0] * jm[1] - r[1] * jm[0]);
-                unsafeAtomicAdd(counters + 0, -(rn[0] + rn[1]));
-                unsafeAtomicAdd(counters + 2, rn[0] + rn[1]);
+        for (int k = 0; k < U; k++) {
+            const int t = base + k * kPB + threadIdx.x;
+            oo[k] = on[k] = OWN_FLUID;
+            nn[k] = 0;
+            xs[k] = ys[k] = zs[k] = 0;
+            if (t < total) {
+                int ix, iy, iz;
+                box_node(t, sz, ix, iy, iz);
+                xs[k] = wrapc_any(lo[0] + ix, Ls[0]);
+                ys[k] = wrapc_any(lo[1] + iy, Ls[1]);
+                zs[k] = wrapc_any(lo[2] + iz, Ls[2]);
+                nn[k] = node_index(bx, xs[k], ys[k], zs[k]);
+                oo[k] = own_old[nn[k]];
+                on[k] = own_new[nn[k]];
             }
+        }
+#pragma unroll
+        for (int k = 0; k < U; k++) {
+            const bool kill = (oo[k] == OWN_FLUID && on[k] == (uint32_t)p);
+            const bool fill = (oo[k] == (uint32_t)p && on[k] == OWN_FLUID);
+            if (kill || fill)
+                killfill_node<P>(bx, f, own_old, own_new, part, cap, counters, p, kill, xs[k], ys[k], zs[k], nn[k], Xn,
+                                 acc);
         }
     }
     double tot[6];
     block_sum6(acc, tot);
-    if (threadIdx.x == 0) {
-        double* o = kpart + ((size_t)p * sl.nslab + slice * sl.tiles + tile) * 6;
-        for (int k = 0; k < 6; k++) o[k] = tot[k];
-    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 6; k++) kpart[(size_t)p * 6 + k] = tot[k];
 }
 template <class P>
-__global__ void k_killfill(Box bx, typename P::S* __restrict__ f, const uint32_t* __restrict__ own_old,
-                           const uint32_t* __restrict__ own_new, const double* __restrict__ part, int cap, Slab sl,
-                           double* __restrict__ kpart, double* __restrict__ counters, int* __restrict__ health) {
-    killfill_body<P>(bx, f, own_old, own_new, part, cap, sl, kpart, counters, health, blockIdx.x, blockIdx.y,
-                     blockIdx.z);
+__global__ __launch_bounds__(kPB) void k_killfill(Box bx, typename P::S* __restrict__ f,
+                                                  const uint32_t* __restrict__ own_old,
+                                                  const uint32_t* __restrict__ own_new,
+                                                  const double* __restrict__ part, int cap, int kext,
+                                                  double* __restrict__ kpart, double* __restrict__ counters,
+                                                  int* __restrict__ health) {
+    killfill_body<P>(bx, f, own_old, own_new, part, cap, kext, kpart, counters, health, blockIdx.x);
 }
-// Batched: item = (system, particle * nslab + slice * tiles + tile); owner
-// copy `oo` is the old map, 1 - oo the new one; populations copy `fd`.
+// Batched: item = (system, particle); owner copy `oo` is the old map, 1 - oo
+// the new one; populations copy `fd`.
 template <class P>
-__global__ void k_killfill_batch(const SysDev* __restrict__ sd, const WorkItem* __restrict__ items, int oo, int fd) {
+__global__ __launch_bounds__(kPB) void k_killfill_batch(const SysDev* __restrict__ sd,
+                                                        const WorkItem* __restrict__ items, int oo, int fd) {
     const WorkItem w = items[blockIdx.x];
     const SysDev& d = sd[w.sys];
-    const int p = w.local / d.sk.nslab, r = w.local - p * d.sk.nslab;
-    killfill_body<P>(d.box, (typename P::S*)d.f[fd], d.owner[oo], d.owner[1 - oo], d.part, d.cap, d.sk, d.kpart,
-                     d.counters, d.health, p, r / d.sk.tiles, r % d.sk.tiles);
+    killfill_body<P>(d.box, (typename P::S*)d.f[fd], d.owner[oo], d.owner[1 - oo], d.part, d.cap, d.kext, d.kpart,
+                     d.counters, d.health, w.local);
 }
 
 // ---------------------------------------------------------------- launchers
 
-Slab make_slab(int ext) {
-    Slab s;
-    s.ext = ext < 1 ? 1 : ext;
-    s.B = 64;
-    s.tiles = (s.ext * s.ext + 63) / 64;
-    s.nslab = s.ext * s.tiles;
-    return s;
-}
-
 // Extent of the raster box for bounding radius rb: floor(2 rb) + 1, at most
-// the longest side; the kill/fill union box has two more nodes.
+// the longest side; the kill/fill union box of a move below two spacings has
+// two more nodes.
 int raster_extent(int nx, int ny, int nz, double rb) {
     const int L = std::max(nx, std::max(ny, nz));
     return std::min((int)floor(2.0 * rb) + 1, L);
@@ -578,50 +614,48 @@ int killfill_extent(int nx, int ny, int nz, double rb) {
     const int L = std::max(nx, std::max(ny, nz));
     return std::min(raster_extent(nx, ny, nz, rb) + 2, L);
 }
-Slab slab_raster(const lb_handle* h) { return make_slab(raster_extent(h->box.nx, h->box.ny, h->box.nz, h->rmax)); }
-Slab slab_killfill(const lb_handle* h) {
-    return make_slab(killfill_extent(h->box.nx, h->box.ny, h->box.nz, h->rmax));
+int surf_nseg(const lb_handle* h) {
+    return surf_segments(raster_extent(h->box.nx, h->box.ny, h->box.nz, h->rmax));
 }
+int kill_ext(const lb_handle* h) { return killfill_extent(h->box.nx, h->box.ny, h->box.nz, h->rmax); }
 
 hipError_t launch_shell(lb_handle* h) {
     if (h->np <= 0) return hipSuccess;
-    const Slab s = slab_raster(h);
-    const dim3 g(h->np, s.ext, s.tiles);
+    const int nseg = surf_nseg(h);
     if (h->prm.precision == LB_FP64)
-        hipLaunchKernelGGL(k_shell<double>, g, dim3(s.B), 0, h->stream, h->box, (double*)h->b.psi,
-                           (const double*)h->b.rho, h->b.owner[h->ocur], h->b.part, h->cap, s, h->b.slist,
+        hipLaunchKernelGGL(k_shell<double>, dim3(h->np), dim3(kPB), 0, h->stream, h->box, (double*)h->b.psi,
+                           (const double*)h->b.rho, h->b.owner[h->ocur], h->b.part, h->cap, nseg, h->b.slist,
                            h->b.scount);
     else
-        hipLaunchKernelGGL(k_shell<float>, g, dim3(s.B), 0, h->stream, h->box, (float*)h->b.psi,
-                           (const float*)h->b.rho, h->b.owner[h->ocur], h->b.part, h->cap, s, h->b.slist,
+        hipLaunchKernelGGL(k_shell<float>, dim3(h->np), dim3(kPB), 0, h->stream, h->box, (float*)h->b.psi,
+                           (const float*)h->b.rho, h->b.owner[h->ocur], h->b.part, h->cap, nseg, h->b.slist,
                            h->b.scount);
     return hipGetLastError();
 }
 
 hipError_t launch_forces(lb_handle* h) {
     if (h->np <= 0) return hipSuccess;
-    const int nslab = slab_raster(h).nslab;
+    const int nseg = surf_nseg(h);
     const void* fn = h->b.f[1 - h->cur];
     // rho^c(n) of fluid nodes: Psi itself when Psi = rho, else the stored rho
     const void* dens = h->prm.psi_kind == 0 ? h->b.psi : h->b.rho;
     LBE_PDISPATCH(h->prm.precision,
                   hipLaunchKernelGGL(k_linkforce<P>, dim3(h->np), dim3(256), 0, h->stream, h->box,
-                                     (const typename P::S*)fn, (const typename P::R*)dens, h->b.part, h->cap, nslab,
+                                     (const typename P::S*)fn, (const typename P::R*)dens, h->b.part, h->cap, nseg,
                                      h->b.slist, h->b.scount));
     return hipGetLastError();
 }
 
 hipError_t launch_bodies(lb_handle* h) {
     if (h->np <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bodies, dim3(h->np), dim3(64), 0, h->stream, h->box, h->b.part, h->cap, h->b.kpart,
-                       slab_killfill(h).nslab);
+    hipLaunchKernelGGL(k_bodies, dim3(h->np), dim3(64), 0, h->stream, h->box, h->b.part, h->cap, h->b.kpart, 1);
     return hipGetLastError();
 }
 
 hipError_t launch_fold_impulses(lb_handle* h) {
     if (h->np <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fold_impulses, dim3((h->np + 63) / 64), dim3(64), 0, h->stream, h->b.part, h->cap, h->np,
-                       h->b.kpart, slab_killfill(h).nslab);
+                       h->b.kpart, 1);
     return hipGetLastError();
 }
 
@@ -629,9 +663,7 @@ hipError_t launch_clear_owner(lb_handle* h, uint32_t* owner) { return launch_fil
 
 hipError_t launch_raster(lb_handle* h, uint32_t* owner, int first, int count) {
     if (count <= 0) return hipSuccess;
-    const Slab s = slab_raster(h);
-    hipLaunchKernelGGL(k_raster, dim3(count, s.ext, s.tiles), dim3(s.B), 0, h->stream, h->box, h->b.part, h->cap, owner,
-                       first, s);
+    hipLaunchKernelGGL(k_raster, dim3(count), dim3(kPB), 0, h->stream, h->box, h->b.part, h->cap, owner, first);
     return hipGetLastError();
 }
 
@@ -640,37 +672,22 @@ hipError_t launch_killfill(lb_handle* h) {
     uint32_t* oo = h->b.owner[h->ocur];
     uint32_t* on = h->b.owner[1 - h->ocur];
     void* fn = h->b.f[1 - h->cur];
-    const Slab s = slab_killfill(h);
-    const dim3 g(h->np, s.ext, s.tiles);
-    switch (h->prm.precision) {
-        case LB_FP64:
-            hipLaunchKernelGGL(k_killfill<PolF64>, g, dim3(s.B), 0, h->stream, h->box, (double*)fn, oo, on, h->b.part,
-                               h->cap, s, h->b.kpart, h->b.counters, h->b.health);
-            break;
-        case LB_FP32:
-            hipLaunchKernelGGL(k_killfill<PolF32>, g, dim3(s.B), 0, h->stream, h->box, (float*)fn, oo, on, h->b.part,
-                               h->cap, s, h->b.kpart, h->b.counters, h->b.health);
-            break;
-        case LB_FP16_DEV:
-            hipLaunchKernelGGL(k_killfill<PolF16>, g, dim3(s.B), 0, h->stream, h->box, (__half*)fn, oo, on, h->b.part,
-                               h->cap, s, h->b.kpart, h->b.counters, h->b.health);
-            break;
-        default:
-            hipLaunchKernelGGL(k_killfill<PolBF16>, g, dim3(s.B), 0, h->stream, h->box, (__hip_bfloat16*)fn, oo, on,
-                               h->b.part, h->cap, s, h->b.kpart, h->b.counters, h->b.health);
-            break;
-    }
+    const int kext = kill_ext(h);
+    LBE_PDISPATCH(h->prm.precision,
+                  hipLaunchKernelGGL(k_killfill<P>, dim3(h->np), dim3(kPB), 0, h->stream, h->box,
+                                     (typename P::S*)fn, oo, on, h->b.part, h->cap, kext, h->b.kpart, h->b.counters,
+                                     h->b.health));
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- batched launchers
 
 hipError_t launch_batch_shell(const BatchLaunch& bl, int precision, hipStream_t st, int o) {
-    if (bl.n[BI_SLABR] == 0) return hipSuccess;
+    if (bl.n[BI_PART] == 0) return hipSuccess;
     if (precision == LB_FP64)
-        hipLaunchKernelGGL(k_shell_batch<double>, dim3(bl.n[BI_SLABR]), dim3(64), 0, st, bl.sys, bl.items[BI_SLABR], o);
+        hipLaunchKernelGGL(k_shell_batch<double>, dim3(bl.n[BI_PART]), dim3(kPB), 0, st, bl.sys, bl.items[BI_PART], o);
     else
-        hipLaunchKernelGGL(k_shell_batch<float>, dim3(bl.n[BI_SLABR]), dim3(64), 0, st, bl.sys, bl.items[BI_SLABR], o);
+        hipLaunchKernelGGL(k_shell_batch<float>, dim3(bl.n[BI_PART]), dim3(kPB), 0, st, bl.sys, bl.items[BI_PART], o);
     return hipGetLastError();
 }
 
@@ -688,15 +705,15 @@ hipError_t launch_batch_bodies(const BatchLaunch& bl, hipStream_t st) {
 }
 
 hipError_t launch_batch_raster(const BatchLaunch& bl, hipStream_t st, int o) {
-    if (bl.n[BI_SLABR] == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_raster_batch, dim3(bl.n[BI_SLABR]), dim3(64), 0, st, bl.sys, bl.items[BI_SLABR], o);
+    if (bl.n[BI_PART] == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_raster_batch, dim3(bl.n[BI_PART]), dim3(kPB), 0, st, bl.sys, bl.items[BI_PART], o);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_killfill(const BatchLaunch& bl, int precision, hipStream_t st, int oo, int fd) {
-    if (bl.n[BI_SLABK] == 0) return hipSuccess;
-    LBE_PDISPATCH(precision, hipLaunchKernelGGL(k_killfill_batch<P>, dim3(bl.n[BI_SLABK]), dim3(64), 0, st, bl.sys,
-                                                bl.items[BI_SLABK], oo, fd));
+    if (bl.n[BI_PART] == 0) return hipSuccess;
+    LBE_PDISPATCH(precision, hipLaunchKernelGGL(k_killfill_batch<P>, dim3(bl.n[BI_PART]), dim3(kPB), 0, st, bl.sys,
+                                                bl.items[BI_PART], oo, fd));
     return hipGetLastError();
 }
 

@@ -57,11 +57,10 @@ Layout layout_of(const lb_params* p) {
     L.owner = align_up(N * sizeof(uint32_t));
     L.part = align_up(NPFIELD * cap * sizeof(double));
     const double rmax = p->max_particles > 0 ? p->max_radius : 0.5;
-    const Slab s1 = make_slab(raster_extent(p->nx, p->ny, p->nz, rmax));
-    const Slab s2 = make_slab(killfill_extent(p->nx, p->ny, p->nz, rmax));
-    L.slist = p->max_particles > 0 ? align_up(cap * (size_t)s1.nslab * 64 * sizeof(uint2)) : 0;
-    L.scount = p->max_particles > 0 ? align_up(cap * (size_t)s1.nslab * sizeof(int)) : 0;
-    L.kpart = align_up(cap * (size_t)s2.nslab * 6 * sizeof(double));
+    const size_t nseg = (size_t)surf_segments(raster_extent(p->nx, p->ny, p->nz, rmax));
+    L.slist = p->max_particles > 0 ? align_up(cap * nseg * 64 * sizeof(uint2)) : 0;
+    L.scount = p->max_particles > 0 ? align_up(cap * nseg * sizeof(int)) : 0;
+    L.kpart = align_up(cap * 6 * sizeof(double));
     L.red = align_up((kRedBlocks + 1) * 8 * sizeof(double));
     L.counters = align_up(8 * sizeof(double));
     L.health = align_up(sizeof(int));
