@@ -26,6 +26,7 @@ struct BatchState {
     bool dirty = true;
     int bx = 64;      // fused tile width in use
     int parity = 0;   // index of the current population and owner copies, shared by all systems
+    bool dens_ready = false;  // every system's Psi / rho match its current populations
     hipStream_t own = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraph_t graph[2] = {nullptr, nullptr};
@@ -162,18 +163,20 @@ int refresh(lb_handle* h) {
     return LB_OK;
 }
 
-// One step of every system, parity c (populations and owner maps at index c).
+// One step of every system, parity c (populations and owner maps at index c),
+// starting from densities of the current populations and ending with those
+// of the next step (formed before kill / fill, as in a single-system step).
 hipError_t enqueue_batch_step(BatchState* B, hipStream_t st, int c) {
     const BatchLaunch& bl = B->bl;
     const int prec = B->precision;
     hipError_t e;
-    if ((e = launch_batch_density(bl, prec, st, c, c)) != hipSuccess) return e;
     if ((e = launch_batch_shell(bl, prec, st, c)) != hipSuccess) return e;
     if ((e = launch_batch_fused(bl, prec, st, c, c)) != hipSuccess) return e;
     if ((e = launch_batch_forces(bl, prec, st, 1 - c)) != hipSuccess) return e;
     if ((e = launch_batch_bodies(bl, st)) != hipSuccess) return e;
     if ((e = launch_batch_clear_owner(bl, st, 1 - c)) != hipSuccess) return e;
     if ((e = launch_batch_raster(bl, st, 1 - c)) != hipSuccess) return e;
+    if ((e = launch_batch_density(bl, prec, st, 1 - c, 1 - c, c)) != hipSuccess) return e;
     return launch_batch_killfill(bl, prec, st, c, 1 - c);
 }
 
@@ -218,6 +221,10 @@ int batch_step_async(lb_handle* h, int nsteps) {
     if (nsteps == 0) return LB_OK;
     LBE_HIP_OR_FAIL(h, hipEventRecord(B->ev_in, h->stream));
     LBE_HIP_OR_FAIL(h, hipStreamWaitEvent(B->own, B->ev_in, 0));
+    if (!B->dens_ready) {
+        LBE_HIP_OR_FAIL(h, launch_batch_density(B->bl, B->precision, B->own, B->parity, B->parity, -1));
+        B->dens_ready = true;
+    }
     const int pairs = nsteps / 2;
     if (pairs > 0) {
         if (!B->exec[B->parity]) {
@@ -230,7 +237,10 @@ int batch_step_async(lb_handle* h, int nsteps) {
         LBE_HIP_OR_FAIL(h, enqueue_batch_step(B, B->own, B->parity));
         B->parity = 1 - B->parity;
     }
-    for (lb_handle* q : B->subs) q->cur = q->ocur = B->parity;
+    for (lb_handle* q : B->subs) {
+        q->cur = q->ocur = B->parity;
+        q->dens_ready = true;
+    }
     LBE_HIP_OR_FAIL(h, hipEventRecord(B->ev_out, B->own));
     LBE_HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, B->ev_out, 0));
     return LB_OK;
@@ -269,7 +279,10 @@ void batch_destroy(lb_handle* h) {
 }
 
 void batch_touch(lb_handle* sub) {
-    if (sub && sub->parent && sub->parent->batch) sub->parent->batch->dirty = true;
+    if (sub && sub->parent && sub->parent->batch) {
+        sub->parent->batch->dirty = true;
+        sub->parent->batch->dens_ready = false;
+    }
 }
 
 }  // namespace lbe
@@ -375,7 +388,7 @@ int lb_batch_tune(lb_handle* h, int32_t* tile_width) {
         B->bx = bx;
         rc = refresh(h);
         if (rc != LB_OK) break;
-        LBE_HIP_OR_FAIL(h, launch_batch_density(B->bl, B->precision, h->stream, c, c));
+        LBE_HIP_OR_FAIL(h, launch_batch_density(B->bl, B->precision, h->stream, c, c, -1));
         LBE_HIP_OR_FAIL(h, launch_batch_shell(B->bl, B->precision, h->stream, c));
         LBE_HIP_OR_FAIL(h, launch_batch_fused(B->bl, B->precision, h->stream, c, c));
         LBE_HIP_OR_FAIL(h, hipEventRecord(e0, h->stream));

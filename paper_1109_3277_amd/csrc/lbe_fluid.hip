@@ -32,15 +32,19 @@ __device__ inline R feq_i(int i, R rho, R ux, R uy, R uz, R uu) {
 // rho^c(n) = sum_i f_i^c(n) on fluid nodes, stored as the effective mass
 // Psi^c(n) of Eq. (3) (what the force stencil reads) and, when the shell fill
 // needs it, as rho^c(n); health flag on NaN / rho < 0.
+// With owner_old given (the pass that follows the re-rasterisation), nodes that
+// were not fluid before are skipped: kill / fill sets a filled node's values.
 template <class P, bool SOLID>
 __device__ inline void density_body(const Box& bx, const typename P::S* __restrict__ f,
                                     typename P::R* __restrict__ psi, typename P::R* __restrict__ rho,
-                                    const uint32_t* __restrict__ owner, int* __restrict__ health, int blk) {
+                                    const uint32_t* __restrict__ owner, const uint32_t* __restrict__ owner_old,
+                                    int* __restrict__ health, int blk) {
     using R = typename P::R;
     const uint32_t N = (uint32_t)bx.N;
     const uint32_t n = (uint32_t)blk * 256u + threadIdx.x;
     if (n >= N) return;
     if (SOLID && owner[n] != OWN_FLUID) return;
+    if (owner_old && owner_old[n] != OWN_FLUID) return;
     const uint32_t nb = n * (uint32_t)sizeof(typename P::S);
     const R ref0 = R(bx.rref[0]), ref1 = R(bx.rref[1]);
     R r0 = R(0), r1 = R(0);
@@ -60,19 +64,21 @@ __device__ inline void density_body(const Box& bx, const typename P::S* __restri
 template <class P, bool SOLID>
 __global__ __launch_bounds__(256) void k_density(Box bx, const typename P::S* __restrict__ f,
                                                  typename P::R* __restrict__ psi, typename P::R* __restrict__ rho,
-                                                 const uint32_t* __restrict__ owner, int* __restrict__ health) {
-    density_body<P, SOLID>(bx, f, psi, rho, owner, health, blockIdx.x);
+                                                 const uint32_t* __restrict__ owner,
+                                                 const uint32_t* __restrict__ owner_old, int* __restrict__ health) {
+    density_body<P, SOLID>(bx, f, psi, rho, owner, owner_old, health, blockIdx.x);
 }
 // Batched: item = (system, block of 256 nodes); populations copy `c`, owner
-// copy `o`; rho is written where the system keeps it (particles present).
+// copy `o` (and, if oo >= 0, old owner copy `oo`); rho is written where the
+// system keeps it (particles present).
 template <class P>
 __global__ __launch_bounds__(256) void k_density_batch(const SysDev* __restrict__ sd,
-                                                       const WorkItem* __restrict__ items, int c, int o) {
+                                                       const WorkItem* __restrict__ items, int c, int o, int oo) {
     const WorkItem w = items[blockIdx.x];
     const SysDev& d = sd[w.sys];
     typename P::R* rho = (d.np > 0 && d.box.psi_kind != 0) ? (typename P::R*)d.rho : nullptr;
-    density_body<P, true>(d.box, (const typename P::S*)d.f[c], (typename P::R*)d.psi, rho, d.owner[o], d.health,
-                          w.local);
+    density_body<P, true>(d.box, (const typename P::S*)d.f[c], (typename P::R*)d.psi, rho, d.owner[o],
+                          oo >= 0 ? d.owner[oo] : nullptr, d.health, w.local);
 }
 
 // ---------------------------------------------------------------- S3-S6
@@ -649,18 +655,21 @@ hipError_t launch_init(lb_handle* h, const double* ra, const double* rb, const d
     return hipGetLastError();
 }
 
-hipError_t launch_density(lb_handle* h) {
+// Densities of populations copy `c` on the nodes fluid in owner copy `o`
+// (and, when oo >= 0, also fluid in owner copy `oo`).
+hipError_t launch_density(lb_handle* h, int c, int o, int oo) {
     void* rho_out = (h->has_solid && h->prm.psi_kind != 0) ? h->b.rho : nullptr;
+    const uint32_t* own_old = oo >= 0 ? h->b.owner[oo] : nullptr;
     if (h->has_solid) {
         LBE_DISPATCH(h->prm.precision,
                      hipLaunchKernelGGL((k_density<P, true>), dim3(nblk(h->box.N)), dim3(256), 0, h->stream, h->box,
-                                        (const typename P::S*)h->b.f[h->cur], (typename P::R*)h->b.psi,
-                                        (typename P::R*)rho_out, h->b.owner[h->ocur], h->b.health));
+                                        (const typename P::S*)h->b.f[c], (typename P::R*)h->b.psi,
+                                        (typename P::R*)rho_out, h->b.owner[o], own_old, h->b.health));
     } else {
         LBE_DISPATCH(h->prm.precision,
                      hipLaunchKernelGGL((k_density<P, false>), dim3(nblk(h->box.N)), dim3(256), 0, h->stream, h->box,
-                                        (const typename P::S*)h->b.f[h->cur], (typename P::R*)h->b.psi,
-                                        (typename P::R*)nullptr, h->b.owner[h->ocur], h->b.health));
+                                        (const typename P::S*)h->b.f[c], (typename P::R*)h->b.psi,
+                                        (typename P::R*)nullptr, h->b.owner[o], nullptr, h->b.health));
     }
     return hipGetLastError();
 }
@@ -778,10 +787,10 @@ size_t rho_elem_bytes(int precision) { return precision == LB_FP64 ? 8 : 4; }
 
 // ---------------------------------------------------------------- batched launchers
 
-hipError_t launch_batch_density(const BatchLaunch& bl, int precision, hipStream_t st, int c, int o) {
+hipError_t launch_batch_density(const BatchLaunch& bl, int precision, hipStream_t st, int c, int o, int oo) {
     if (bl.n[BI_NODE] == 0) return hipSuccess;
     LBE_DISPATCH(precision, hipLaunchKernelGGL(k_density_batch<P>, dim3(bl.n[BI_NODE]), dim3(256), 0, st, bl.sys,
-                                               bl.items[BI_NODE], c, o));
+                                               bl.items[BI_NODE], c, o, oo));
     return hipGetLastError();
 }
 

@@ -56,6 +56,7 @@ struct lb_handle {
     int64_t kpart_len = 0;  // doubles in the kill/fill slot buffer
     bool inited = false;
     bool has_solid = false;
+    bool dens_ready = false;  // Psi (and rho) of the current populations already computed (end of the last step)
     std::string err;
     // phase timing (lb_profile_*)
     bool prof_on = false;
@@ -97,7 +98,7 @@ void batch_destroy(lb_handle* h);
 void batch_touch(lb_handle* sub);  // a system changed: its batch refreshes its tables before stepping
 
 // Batched launchers (one launch per phase over every system).
-hipError_t launch_batch_density(const BatchLaunch& bl, int precision, hipStream_t st, int c, int o);
+hipError_t launch_batch_density(const BatchLaunch& bl, int precision, hipStream_t st, int c, int o, int oo);
 hipError_t launch_batch_fused(const BatchLaunch& bl, int precision, hipStream_t st, int c, int o);
 hipError_t launch_batch_clear_owner(const BatchLaunch& bl, hipStream_t st, int o);
 hipError_t launch_batch_shell(const BatchLaunch& bl, int precision, hipStream_t st, int o);
@@ -113,7 +114,7 @@ size_t rho_elem_bytes(int precision);
 
 // Launchers (all enqueue on h->stream; return hipSuccess or the launch error).
 hipError_t launch_init(lb_handle* h, const double* d_rho_a, const double* d_rho_b, const double* d_u);
-hipError_t launch_density(lb_handle* h);
+hipError_t launch_density(lb_handle* h, int c, int o, int oo);
 hipError_t launch_shell(lb_handle* h);
 hipError_t launch_fused(lb_handle* h);
 hipError_t launch_forces(lb_handle* h);

@@ -435,11 +435,14 @@ __device__ inline R feq_p(int i, R rho, R ux, R uy, R uz) {
 }
 
 // Kill / fill over the union of the particle's bounding boxes before and after
-// the move. Node n with old owner o and new owner o2:
+// the move; runs after the density pass of the next step (populations after
+// streaming, nodes fluid in both owner maps). Node n with old owner o and new
+// owner o2:
 //   o fluid, o2 == p : kill  -> J_p += sum_c j^c(n), H_p += r x that, f(n) = 0
 //   o == p, o2 fluid : fill  -> rho_new^c = mean rho^c of neighbours fluid
 //                      before and after (initial mean if none), u = V + W x r,
-//                      f = f^eq(rho_new^c, u), J_p -= sum_c rho_new^c u, H_p -= r x that.
+//                      f = f^eq(rho_new^c, u), J_p -= sum_c rho_new^c u, H_p -= r x that;
+//                      the node's Psi (and rho) follow from the stored f.
 // Each changing node is handled by exactly one thread (of its owner's block).
 // One block loops over the union box, four nodes per thread in flight; the
 // block's fixed-order sum is the particle's impulse of this step. A union box
@@ -447,6 +450,7 @@ __device__ inline R feq_p(int i, R rho, R ux, R uy, R uz) {
 template <class P>
 __device__ inline void killfill_node(const Box& bx, typename P::S* __restrict__ f,
                                      const uint32_t* __restrict__ own_old, const uint32_t* __restrict__ own_new,
+                                     typename P::R* __restrict__ psi, typename P::R* __restrict__ rho,
                                      const double* __restrict__ part, int cap, double* __restrict__ counters, int p,
                                      bool kill, int x, int y, int z, int64_t n, const double (&Xn)[3],
                                      double (&acc)[6]) {
@@ -481,32 +485,50 @@ __device__ inline void killfill_node(const Box& bx, typename P::S* __restrict__ 
     } else {
         const double V[3] = {part[VX * cap + p], part[VY * cap + p], part[VZ * cap + p]};
         const double W[3] = {part[WX * cap + p], part[WY * cap + p], part[WZ * cap + p]};
+        // neighbour densities after streaming: the density pass that precedes
+        // kill / fill has stored them for every node fluid before and after
+        const R* dens = bx.psi_kind == 0 ? psi : rho;
         double rn[2] = {0.0, 0.0};
         int cnt = 0;
-        // neighbours one at a time (each one's 2 x 19 loads in flight together)
-#pragma unroll 1
+        uint32_t oo[Q], on[Q];
+        R d0[Q], d1[Q];
+#pragma unroll
         for (int i = 1; i < Q; i++) {
             const int64_t m = node_index(bx, wrapc(x + cx(i), Ls[0]), wrapc(y + cy(i), Ls[1]), wrapc(z + cz(i), Ls[2]));
-            if (own_old[m] != OWN_FLUID || own_new[m] != OWN_FLUID) continue;
-            for (int cc = 0; cc < 2; cc++) {
-                const R ref = R(bx.rref[cc]);
-                double s = 0.0;
+            oo[i] = own_old[m];
+            on[i] = own_new[m];
+            d0[i] = dens[m];
+            d1[i] = dens[N + m];
+        }
 #pragma unroll
-                for (int q = 0; q < Q; q++) s += (double)P::ld(f + (size_t)(cc * Q + q) * N + m, R(wq(q)) * ref);
-                rn[cc] += s;
-            }
+        for (int i = 1; i < Q; i++) {
+            if (oo[i] != OWN_FLUID || on[i] != OWN_FLUID) continue;
+            rn[0] += (double)d0[i];
+            rn[1] += (double)d1[i];
             cnt++;
         }
         for (int cc = 0; cc < 2; cc++) rn[cc] = cnt > 0 ? rn[cc] / (double)cnt : bx.rmean0[cc];
         const double ub[3] = {V[0] + (W[1] * r[2] - W[2] * r[1]), V[1] + (W[2] * r[0] - W[0] * r[2]),
                               V[2] + (W[0] * r[1] - W[1] * r[0])};
         double jm[3] = {0.0, 0.0, 0.0};
+        R rs[2];
         for (int cc = 0; cc < 2; cc++) {
             const R ref = R(bx.rref[cc]);
 #pragma unroll
             for (int i = 0; i < Q; i++)
                 P::st(f + (size_t)(cc * Q + i) * N + n, R(feq_p<double>(i, rn[cc], ub[0], ub[1], ub[2])), R(wq(i)) * ref);
             for (int d = 0; d < 3; d++) jm[d] += rn[cc] * ub[d];
+            // the node's density as the density pass forms it from the stored values
+            R r = R(0);
+#pragma unroll
+            for (int i = 0; i < Q; i++) r += P::ld(f + (size_t)(cc * Q + i) * N + n, R(wq(i)) * ref);
+            rs[cc] = r;
+        }
+        psi[n] = psi_of(rs[0], bx.psi_kind);
+        psi[N + n] = psi_of(rs[1], bx.psi_kind);
+        if (bx.psi_kind != 0) {
+            rho[n] = rs[0];
+            rho[N + n] = rs[1];
         }
         acc[0] -= jm[0];
         acc[1] -= jm[1];
@@ -522,6 +544,7 @@ __device__ inline void killfill_node(const Box& bx, typename P::S* __restrict__ 
 template <class P>
 __device__ inline void killfill_body(const Box& bx, typename P::S* __restrict__ f,
                                      const uint32_t* __restrict__ own_old, const uint32_t* __restrict__ own_new,
+                                     typename P::R* __restrict__ psi, typename P::R* __restrict__ rho,
                                      const double* __restrict__ part, int cap, int kext, double* __restrict__ kpart,
                                      double* __restrict__ counters, int* __restrict__ health, int p) {
     const int Ls[3] = {bx.nx, bx.ny, bx.nz};
@@ -572,8 +595,8 @@ __device__ inline void killfill_body(const Box& bx, typename P::S* __restrict__ 
             const bool kill = (oo[k] == OWN_FLUID && on[k] == (uint32_t)p);
             const bool fill = (oo[k] == (uint32_t)p && on[k] == OWN_FLUID);
             if (kill || fill)
-                killfill_node<P>(bx, f, own_old, own_new, part, cap, counters, p, kill, xs[k], ys[k], zs[k], nn[k], Xn,
-                                 acc);
+                killfill_node<P>(bx, f, own_old, own_new, psi, rho, part, cap, counters, p, kill, xs[k], ys[k], zs[k],
+                                 nn[k], Xn, acc);
         }
     }
     double tot[6];
@@ -584,11 +607,11 @@ __device__ inline void killfill_body(const Box& bx, typename P::S* __restrict__ 
 template <class P>
 __global__ __launch_bounds__(kPB) void k_killfill(Box bx, typename P::S* __restrict__ f,
                                                   const uint32_t* __restrict__ own_old,
-                                                  const uint32_t* __restrict__ own_new,
-                                                  const double* __restrict__ part, int cap, int kext,
-                                                  double* __restrict__ kpart, double* __restrict__ counters,
-                                                  int* __restrict__ health) {
-    killfill_body<P>(bx, f, own_old, own_new, part, cap, kext, kpart, counters, health, blockIdx.x);
+                                                  const uint32_t* __restrict__ own_new, typename P::R* __restrict__ psi,
+                                                  typename P::R* __restrict__ rho, const double* __restrict__ part,
+                                                  int cap, int kext, double* __restrict__ kpart,
+                                                  double* __restrict__ counters, int* __restrict__ health) {
+    killfill_body<P>(bx, f, own_old, own_new, psi, rho, part, cap, kext, kpart, counters, health, blockIdx.x);
 }
 // Batched: item = (system, particle); owner copy `oo` is the old map, 1 - oo
 // the new one; populations copy `fd`.
@@ -597,8 +620,8 @@ __global__ __launch_bounds__(kPB) void k_killfill_batch(const SysDev* __restrict
                                                         const WorkItem* __restrict__ items, int oo, int fd) {
     const WorkItem w = items[blockIdx.x];
     const SysDev& d = sd[w.sys];
-    killfill_body<P>(d.box, (typename P::S*)d.f[fd], d.owner[oo], d.owner[1 - oo], d.part, d.cap, d.kext, d.kpart,
-                     d.counters, d.health, w.local);
+    killfill_body<P>(d.box, (typename P::S*)d.f[fd], d.owner[oo], d.owner[1 - oo], (typename P::R*)d.psi,
+                     (typename P::R*)d.rho, d.part, d.cap, d.kext, d.kpart, d.counters, d.health, w.local);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -675,8 +698,8 @@ hipError_t launch_killfill(lb_handle* h) {
     const int kext = kill_ext(h);
     LBE_PDISPATCH(h->prm.precision,
                   hipLaunchKernelGGL(k_killfill<P>, dim3(h->np), dim3(kPB), 0, h->stream, h->box,
-                                     (typename P::S*)fn, oo, on, h->b.part, h->cap, kext, h->b.kpart, h->b.counters,
-                                     h->b.health));
+                                     (typename P::S*)fn, oo, on, (typename P::R*)h->b.psi, (typename P::R*)h->b.rho,
+                                     h->b.part, h->cap, kext, h->b.kpart, h->b.counters, h->b.health));
     return hipGetLastError();
 }
 

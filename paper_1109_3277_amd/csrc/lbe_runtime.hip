@@ -153,8 +153,13 @@ hipError_t mark(lb_handle* h, int phase, bool start) {
         LBE_HIP(h, mark(h, ph, false));         \
     } while (0)
 
+// One time step. With particles, the densities of the next step are formed
+// right after the re-rasterisation (on nodes fluid before and after), so that
+// kill / fill reads its neighbours' densities instead of summing their
+// populations; the next step then starts from them.
 int enqueue_step(lb_handle* h) {
-    LBE_PHASE(h, 0, launch_density(h));
+    if (!h->dens_ready) LBE_PHASE(h, 0, launch_density(h, h->cur, h->ocur, -1));
+    h->dens_ready = false;
     if (h->np > 0) LBE_PHASE(h, 1, launch_shell(h));
     LBE_PHASE(h, 2, launch_fused(h));
     if (h->np > 0) {
@@ -165,8 +170,10 @@ int enqueue_step(lb_handle* h) {
         LBE_HIP(h, launch_clear_owner(h, on));
         LBE_HIP(h, launch_raster(h, on, 0, h->np));
         LBE_HIP(h, mark(h, 5, false));
+        LBE_PHASE(h, 0, launch_density(h, 1 - h->cur, 1 - h->ocur, h->ocur));
         LBE_PHASE(h, 6, launch_killfill(h));
         h->ocur = 1 - h->ocur;
+        h->dens_ready = true;
     }
     h->cur = 1 - h->cur;
     return LB_OK;
@@ -258,6 +265,7 @@ int lb_init_fields(lb_handle* h, const double* rho_a, const double* rho_b, const
     LBE_HIP(h, launch_init(h, d_ra, d_rb, d_u));
     LBE_HIP(h, hipStreamSynchronize(h->stream));
     h->inited = true;
+    h->dens_ready = false;
     batch_touch(h);
     return LB_OK;
 }
@@ -332,6 +340,7 @@ int lb_add_ellipsoids(lb_handle* h, int32_t n, const double* radii, const double
     LBE_HIP(h, launch_raster(h, h->b.owner[h->ocur], first, n));
     LBE_HIP(h, launch_remove_covered(h));
     LBE_HIP(h, hipStreamSynchronize(h->stream));
+    h->dens_ready = false;
     batch_touch(h);
     return LB_OK;
 }
@@ -517,6 +526,7 @@ int lb_load_state(lb_handle* h, const void* host_buf, size_t bytes) {
     h->rmax = hdr[5];
     h->has_solid = h->np > 0;
     h->inited = true;
+    h->dens_ready = false;
     batch_touch(h);
     return LB_OK;
 }
