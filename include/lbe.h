@@ -165,7 +165,9 @@ int lb_probe_copy(void* dev_dst, const void* dev_src, size_t bytes, void* hip_st
 /* ---- Batches: many independent periodic systems advanced together.
  * The method per system is unchanged (same equations, same arithmetic: a
  * system stepped in a batch ends bit for bit where a lone handle with the
- * same parameters and inputs ends). Each kernel phase is one launch over all
+ * same parameters and inputs ends; the one exception is a particle-free box
+ * in 4- or 2-byte storage whose width is 64, 128, 256 or 512, which a lone
+ * handle runs with its row kernel and a batch with tiles, equal to rounding). Each kernel phase is one launch over all
  * systems, and the step sequence runs as a HIP graph of two steps on the
  * batch's own stream (ordered after and before the creation stream with
  * events), so many small systems fill the GPU and launch cost is paid once

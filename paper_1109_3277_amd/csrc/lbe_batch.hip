@@ -52,6 +52,7 @@ void item_capacity(const lb_params& p, size_t cap[BI_COUNT]) {
     }
     cap[BI_NODE] = (N + 255) / 256;
     cap[BI_TILE] = tiles;
+    cap[BI_TILE_PLAIN] = tiles;
     cap[BI_PART] = (size_t)std::max(p.max_particles, 0);
 }
 
@@ -131,7 +132,6 @@ int refresh(lb_handle* h) {
         d.slist = q->b.slist;
         d.scount = q->b.scount;
         d.kpart = q->b.kpart;
-        d.counters = q->b.counters;
         d.health = q->b.health;
         d.cap = q->cap;
         d.np = q->np;
@@ -141,7 +141,7 @@ int refresh(lb_handle* h) {
         const int nnode = (int)((q->box.N + 255) / 256);
         const int ntile = d.tiles_x * d.tiles_y * q->box.nz;
         for (int i = 0; i < nnode; i++) B->h_items[BI_NODE].push_back({s, i});
-        for (int i = 0; i < ntile; i++) B->h_items[BI_TILE].push_back({s, i});
+        for (int i = 0; i < ntile; i++) B->h_items[q->has_solid ? BI_TILE : BI_TILE_PLAIN].push_back({s, i});
         for (int i = 0; i < q->np; i++) B->h_items[BI_PART].push_back({s, i});
     }
     for (int k = 0; k < BI_COUNT; k++)

@@ -47,6 +47,7 @@ enum PField : int {
     JX, JY, JZ, HX, HY, HZ,    // pending kill/fill impulses
     LFX, LFY, LFZ, LTX, LTY, LTZ,  // totals applied in the last body update
     OX, OY, OZ,                // centre before the last body update
+    KMASS, FMASS,              // fluid mass killed / filled by this particle (cumulative)
     NPFIELD
 };
 
@@ -190,7 +191,6 @@ struct SysDev {
     uint2* slist;
     int* scount;
     double* kpart;
-    double* counters;
     int* health;
     int cap, np;
     int tiles_x, tiles_y;
@@ -204,19 +204,20 @@ struct WorkItem {
     int local;
 };
 
-// Deterministic block sum of 6 doubles (every thread of the block calls it;
+// Deterministic block sum of K doubles (every thread of the block calls it;
 // blockDim.x is a multiple of 64). The result is valid in thread 0.
-__device__ inline void block_sum6(double v[6], double out[6]) {
-    __shared__ double sh[16][6];
+template <int K>
+__device__ inline void block_sum(double (&v)[K], double (&out)[K]) {
+    __shared__ double sh[16][K];
 #pragma unroll
-    for (int k = 0; k < 6; k++)
+    for (int k = 0; k < K; k++)
         for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     if (lane == 0)
-        for (int k = 0; k < 6; k++) sh[w][k] = v[k];
+        for (int k = 0; k < K; k++) sh[w][k] = v[k];
     __syncthreads();
     if (threadIdx.x == 0)
-        for (int k = 0; k < 6; k++) {
+        for (int k = 0; k < K; k++) {
             double s = 0.0;
             for (int j = 0; j < nw; j++) s += sh[j][k];
             out[k] = s;

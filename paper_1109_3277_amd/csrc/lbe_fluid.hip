@@ -335,15 +335,17 @@ __global__ __launch_bounds__(256, sizeof(typename P::R) == 8 ? 2 : 3) void k_fus
     fused_body<P, SOLID, BX, BY>(bx, fs, fd, psi, owner, part, cap, tiles_x, tiles_y,
                                  xcd_remap(blockIdx.x, gridDim.x));
 }
-// Batched: item = (system, tile); every system has solids. Items of one
-// system are contiguous, so the XCD remap keeps neighbouring tiles together.
-template <class P, int BX, int BY>
+// Batched: item = (system, tile); SOLID for the systems with particles.
+// Items of one system are contiguous, so the XCD remap keeps neighbouring
+// tiles together.
+template <class P, bool SOLID, int BX, int BY>
 __global__ __launch_bounds__(256, sizeof(typename P::R) == 8 ? 2 : 3) void k_fused_batch(
     const SysDev* __restrict__ sd, const WorkItem* __restrict__ items, int c, int o) {
     const WorkItem w = items[xcd_remap(blockIdx.x, gridDim.x)];
     const SysDev& d = sd[w.sys];
-    fused_body<P, true, BX, BY>(d.box, (const typename P::S*)d.f[c], (typename P::S*)d.f[1 - c],
-                                (const typename P::R*)d.psi, d.owner[o], d.part, d.cap, d.tiles_x, d.tiles_y, w.local);
+    fused_body<P, SOLID, BX, BY>(d.box, (const typename P::S*)d.f[c], (typename P::S*)d.f[1 - c],
+                                 (const typename P::R*)d.psi, d.owner[o], d.part, d.cap, d.tiles_x, d.tiles_y,
+                                 w.local);
 }
 
 // Row kernel for boxes without solids (nx a multiple of 64): a block holds
@@ -582,28 +584,21 @@ __global__ void k_stats_final(double* __restrict__ red, int nblocks) {
     for (int k = 0; k < 7; k++) red[nblocks * 8 + k] = t[k];
 }
 
-// Remove the fluid on nodes covered at particle placement; removed mass is
-// added to counters[0].
+// Remove the fluid on nodes covered at particle placement (the removed mass is
+// measured by fixed-order reductions before and after).
 template <class P>
 __global__ __launch_bounds__(256) void k_remove_covered(Box bx, typename P::S* __restrict__ f,
-                                                        const uint32_t* __restrict__ owner,
-                                                        double* __restrict__ counters) {
+                                                        const uint32_t* __restrict__ owner) {
     using R = typename P::R;
     const int64_t N = bx.N;
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N || owner[n] == OWN_FLUID) return;
-    double m = 0.0;
 #pragma unroll
     for (int c = 0; c < 2; c++) {
         const R ref = R(bx.rref[c]);
 #pragma unroll
-        for (int i = 0; i < Q; i++) {
-            typename P::S* p = f + (size_t)(c * Q + i) * N + n;
-            m += (double)P::ld(p, R(wq(i)) * ref);
-            P::st(p, R(0), R(wq(i)) * ref);
-        }
+        for (int i = 0; i < Q; i++) P::st(f + (size_t)(c * Q + i) * N + n, R(0), R(wq(i)) * ref);
     }
-    if (m != 0.0) unsafeAtomicAdd(counters, m);
 }
 
 __global__ void k_copy16(const uint4* __restrict__ a, uint4* __restrict__ b, size_t n) {
@@ -757,7 +752,7 @@ hipError_t launch_stats(lb_handle* h) {
 hipError_t launch_remove_covered(lb_handle* h) {
     LBE_DISPATCH(h->prm.precision,
                  hipLaunchKernelGGL(k_remove_covered<P>, dim3(nblk(h->box.N)), dim3(256), 0, h->stream, h->box,
-                                    (typename P::S*)h->b.f[h->cur], h->b.owner[h->ocur], h->b.counters));
+                                    (typename P::S*)h->b.f[h->cur], h->b.owner[h->ocur]));
     return hipGetLastError();
 }
 
@@ -794,19 +789,21 @@ hipError_t launch_batch_density(const BatchLaunch& bl, int precision, hipStream_
     return hipGetLastError();
 }
 
-template <class P>
+template <class P, bool SOLID>
 static void launch_batch_fused_t(const BatchLaunch& bl, hipStream_t st, int c, int o) {
+    const int k = SOLID ? BI_TILE : BI_TILE_PLAIN;
+    if (bl.n[k] == 0) return;
     if (bl.bx == 64)
-        hipLaunchKernelGGL((k_fused_batch<P, 64, 4>), dim3(bl.n[BI_TILE]), dim3(256), 0, st, bl.sys, bl.items[BI_TILE],
-                           c, o);
+        hipLaunchKernelGGL((k_fused_batch<P, SOLID, 64, 4>), dim3(bl.n[k]), dim3(256), 0, st, bl.sys, bl.items[k], c,
+                           o);
     else
-        hipLaunchKernelGGL((k_fused_batch<P, 32, 8>), dim3(bl.n[BI_TILE]), dim3(256), 0, st, bl.sys, bl.items[BI_TILE],
-                           c, o);
+        hipLaunchKernelGGL((k_fused_batch<P, SOLID, 32, 8>), dim3(bl.n[k]), dim3(256), 0, st, bl.sys, bl.items[k], c,
+                           o);
 }
 
 hipError_t launch_batch_fused(const BatchLaunch& bl, int precision, hipStream_t st, int c, int o) {
-    if (bl.n[BI_TILE] == 0) return hipSuccess;
-    LBE_DISPATCH(precision, (launch_batch_fused_t<P>(bl, st, c, o)));
+    LBE_DISPATCH(precision, (launch_batch_fused_t<P, true>(bl, st, c, o)));
+    LBE_DISPATCH(precision, (launch_batch_fused_t<P, false>(bl, st, c, o)));
     return hipGetLastError();
 }
 

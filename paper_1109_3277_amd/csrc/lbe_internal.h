@@ -21,9 +21,9 @@ struct Buffers {
     double* part = nullptr;            // particle table, NPFIELD x cap
     uint2* slist = nullptr;            // surface list segments, cap x nseg x 64 (node, link mask)
     int* scount = nullptr;             // entries per surface list segment, cap x nseg
-    double* kpart = nullptr;           // kill/fill impulse of the last step, cap x 6
+    double* kpart = nullptr;           // kill/fill impulse and masses of the last step, cap x 8
     double* red = nullptr;             // reduction partials, kRedBlocks x 8, then totals
-    double* counters = nullptr;        // [0] mass removed (cumulative), [1] kill mass, [2] fill mass
+    double* counters = nullptr;        // [0] fluid mass removed at particle placement (cumulative)
     int* health = nullptr;             // nonzero once a NaN / negative density was seen
 };
 
@@ -32,7 +32,9 @@ constexpr int kRedBlocks = 1024;       // fixed grid of the deterministic reduct
 struct BatchState;
 
 // Work-item lists of a batched launch, one per kind of block.
-enum BatchItems { BI_NODE = 0, BI_TILE, BI_PART, BI_COUNT };
+// BI_TILE: tiles of systems with particles; BI_TILE_PLAIN: tiles of systems
+// without (they run the kernel a lone handle would run).
+enum BatchItems { BI_NODE = 0, BI_TILE, BI_TILE_PLAIN, BI_PART, BI_COUNT };
 struct BatchLaunch {
     const SysDev* sys = nullptr;
     const WorkItem* items[BI_COUNT] = {};

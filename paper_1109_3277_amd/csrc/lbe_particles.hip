@@ -282,7 +282,7 @@ __device__ inline void linkforce_body(const Box& bx, const typename P::S* __rest
         __syncthreads();  // s_pre / s_wsum are rewritten by the next chunk
     }
     double tot[6];
-    block_sum6(acc, tot);
+    block_sum<6>(acc, tot);
     if (tid == 0) {
         const int fld[6] = {FX, FY, FZ, TX, TY, TZ};
         for (int k = 0; k < 6; k++) part[fld[k] * cap + p] = tot[k];
@@ -316,15 +316,17 @@ __global__ __launch_bounds__(256) void k_linkforce_batch(const SysDev* __restric
 __device__ inline void bodies_body(const Box& bx, double* __restrict__ part, int cap,
                                    const double* __restrict__ kpart, int nk, int p) {
     const int lane = threadIdx.x;
-    double Jk[6] = {0, 0, 0, 0, 0, 0};
+    double Jk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int s = lane; s < nk; s += 64)
-        for (int k = 0; k < 6; k++) Jk[k] += kpart[((size_t)p * nk + s) * 6 + k];
+        for (int k = 0; k < 8; k++) Jk[k] += kpart[((size_t)p * nk + s) * 8 + k];
 #pragma unroll
-    for (int k = 0; k < 6; k++)
+    for (int k = 0; k < 8; k++)
         for (int off = 32; off > 0; off >>= 1) Jk[k] += __shfl_down(Jk[k], off, 64);
     if (lane != 0) return;
     double* P = part;
 #define F_(k) P[(k) * cap + p]
+    F_(KMASS) += Jk[6];
+    F_(FMASS) += Jk[7];
     const double Fl[6] = {F_(FX), F_(FY), F_(FZ), F_(TX), F_(TY), F_(TZ)};
     const double J[3] = {F_(JX) + Jk[0], F_(JY) + Jk[1], F_(JZ) + Jk[2]};
     const double H[3] = {F_(HX) + Jk[3], F_(HY) + Jk[4], F_(HZ) + Jk[5]};
@@ -416,14 +418,14 @@ __global__ __launch_bounds__(64) void k_bodies_batch(const SysDev* __restrict__ 
 __global__ void k_fold_impulses(double* __restrict__ part, int cap, int np, double* __restrict__ kpart, int nk) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
-    double J[6] = {0, 0, 0, 0, 0, 0};
+    double J[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int s = 0; s < nk; s++)
-        for (int k = 0; k < 6; k++) {
-            J[k] += kpart[((size_t)p * nk + s) * 6 + k];
-            kpart[((size_t)p * nk + s) * 6 + k] = 0.0;
+        for (int k = 0; k < 8; k++) {
+            J[k] += kpart[((size_t)p * nk + s) * 8 + k];
+            kpart[((size_t)p * nk + s) * 8 + k] = 0.0;
         }
-    const int fld[6] = {JX, JY, JZ, HX, HY, HZ};
-    for (int k = 0; k < 6; k++) part[fld[k] * cap + p] += J[k];
+    const int fld[8] = {JX, JY, JZ, HX, HY, HZ, KMASS, FMASS};
+    for (int k = 0; k < 8; k++) part[fld[k] * cap + p] += J[k];
 }
 
 // ---------------------------------------------------------------- S8
@@ -445,15 +447,15 @@ __device__ inline R feq_p(int i, R rho, R ux, R uy, R uz) {
 //                      the node's Psi (and rho) follow from the stored f.
 // Each changing node is handled by exactly one thread (of its owner's block).
 // One block loops over the union box, four nodes per thread in flight; the
-// block's fixed-order sum is the particle's impulse of this step. A union box
+// block's fixed-order sum is the particle's impulse (and killed / filled
+// mass) of this step. A union box
 // wider than kext (a move of more than two spacings) raises health bit 2.
 template <class P>
 __device__ inline void killfill_node(const Box& bx, typename P::S* __restrict__ f,
                                      const uint32_t* __restrict__ own_old, const uint32_t* __restrict__ own_new,
                                      typename P::R* __restrict__ psi, typename P::R* __restrict__ rho,
-                                     const double* __restrict__ part, int cap, double* __restrict__ counters, int p,
-                                     bool kill, int x, int y, int z, int64_t n, const double (&Xn)[3],
-                                     double (&acc)[6]) {
+                                     const double* __restrict__ part, int cap, int p, bool kill, int x, int y,
+                                     int z, int64_t n, const double (&Xn)[3], double (&acc)[8]) {
     using R = typename P::R;
     const int64_t N = bx.N;
     const int Ls[3] = {bx.nx, bx.ny, bx.nz};
@@ -480,8 +482,7 @@ __device__ inline void killfill_node(const Box& bx, typename P::S* __restrict__ 
         acc[3] += r[1] * j[2] - r[2] * j[1];
         acc[4] += r[2] * j[0] - r[0] * j[2];
         acc[5] += r[0] * j[1] - r[1] * j[0];
-        unsafeAtomicAdd(counters + 0, m);
-        unsafeAtomicAdd(counters + 1, m);
+        acc[6] += m;
     } else {
         const double V[3] = {part[VX * cap + p], part[VY * cap + p], part[VZ * cap + p]};
         const double W[3] = {part[WX * cap + p], part[WY * cap + p], part[WZ * cap + p]};
@@ -536,8 +537,7 @@ __device__ inline void killfill_node(const Box& bx, typename P::S* __restrict__ 
         acc[3] -= r[1] * jm[2] - r[2] * jm[1];
         acc[4] -= r[2] * jm[0] - r[0] * jm[2];
         acc[5] -= r[0] * jm[1] - r[1] * jm[0];
-        unsafeAtomicAdd(counters + 0, -(rn[0] + rn[1]));
-        unsafeAtomicAdd(counters + 2, rn[0] + rn[1]);
+        acc[7] += rn[0] + rn[1];
     }
 }
 
@@ -546,9 +546,9 @@ __device__ inline void killfill_body(const Box& bx, typename P::S* __restrict__ 
                                      const uint32_t* __restrict__ own_old, const uint32_t* __restrict__ own_new,
                                      typename P::R* __restrict__ psi, typename P::R* __restrict__ rho,
                                      const double* __restrict__ part, int cap, int kext, double* __restrict__ kpart,
-                                     double* __restrict__ counters, int* __restrict__ health, int p) {
+                                     int* __restrict__ health, int p) {
     const int Ls[3] = {bx.nx, bx.ny, bx.nz};
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // J, H, killed mass, filled mass
     int lo[3] = {0, 0, 0}, sz[3] = {0, 0, 0};
     bool ok = true;
     const double Xn[3] = {part[PX * cap + p], part[PY * cap + p], part[PZ * cap + p]};
@@ -595,14 +595,14 @@ __device__ inline void killfill_body(const Box& bx, typename P::S* __restrict__ 
             const bool kill = (oo[k] == OWN_FLUID && on[k] == (uint32_t)p);
             const bool fill = (oo[k] == (uint32_t)p && on[k] == OWN_FLUID);
             if (kill || fill)
-                killfill_node<P>(bx, f, own_old, own_new, psi, rho, part, cap, counters, p, kill, xs[k], ys[k], zs[k],
-                                 nn[k], Xn, acc);
+                killfill_node<P>(bx, f, own_old, own_new, psi, rho, part, cap, p, kill, xs[k], ys[k], zs[k], nn[k], Xn,
+                                 acc);
         }
     }
-    double tot[6];
-    block_sum6(acc, tot);
+    double tot[8];
+    block_sum<8>(acc, tot);
     if (threadIdx.x == 0)
-        for (int k = 0; k < 6; k++) kpart[(size_t)p * 6 + k] = tot[k];
+        for (int k = 0; k < 8; k++) kpart[(size_t)p * 8 + k] = tot[k];
 }
 template <class P>
 __global__ __launch_bounds__(kPB) void k_killfill(Box bx, typename P::S* __restrict__ f,
@@ -610,8 +610,8 @@ __global__ __launch_bounds__(kPB) void k_killfill(Box bx, typename P::S* __restr
                                                   const uint32_t* __restrict__ own_new, typename P::R* __restrict__ psi,
                                                   typename P::R* __restrict__ rho, const double* __restrict__ part,
                                                   int cap, int kext, double* __restrict__ kpart,
-                                                  double* __restrict__ counters, int* __restrict__ health) {
-    killfill_body<P>(bx, f, own_old, own_new, psi, rho, part, cap, kext, kpart, counters, health, blockIdx.x);
+                                                  int* __restrict__ health) {
+    killfill_body<P>(bx, f, own_old, own_new, psi, rho, part, cap, kext, kpart, health, blockIdx.x);
 }
 // Batched: item = (system, particle); owner copy `oo` is the old map, 1 - oo
 // the new one; populations copy `fd`.
@@ -621,7 +621,7 @@ __global__ __launch_bounds__(kPB) void k_killfill_batch(const SysDev* __restrict
     const WorkItem w = items[blockIdx.x];
     const SysDev& d = sd[w.sys];
     killfill_body<P>(d.box, (typename P::S*)d.f[fd], d.owner[oo], d.owner[1 - oo], (typename P::R*)d.psi,
-                     (typename P::R*)d.rho, d.part, d.cap, d.kext, d.kpart, d.counters, d.health, w.local);
+                     (typename P::R*)d.rho, d.part, d.cap, d.kext, d.kpart, d.health, w.local);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -699,7 +699,7 @@ hipError_t launch_killfill(lb_handle* h) {
     LBE_PDISPATCH(h->prm.precision,
                   hipLaunchKernelGGL(k_killfill<P>, dim3(h->np), dim3(kPB), 0, h->stream, h->box,
                                      (typename P::S*)fn, oo, on, (typename P::R*)h->b.psi, (typename P::R*)h->b.rho,
-                                     h->b.part, h->cap, kext, h->b.kpart, h->b.counters, h->b.health));
+                                     h->b.part, h->cap, kext, h->b.kpart, h->b.health));
     return hipGetLastError();
 }
 

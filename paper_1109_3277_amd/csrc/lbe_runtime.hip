@@ -60,7 +60,7 @@ Layout layout_of(const lb_params* p) {
     const size_t nseg = (size_t)surf_segments(raster_extent(p->nx, p->ny, p->nz, rmax));
     L.slist = p->max_particles > 0 ? align_up(cap * nseg * 64 * sizeof(uint2)) : 0;
     L.scount = p->max_particles > 0 ? align_up(cap * nseg * sizeof(int)) : 0;
-    L.kpart = align_up(cap * 6 * sizeof(double));
+    L.kpart = align_up(cap * 8 * sizeof(double));
     L.red = align_up((kRedBlocks + 1) * 8 * sizeof(double));
     L.counters = align_up(8 * sizeof(double));
     L.health = align_up(sizeof(int));
@@ -335,10 +335,21 @@ int lb_add_ellipsoids(lb_handle* h, int32_t n, const double* radii, const double
     for (int fld = 0; fld < NPFIELD; fld++)
         LBE_HIP(h, hipMemcpyAsync(h->b.part + (size_t)fld * h->cap + first, &t[(size_t)fld * n], n * sizeof(double),
                                   hipMemcpyHostToDevice, h->stream));
+    // fluid mass removed under the new particles: fixed-order totals before
+    // and after the removal
+    double before[7], after[7], removed = 0.0;
+    LBE_HIP(h, launch_stats(h));
+    LBE_HIP(h, hipMemcpyAsync(before, h->b.red + kRedBlocks * 8, 7 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     h->np += n;
     h->has_solid = true;
     LBE_HIP(h, launch_raster(h, h->b.owner[h->ocur], first, n));
     LBE_HIP(h, launch_remove_covered(h));
+    LBE_HIP(h, launch_stats(h));
+    LBE_HIP(h, hipMemcpyAsync(after, h->b.red + kRedBlocks * 8, 7 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    LBE_HIP(h, hipMemcpyAsync(&removed, h->b.counters, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    LBE_HIP(h, hipStreamSynchronize(h->stream));
+    removed += (before[0] + before[1]) - (after[0] + after[1]);
+    LBE_HIP(h, hipMemcpyAsync(h->b.counters, &removed, sizeof(double), hipMemcpyHostToDevice, h->stream));
     LBE_HIP(h, hipStreamSynchronize(h->stream));
     h->dens_ready = false;
     batch_touch(h);
@@ -426,16 +437,29 @@ int lb_stats(lb_handle* h, double out[8]) {
     LBE_NOT_BATCH(h);
     if (!h->inited) return fail(h, LB_ESTATE, "fields not initialised");
     LBE_HIP(h, launch_stats(h));
-    double t[7], c[3];
+    double t[7], c0 = 0.0;
+    std::vector<double> km((size_t)h->np), fm((size_t)h->np), kp((size_t)h->np * 8);
     LBE_HIP(h, hipMemcpyAsync(t, h->b.red + kRedBlocks * 8, 7 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    LBE_HIP(h, hipMemcpyAsync(c, h->b.counters, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    LBE_HIP(h, hipMemcpyAsync(&c0, h->b.counters, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    if (h->np > 0) {
+        LBE_HIP(h, hipMemcpyAsync(km.data(), h->b.part + (size_t)KMASS * h->cap, h->np * sizeof(double),
+                                  hipMemcpyDeviceToHost, h->stream));
+        LBE_HIP(h, hipMemcpyAsync(fm.data(), h->b.part + (size_t)FMASS * h->cap, h->np * sizeof(double),
+                                  hipMemcpyDeviceToHost, h->stream));
+        LBE_HIP(h, hipMemcpyAsync(kp.data(), h->b.kpart, kp.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                  h->stream));
+    }
     LBE_HIP(h, hipStreamSynchronize(h->stream));
+    // removed at placement, plus killed minus filled by each particle (the
+    // last step's amounts still wait in its kill/fill slot), in order
+    double removed = c0;
+    for (int k = 0; k < h->np; k++) removed += (km[k] + kp[8 * k + 6]) - (fm[k] + kp[8 * k + 7]);
     out[0] = t[0];
     out[1] = t[1];
     out[2] = t[2];
     out[3] = t[3];
     out[4] = t[4];
-    out[5] = c[0];
+    out[5] = removed;
     out[6] = t[5];
     out[7] = t[6];
     return LB_OK;

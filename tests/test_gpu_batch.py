@@ -131,3 +131,31 @@ def test_full_ensemble_64_systems_equals_lone_handles():
         g = run_gpu(s, 20, "fp32")
         assert _same(b[k], g), f"system {k} {s.dims} differs"
         del g
+
+
+def test_batch_mixed_kinds_equals_lone_handles():
+    """A batch mixing a particle-free system, a Psi = rho system and a system
+    with several moving particles of both colours matches lone handles bit for
+    bit, stats included."""
+    from paper_1109_3277_amd.binding import Lattice
+    from paper_1109_3277_amd.workloads import System, layered_fields, uniform_fields
+
+    a = W.spinodal_system(dims=(40, 24, 16), seed=21)
+    ra, rb = layered_fields((32, 32, 48), 22)
+    b = System("psi-rho", (32, 32, 48), 1.0, 0.08, ra, rb, np.array([[6.0, 3.0]]), np.array([[16.0, 16.0, 23.5]]),
+               np.array([[0.9, 0.1, 0.3, 0.2]]), np.array([0.2]), np.array([2.0]), psi_kind=0)
+    rc, rd = uniform_fields((48, 40, 32), 23, 0.7, 0.7, 0.01)
+    c = System("several", (48, 40, 32), 1.0, 0.08, rc, rd, np.array([[5.0, 3.0], [4.0, 4.0], [3.0, 5.0]]),
+               np.array([[10.0, 10.0, 10.0], [30.0, 25.0, 16.0], [12.0, 30.0, 24.0]]),
+               np.array([[1.0, 0, 0, 0], [0.8, 0.2, -0.1, 0.5], [0.3, 0.9, 0.2, -0.1]]),
+               np.array([0.3, -0.3, 0.0]), np.array([1.5, 1.5, 1.5]))
+    systems = [a, b, c]
+    bt = _batch(systems, "fp64")
+    lone = [run_gpu(s, 0, "fp64") for s in systems]
+    for n in (3, 2, 5):
+        bt.step(n)
+        for g in lone:
+            g.step(n)
+        for k in range(3):
+            assert _same(bt[k], lone[k]), f"system {k} differs"
+            assert np.array_equal(bt[k].stats(), lone[k].stats())
