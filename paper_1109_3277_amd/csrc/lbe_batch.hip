@@ -131,6 +131,8 @@ int refresh(lb_handle* h) {
         d.part = q->b.part;
         d.slist = q->b.slist;
         d.scount = q->b.scount;
+        d.rec = q->b.rec;
+        d.pfast = q->b.pfast;
         d.kpart = q->b.kpart;
         d.health = q->b.health;
         d.cap = q->cap;
@@ -172,7 +174,7 @@ hipError_t enqueue_batch_step(BatchState* B, hipStream_t st, int c) {
     hipError_t e;
     if ((e = launch_batch_shell(bl, prec, st, c)) != hipSuccess) return e;
     if ((e = launch_batch_fused(bl, prec, st, c, c)) != hipSuccess) return e;
-    if ((e = launch_batch_forces(bl, prec, st, 1 - c)) != hipSuccess) return e;
+    if ((e = launch_batch_forces(bl, st)) != hipSuccess) return e;
     if ((e = launch_batch_bodies(bl, st)) != hipSuccess) return e;
     if ((e = launch_batch_clear_owner(bl, st, 1 - c)) != hipSuccess) return e;
     if ((e = launch_batch_raster(bl, st, 1 - c)) != hipSuccess) return e;

@@ -139,12 +139,10 @@ __device__ inline R psi_ratio(R r, int kind) {
     return -expm1(-r) / r;
 }
 
-// Bounding box of particle p: first node lo[d] and extent sz[d] per axis;
-// false if the particle state is not usable (then nothing is touched).
-__device__ inline bool particle_box(const Box& bx, const double* part, int cap, int p, int lo[3], int sz[3]) {
-    const double X[3] = {part[PX * cap + p], part[PY * cap + p], part[PZ * cap + p]};
-    const double rpar = part[RPAR * cap + p], rperp = part[RPERP * cap + p];
-    const double rb = rpar > rperp ? rpar : rperp;
+// Bounding box of a particle with centre X and bounding radius rb: first
+// node lo[d] and extent sz[d] per axis; false if the state is not usable
+// (then nothing is touched).
+__device__ inline bool box_of(const Box& bx, const double X[3], double rb, int lo[3], int sz[3]) {
     const int Ls[3] = {bx.nx, bx.ny, bx.nz};
     for (int d = 0; d < 3; d++) {
         if (!isfinite(X[d]) || !(rb < 0.5 * Ls[d])) return false;
@@ -152,6 +150,29 @@ __device__ inline bool particle_box(const Box& bx, const double* part, int cap, 
         sz[d] = max(0, min((int)floor(X[d] + rb) - lo[d] + 1, Ls[d]));
     }
     return true;
+}
+__device__ inline double bound_radius(const double* part, int cap, int p) {
+    const double rpar = part[RPAR * cap + p], rperp = part[RPERP * cap + p];
+    return rpar > rperp ? rpar : rperp;
+}
+__device__ inline bool particle_box(const Box& bx, const double* part, int cap, int p, int lo[3], int sz[3]) {
+    const double X[3] = {part[PX * cap + p], part[PY * cap + p], part[PZ * cap + p]};
+    return box_of(bx, X, bound_radius(part, cap, p), lo, sz);
+}
+
+// Packed copy of what the fused kernel reads of a particle: kPF doubles per
+// particle (one 128-byte line), centre, velocity, angular velocity and
+// bounding radius, so that a wave reads a particle with one scalar load.
+// Rewritten whenever the particle table changes (body update, placement,
+// state load).
+constexpr int kPF = 16;
+enum PFastField : int { PF_X = 0, PF_V = 3, PF_W = 6, PF_RB = 9 };
+__device__ inline void pack_fast(const double* part, int cap, int p, double* __restrict__ pfast) {
+    double* o = pfast + (size_t)p * kPF;
+    const int src[9] = {PX, PY, PZ, VX, VY, VZ, WX, WY, WZ};
+    for (int k = 0; k < 9; k++) o[k] = part[src[k] * cap + p];
+    o[PF_RB] = bound_radius(part, cap, p);
+    for (int k = PF_RB + 1; k < kPF; k++) o[k] = 0.0;
 }
 
 // Tiles of the fused kernel: BX x BY nodes of one xy-plane per 256-thread
@@ -168,6 +189,30 @@ constexpr int kPB = 256;
 __host__ __device__ inline int surf_segments(int ext) {
     const int cells = ext * ext * ext;
     return (kPB / 64) * ((cells + kPB - 1) / kPB);
+}
+
+// Link records of a particle: one record of kRec doubles per node of its
+// record box (its bounding box grown by one node on every side, each edge at
+// most the lattice edge; x fastest). Slot i - 1 of the record of fluid node n
+// holds the momentum exchange 2 f*_i(n) + C of the link n -> n + c_i, summed
+// over both components, when n + c_i is a node of the particle; only the
+// slots of the current step's links are live.
+constexpr int kRec = 18;
+
+// Record cell of node xyz for a particle whose bounding box is (lo, sz), or
+// -1 when the node lies outside the record box.
+__device__ inline int rec_cell(const int xyz[3], const int lo[3], const int sz[3], const int Ls[3]) {
+    int off[3], esz[3];
+    bool in = true;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        int v = xyz[d] - (lo[d] - 1);  // in (-L, 2L) for a centre in [0, L) and rb < L / 2
+        v = v < 0 ? v + Ls[d] : (v >= Ls[d] ? v - Ls[d] : v);
+        esz[d] = min(sz[d] + 2, Ls[d]);
+        off[d] = v;
+        in = in && (unsigned)v < (unsigned)esz[d];
+    }
+    return in ? (off[2] * esz[1] + off[1]) * esz[0] + off[0] : -1;
 }
 
 // Node (ix, iy, iz) of box index t in a box of sz[0] x sz[1] x sz[2].
@@ -190,6 +235,8 @@ struct SysDev {
     double* part;
     uint2* slist;
     int* scount;
+    double* rec;
+    double* pfast;
     double* kpart;
     int* health;
     int cap, np;

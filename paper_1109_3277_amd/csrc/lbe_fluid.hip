@@ -90,9 +90,9 @@ __global__ __launch_bounds__(256) void k_density_batch(const SysDev* __restrict_
 // body the surface velocity at the link midpoint, V + W x (r_n + c_i/2), has
 // the same projection on c_i as U_n = V + W x r_n at the node (W x c_i is
 // normal to c_i), so C needs one U_n per node and particle. The particle's
-// share (2 f*_i + C) c_i of Eq. (5) is not summed here: f'_ibar(n) is stored
-// and equals f*_i + C, so k_linkforce recovers it afterwards as
-// (2 f'_ibar(n) - C) c_i from the solid side of each link.
+// share (2 f*_i + C) c_i of Eq. (5) is not summed here: each link writes
+// 2 f*_i + C (both components) into slot i of node n's record of that
+// particle; k_linkforce sums the records.
 
 // Moments, Shan-Chen velocity shift and BGK relaxation of one node, in place
 // on f0 / f1 (component A / B). q0[i], q1[i]: Psi^A, Psi^B of neighbour i.
@@ -152,7 +152,8 @@ __device__ inline void collide_node(const Box& bx, typename P::R (&f0)[Q], typen
 template <class P, bool SOLID, int BX, int BY>
 __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict__ fs, typename P::S* __restrict__ fd,
                                   const typename P::R* __restrict__ psi, const uint32_t* __restrict__ owner,
-                                  const double* __restrict__ part, int cap, int tiles_x, int tiles_y, int tile) {
+                                  const double* __restrict__ pfast, double* __restrict__ rec, int rstride,
+                                  int tiles_x, int tiles_y, int tile) {
     using R = typename P::R;
     using S = typename P::S;
     static_assert(BX * BY == 256, "one node per thread");
@@ -264,38 +265,50 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
         uint32_t p2 = OWN_FLUID;
 #pragma unroll
         for (int i = 1; i < Q; i++) p2 = (p2 == OWN_FLUID && on[i] < OWN_WALL && on[i] != p1) ? on[i] : p2;
+        // per particle slot: surface velocity U_n at this node and the
+        // node's cell in the particle's link records
         double Ux2 = 0.0, Uy2 = 0.0, Uz2 = 0.0;
+        int cb2 = -1;
         bool need2 = p2 < OWN_WALL;
         double Ux1 = 0.0, Uy1 = 0.0, Uz1 = 0.0;
+        int cb1 = -1;
         bool need = p1 < OWN_WALL;
+        const int Ls[3] = {nx, ny, nz};
+        const int xyz[3] = {x, y, z};
         while (true) {
             const unsigned long long m = __ballot(need || need2);
             if (m == 0ull) break;
             const int lead = __ffsll(m) - 1;
             const uint32_t q = __builtin_amdgcn_readfirstlane(__shfl(need ? p1 : p2, lead, 64));
-            const double qX = part[PX * cap + q], qY = part[PY * cap + q], qZ = part[PZ * cap + q];
-            const double qVx = part[VX * cap + q], qVy = part[VY * cap + q], qVz = part[VZ * cap + q];
-            const double qWx = part[WX * cap + q], qWy = part[WY * cap + q], qWz = part[WZ * cap + q];
-            const double rx = minimg((double)x - qX, nx), ry = minimg((double)y - qY, ny),
-                         rz = minimg((double)z - qZ, nz);
+            const double* pq = pfast + (size_t)q * kPF;
+            const double qX[3] = {pq[PF_X], pq[PF_X + 1], pq[PF_X + 2]};
+            const double qVx = pq[PF_V], qVy = pq[PF_V + 1], qVz = pq[PF_V + 2];
+            const double qWx = pq[PF_W], qWy = pq[PF_W + 1], qWz = pq[PF_W + 2];
+            const double rx = minimg((double)x - qX[0], nx), ry = minimg((double)y - qX[1], ny),
+                         rz = minimg((double)z - qX[2], nz);
             const double ux = qVx + (qWy * rz - qWz * ry);
             const double uy = qVy + (qWz * rx - qWx * rz);
             const double uz = qVz + (qWx * ry - qWy * rx);
+            int lo[3], sz[3];
+            const int cb = box_of(bx, qX, pq[PF_RB], lo, sz) ? rec_cell(xyz, lo, sz, Ls) : -1;
             if (need && p1 == q) {
                 Ux1 = ux;
                 Uy1 = uy;
                 Uz1 = uz;
+                cb1 = cb;
                 need = false;
             }
             if (need2 && p2 == q) {
                 Ux2 = ux;
                 Uy2 = uy;
                 Uz2 = uz;
+                cb2 = cb;
                 need2 = false;
             }
         }
         // one store per direction: the push to (i, n + c_i) for a fluid
-        // target, the bounce-back value at (ibar, n) for a solid one
+        // target, the bounce-back value at (ibar, n) for a solid one; a
+        // particle link also writes its record slot
 #pragma unroll
         for (int i = 1; i < Q; i++) {
             const uint32_t o = on[i];
@@ -303,18 +316,26 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
             R C0 = R(0), C1 = R(0);
             if (o < OWN_WALL) {
                 double Ux = o == p1 ? Ux1 : Ux2, Uy = o == p1 ? Uy1 : Uy2, Uz = o == p1 ? Uz1 : Uz2;
+                int cb = o == p1 ? cb1 : cb2;
                 if (o != p1 && o != p2) {
-                    const double rx = minimg((double)x - part[PX * cap + o], nx);
-                    const double ry = minimg((double)y - part[PY * cap + o], ny);
-                    const double rz = minimg((double)z - part[PZ * cap + o], nz);
-                    const double wx = part[WX * cap + o], wy = part[WY * cap + o], wz = part[WZ * cap + o];
-                    Ux = part[VX * cap + o] + (wy * rz - wz * ry);
-                    Uy = part[VY * cap + o] + (wz * rx - wx * rz);
-                    Uz = part[VZ * cap + o] + (wx * ry - wy * rx);
+                    const double* po = pfast + (size_t)o * kPF;
+                    const double X[3] = {po[PF_X], po[PF_X + 1], po[PF_X + 2]};
+                    const double rx = minimg((double)x - X[0], nx);
+                    const double ry = minimg((double)y - X[1], ny);
+                    const double rz = minimg((double)z - X[2], nz);
+                    const double wx = po[PF_W], wy = po[PF_W + 1], wz = po[PF_W + 2];
+                    Ux = po[PF_V] + (wy * rz - wz * ry);
+                    Uy = po[PF_V + 1] + (wz * rx - wx * rz);
+                    Uz = po[PF_V + 2] + (wx * ry - wy * rx);
+                    int lo[3], sz[3];
+                    cb = box_of(bx, X, po[PF_RB], lo, sz) ? rec_cell(xyz, lo, sz, Ls) : -1;
                 }
                 const double cu = Ux * cx(i) + Uy * cy(i) + Uz * cz(i);
                 C0 = R(-6.0 * wq(i) * cu) * r0;
                 C1 = R(-6.0 * wq(i) * cu) * r1;
+                if (cb >= 0)
+                    rec[((size_t)o * rstride + cb) * kRec + (i - 1)] =
+                        2.0 * ((double)f0[i] + (double)f1[i]) + ((double)C0 + (double)C1);
             }
             const int b = opp(i);
             const uint32_t mb = sol ? nb : LBE_NB(i) * (uint32_t)sizeof(S);
@@ -331,8 +352,9 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
 template <class P, bool SOLID, int BX, int BY>
 __global__ __launch_bounds__(256, sizeof(typename P::R) == 8 ? 2 : 3) void k_fused(
     Box bx, const typename P::S* __restrict__ fs, typename P::S* __restrict__ fd, const typename P::R* __restrict__ psi,
-    const uint32_t* __restrict__ owner, const double* __restrict__ part, int cap, int tiles_x, int tiles_y) {
-    fused_body<P, SOLID, BX, BY>(bx, fs, fd, psi, owner, part, cap, tiles_x, tiles_y,
+    const uint32_t* __restrict__ owner, const double* __restrict__ pfast, double* __restrict__ rec, int rstride,
+    int tiles_x, int tiles_y) {
+    fused_body<P, SOLID, BX, BY>(bx, fs, fd, psi, owner, pfast, rec, rstride, tiles_x, tiles_y,
                                  xcd_remap(blockIdx.x, gridDim.x));
 }
 // Batched: item = (system, tile); SOLID for the systems with particles.
@@ -344,8 +366,8 @@ __global__ __launch_bounds__(256, sizeof(typename P::R) == 8 ? 2 : 3) void k_fus
     const WorkItem w = items[xcd_remap(blockIdx.x, gridDim.x)];
     const SysDev& d = sd[w.sys];
     fused_body<P, SOLID, BX, BY>(d.box, (const typename P::S*)d.f[c], (typename P::S*)d.f[1 - c],
-                                 (const typename P::R*)d.psi, d.owner[o], d.part, d.cap, d.tiles_x, d.tiles_y,
-                                 w.local);
+                                 (const typename P::R*)d.psi, d.owner[o], d.pfast, d.rec,
+                                 d.kext * d.kext * d.kext, d.tiles_x, d.tiles_y, w.local);
 }
 
 // Row kernel for boxes without solids (nx a multiple of 64): a block holds
@@ -715,12 +737,14 @@ static void launch_fused_t(lb_handle* h, const Tiles& tl, unsigned grid) {
         }
         return;
     }
+    const int ke = h->np > 0 ? kill_ext(h) : 0;
+    const int rstride = ke * ke * ke;
     if (tl.BX == 64)
         hipLaunchKernelGGL((k_fused<P, SOLID, 64, 4>), dim3(grid), dim3(256), 0, h->stream, h->box, fs, fd, ps, ow,
-                           h->b.part, h->cap, tl.tiles_x, tl.tiles_y);
+                           h->b.pfast, h->b.rec, rstride, tl.tiles_x, tl.tiles_y);
     else
         hipLaunchKernelGGL((k_fused<P, SOLID, 32, 8>), dim3(grid), dim3(256), 0, h->stream, h->box, fs, fd, ps, ow,
-                           h->b.part, h->cap, tl.tiles_x, tl.tiles_y);
+                           h->b.pfast, h->b.rec, rstride, tl.tiles_x, tl.tiles_y);
 }
 
 hipError_t launch_fused(lb_handle* h) {

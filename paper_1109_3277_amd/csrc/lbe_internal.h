@@ -21,6 +21,8 @@ struct Buffers {
     double* part = nullptr;            // particle table, NPFIELD x cap
     uint2* slist = nullptr;            // surface list segments, cap x nseg x 64 (node, link mask)
     int* scount = nullptr;             // entries per surface list segment, cap x nseg
+    double* rec = nullptr;             // link records, cap x kext^3 cells x kRec
+    double* pfast = nullptr;           // packed particle copy read by the fused kernel, cap x kPF
     double* kpart = nullptr;           // kill/fill impulse and masses of the last step, cap x 8
     double* red = nullptr;             // reduction partials, kRedBlocks x 8, then totals
     double* counters = nullptr;        // [0] fluid mass removed at particle placement (cumulative)
@@ -85,7 +87,7 @@ namespace lbe {
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
-    size_t f, psi, rho, owner, part, slist, scount, kpart, red, counters, health, total;
+    size_t f, psi, rho, owner, part, pfast, slist, scount, rec, kpart, red, counters, health, total;
 };
 bool params_ok(const lb_params* p, std::string* why);
 Layout layout_of(const lb_params* p);
@@ -104,7 +106,7 @@ hipError_t launch_batch_density(const BatchLaunch& bl, int precision, hipStream_
 hipError_t launch_batch_fused(const BatchLaunch& bl, int precision, hipStream_t st, int c, int o);
 hipError_t launch_batch_clear_owner(const BatchLaunch& bl, hipStream_t st, int o);
 hipError_t launch_batch_shell(const BatchLaunch& bl, int precision, hipStream_t st, int o);
-hipError_t launch_batch_forces(const BatchLaunch& bl, int precision, hipStream_t st, int d);
+hipError_t launch_batch_forces(const BatchLaunch& bl, hipStream_t st);
 hipError_t launch_batch_bodies(const BatchLaunch& bl, hipStream_t st);
 hipError_t launch_batch_raster(const BatchLaunch& bl, hipStream_t st, int o);
 hipError_t launch_batch_killfill(const BatchLaunch& bl, int precision, hipStream_t st, int oo, int fd);
@@ -125,6 +127,7 @@ hipError_t launch_fields(lb_handle* h, double* d_out);       // rho_a, rho_b, u 
 hipError_t launch_stats(lb_handle* h);                       // totals into b.red[kRedBlocks*8 ...]
 hipError_t launch_remove_covered(lb_handle* h);
 hipError_t launch_bodies(lb_handle* h);
+hipError_t launch_pack_fast(lb_handle* h);  // packed particle copy from the particle table
 hipError_t launch_raster(lb_handle* h, uint32_t* owner, int first, int count);
 hipError_t launch_clear_owner(lb_handle* h, uint32_t* owner);
 hipError_t launch_killfill(lb_handle* h);

@@ -184,32 +184,26 @@ __global__ __launch_bounds__(kPB) void k_shell_batch(const SysDev* __restrict__ 
 // ---------------------------------------------------------------- S6 forces
 // Bounce-back force and torque of particle p (Eq. (5)), link by link from the
 // solid end. A surface node m of p and a direction i whose source n = m - c_i
-// is fluid form the link n -> m: the fused kernel sent f*_i(n) along it and
-// stored f'_ibar(n) = f*_i(n) + C back at n, so the link's momentum exchange
-// (2 f*_i + C) c_i equals (2 f'_ibar(n) - C) c_i, summed over both
-// components. C = -6 w_i rho^c(n) (U_n . c_i) is formed exactly as the fused
-// kernel formed it (U_n = V + W x r_n at n, rho^c(n) from the density pass).
-// The torque is r_n x F. One block per particle walks p's surface list (the
-// shell pass wrote it for the same owner map): entry e goes to thread
-// e mod 256, entries and links in increasing order, then a fixed block sum,
-// so the result is reproducible bit for bit.
-template <class P>
-__device__ inline void linkforce_body(const Box& bx, const typename P::S* __restrict__ f,
-                                      const typename P::R* __restrict__ dens, double* __restrict__ part, int cap,
-                                      int nseg, const uint2* __restrict__ slist, const int* __restrict__ scount,
-                                      int p) {
-    using R = typename P::R;
+// is fluid form the link n -> m; the fused kernel wrote the link's momentum
+// exchange 2 f*_i(n) + C (both components, C = -6 w_i rho^c(n) (U_n . c_i))
+// into slot i of n's record of p, so the force is the sum of record * c_i and
+// the torque the sum of r_n x (record * c_i). One block per particle walks
+// p's surface list (the shell pass wrote it for the same owner map): entry e
+// goes to thread e mod 256, entries and links in increasing order, then a
+// fixed block sum, so the result is reproducible bit for bit.
+__device__ inline void linkforce_body(const Box& bx, const double* __restrict__ rec, int rstride,
+                                      double* __restrict__ part, int cap, int nseg,
+                                      const uint2* __restrict__ slist, const int* __restrict__ scount, int p) {
     __shared__ int s_pre[257];
     __shared__ int s_wsum[4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int64_t N = bx.N;
     const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
+    const int Ls[3] = {nx, ny, nz};
     const double X[3] = {part[PX * cap + p], part[PY * cap + p], part[PZ * cap + p]};
-    const double V[3] = {part[VX * cap + p], part[VY * cap + p], part[VZ * cap + p]};
-    const double W[3] = {part[WX * cap + p], part[WY * cap + p], part[WZ * cap + p]};
-    const R ref0 = R(bx.rref[0]), ref1 = R(bx.rref[1]);
+    int lo[3], sz[3];
+    const bool ok = particle_box(bx, part, cap, p, lo, sz);
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int c0 = 0; c0 < nseg; c0 += 256) {
+    for (int c0 = 0; ok && c0 < nseg; c0 += 256) {
         const int nc = min(256, nseg - c0);
         // exclusive prefix of the segment counts of this chunk
         const int cnt = tid < nc ? scount[(size_t)p * nseg + c0 + tid] : 0;
@@ -238,45 +232,30 @@ __device__ inline void linkforce_body(const Box& bx, const typename P::S* __rest
             const int mz = (int)(m / (uint32_t)(nx * ny));
             const int rem = (int)(m - (uint32_t)mz * (uint32_t)(nx * ny));
             const int my = rem / nx, mx = rem - my * nx;
-            // the link loads of half of the directions are issued together
+            double g[Q - 1];
+            int nn[Q - 1][3];
 #pragma unroll
-            for (int h = 0; h < 2; h++) {
-                R a0[9], a1[9], g0[9], g1[9];
+            for (int i = 1; i < Q; i++) {
+                nn[i - 1][0] = wrapc(mx - cx(i), nx);
+                nn[i - 1][1] = wrapc(my - cy(i), ny);
+                nn[i - 1][2] = wrapc(mz - cz(i), nz);
+                const int cb = (mask & (1u << i)) ? rec_cell(nn[i - 1], lo, sz, Ls) : -1;
+                g[i - 1] = cb >= 0 ? rec[((size_t)p * rstride + cb) * kRec + (i - 1)] : 0.0;
+            }
 #pragma unroll
-                for (int j = 0; j < 9; j++) {
-                    const int i = 1 + 9 * h + j;
-                    a0[j] = a1[j] = g0[j] = g1[j] = R(0);
-                    if (mask & (1u << i)) {
-                        const int64_t n =
-                            node_index(bx, wrapc(mx - cx(i), nx), wrapc(my - cy(i), ny), wrapc(mz - cz(i), nz));
-                        a0[j] = dens[n];
-                        a1[j] = dens[N + n];
-                        g0[j] = P::ld(f + (size_t)opp(i) * N + n, R(wq(i)) * ref0);
-                        g1[j] = P::ld(f + (size_t)(Q + opp(i)) * N + n, R(wq(i)) * ref1);
-                    }
-                }
-#pragma unroll
-                for (int j = 0; j < 9; j++) {
-                    const int i = 1 + 9 * h + j;
-                    if (!(mask & (1u << i))) continue;
-                    const double rx = minimg((double)wrapc(mx - cx(i), nx) - X[0], nx);
-                    const double ry = minimg((double)wrapc(my - cy(i), ny) - X[1], ny);
-                    const double rz = minimg((double)wrapc(mz - cz(i), nz) - X[2], nz);
-                    const double Ux = V[0] + (W[1] * rz - W[2] * ry);
-                    const double Uy = V[1] + (W[2] * rx - W[0] * rz);
-                    const double Uz = V[2] + (W[0] * ry - W[1] * rx);
-                    const double cu = Ux * cx(i) + Uy * cy(i) + Uz * cz(i);
-                    const R C0 = R(-6.0 * wq(i) * cu) * a0[j];
-                    const R C1 = R(-6.0 * wq(i) * cu) * a1[j];
-                    const double mag = 2.0 * ((double)g0[j] + (double)g1[j]) - ((double)C0 + (double)C1);
-                    const double Fx = mag * cx(i), Fy = mag * cy(i), Fz = mag * cz(i);
-                    acc[0] += Fx;
-                    acc[1] += Fy;
-                    acc[2] += Fz;
-                    acc[3] += ry * Fz - rz * Fy;
-                    acc[4] += rz * Fx - rx * Fz;
-                    acc[5] += rx * Fy - ry * Fx;
-                }
+            for (int i = 1; i < Q; i++) {
+                if (!(mask & (1u << i))) continue;
+                const double rx = minimg((double)nn[i - 1][0] - X[0], nx);
+                const double ry = minimg((double)nn[i - 1][1] - X[1], ny);
+                const double rz = minimg((double)nn[i - 1][2] - X[2], nz);
+                const double mag = g[i - 1];
+                const double Fx = mag * cx(i), Fy = mag * cy(i), Fz = mag * cz(i);
+                acc[0] += Fx;
+                acc[1] += Fy;
+                acc[2] += Fz;
+                acc[3] += ry * Fz - rz * Fy;
+                acc[4] += rz * Fx - rx * Fz;
+                acc[5] += rx * Fy - ry * Fx;
             }
         }
         __syncthreads();  // s_pre / s_wsum are rewritten by the next chunk
@@ -288,22 +267,17 @@ __device__ inline void linkforce_body(const Box& bx, const typename P::S* __rest
         for (int k = 0; k < 6; k++) part[fld[k] * cap + p] = tot[k];
     }
 }
-template <class P>
-__global__ __launch_bounds__(256) void k_linkforce(Box bx, const typename P::S* __restrict__ f,
-                                                   const typename P::R* __restrict__ dens,
+__global__ __launch_bounds__(256) void k_linkforce(Box bx, const double* __restrict__ rec, int rstride,
                                                    double* __restrict__ part, int cap, int nseg,
                                                    const uint2* __restrict__ slist, const int* __restrict__ scount) {
-    linkforce_body<P>(bx, f, dens, part, cap, nseg, slist, scount, blockIdx.x);
+    linkforce_body(bx, rec, rstride, part, cap, nseg, slist, scount, blockIdx.x);
 }
-// Batched: item = (system, particle); `d` is the post-streaming population copy.
-template <class P>
+// Batched: item = (system, particle).
 __global__ __launch_bounds__(256) void k_linkforce_batch(const SysDev* __restrict__ sd,
-                                                         const WorkItem* __restrict__ items, int d_) {
+                                                         const WorkItem* __restrict__ items) {
     const WorkItem w = items[blockIdx.x];
     const SysDev& d = sd[w.sys];
-    const void* dens = d.box.psi_kind == 0 ? d.psi : d.rho;
-    linkforce_body<P>(d.box, (const typename P::S*)d.f[d_], (const typename P::R*)dens, d.part, d.cap, d.nseg,
-                      d.slist, d.scount, w.local);
+    linkforce_body(d.box, d.rec, d.kext * d.kext * d.kext, d.part, d.cap, d.nseg, d.slist, d.scount, w.local);
 }
 
 // ---------------------------------------------------------------- S7
@@ -314,7 +288,7 @@ __global__ __launch_bounds__(256) void k_linkforce_batch(const SysDev* __restric
 // particle: lane l sums slots l, l + 64, ... in order, then a fixed shuffle
 // tree; lane 0 updates the body.
 __device__ inline void bodies_body(const Box& bx, double* __restrict__ part, int cap,
-                                   const double* __restrict__ kpart, int nk, int p) {
+                                   const double* __restrict__ kpart, int nk, double* __restrict__ pfast, int p) {
     const int lane = threadIdx.x;
     double Jk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int s = lane; s < nk; s += 64)
@@ -401,16 +375,24 @@ __device__ inline void bodies_body(const Box& bx, double* __restrict__ part, int
     F_(QY) = nyq / nn;
     F_(QZ) = nzq / nn;
 #undef F_
+    pack_fast(part, cap, p, pfast);
 }
 __global__ __launch_bounds__(64) void k_bodies(Box bx, double* __restrict__ part, int cap,
-                                               const double* __restrict__ kpart, int nk) {
-    bodies_body(bx, part, cap, kpart, nk, blockIdx.x);
+                                               const double* __restrict__ kpart, int nk,
+                                               double* __restrict__ pfast) {
+    bodies_body(bx, part, cap, kpart, nk, pfast, blockIdx.x);
 }
 __global__ __launch_bounds__(64) void k_bodies_batch(const SysDev* __restrict__ sd,
                                                      const WorkItem* __restrict__ items) {
     const WorkItem w = items[blockIdx.x];
     const SysDev& d = sd[w.sys];
-    bodies_body(d.box, d.part, d.cap, d.kpart, 1, w.local);
+    bodies_body(d.box, d.part, d.cap, d.kpart, 1, d.pfast, w.local);
+}
+
+// Packed particle table of particles [0, np) from the particle table.
+__global__ void k_pack_fast(const double* __restrict__ part, int cap, int np, double* __restrict__ pfast) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < np) pack_fast(part, cap, p, pfast);
 }
 
 // Pending kill/fill impulses: add the partial slots into the particle's J, H
@@ -658,20 +640,21 @@ hipError_t launch_shell(lb_handle* h) {
 
 hipError_t launch_forces(lb_handle* h) {
     if (h->np <= 0) return hipSuccess;
-    const int nseg = surf_nseg(h);
-    const void* fn = h->b.f[1 - h->cur];
-    // rho^c(n) of fluid nodes: Psi itself when Psi = rho, else the stored rho
-    const void* dens = h->prm.psi_kind == 0 ? h->b.psi : h->b.rho;
-    LBE_PDISPATCH(h->prm.precision,
-                  hipLaunchKernelGGL(k_linkforce<P>, dim3(h->np), dim3(256), 0, h->stream, h->box,
-                                     (const typename P::S*)fn, (const typename P::R*)dens, h->b.part, h->cap, nseg,
-                                     h->b.slist, h->b.scount));
+    const int nseg = surf_nseg(h), ke = kill_ext(h);
+    hipLaunchKernelGGL(k_linkforce, dim3(h->np), dim3(256), 0, h->stream, h->box, h->b.rec, ke * ke * ke, h->b.part,
+                       h->cap, nseg, h->b.slist, h->b.scount);
     return hipGetLastError();
 }
-
 hipError_t launch_bodies(lb_handle* h) {
     if (h->np <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bodies, dim3(h->np), dim3(64), 0, h->stream, h->box, h->b.part, h->cap, h->b.kpart, 1);
+    hipLaunchKernelGGL(k_bodies, dim3(h->np), dim3(64), 0, h->stream, h->box, h->b.part, h->cap, h->b.kpart, 1,
+                       h->b.pfast);
+    return hipGetLastError();
+}
+hipError_t launch_pack_fast(lb_handle* h) {
+    if (h->np <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_fast, dim3((h->np + 255) / 256), dim3(256), 0, h->stream, h->b.part, h->cap, h->np,
+                       h->b.pfast);
     return hipGetLastError();
 }
 
@@ -714,10 +697,9 @@ hipError_t launch_batch_shell(const BatchLaunch& bl, int precision, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_batch_forces(const BatchLaunch& bl, int precision, hipStream_t st, int d) {
+hipError_t launch_batch_forces(const BatchLaunch& bl, hipStream_t st) {
     if (bl.n[BI_PART] == 0) return hipSuccess;
-    LBE_PDISPATCH(precision, hipLaunchKernelGGL(k_linkforce_batch<P>, dim3(bl.n[BI_PART]), dim3(256), 0, st, bl.sys,
-                                                bl.items[BI_PART], d));
+    hipLaunchKernelGGL(k_linkforce_batch, dim3(bl.n[BI_PART]), dim3(256), 0, st, bl.sys, bl.items[BI_PART]);
     return hipGetLastError();
 }
 

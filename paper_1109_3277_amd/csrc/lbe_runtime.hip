@@ -56,15 +56,18 @@ Layout layout_of(const lb_params* p) {
     L.rho = p->max_particles > 0 ? align_up(2 * N * rho_elem_bytes(p->precision)) : 0;
     L.owner = align_up(N * sizeof(uint32_t));
     L.part = align_up(NPFIELD * cap * sizeof(double));
+    L.pfast = align_up(kPF * cap * sizeof(double));
     const double rmax = p->max_particles > 0 ? p->max_radius : 0.5;
     const size_t nseg = (size_t)surf_segments(raster_extent(p->nx, p->ny, p->nz, rmax));
     L.slist = p->max_particles > 0 ? align_up(cap * nseg * 64 * sizeof(uint2)) : 0;
     L.scount = p->max_particles > 0 ? align_up(cap * nseg * sizeof(int)) : 0;
+    const size_t kext = (size_t)killfill_extent(p->nx, p->ny, p->nz, rmax);
+    L.rec = p->max_particles > 0 ? align_up(cap * kext * kext * kext * kRec * sizeof(double)) : 0;
     L.kpart = align_up(cap * 8 * sizeof(double));
     L.red = align_up((kRedBlocks + 1) * 8 * sizeof(double));
     L.counters = align_up(8 * sizeof(double));
     L.health = align_up(sizeof(int));
-    L.total = 2 * L.f + L.psi + L.rho + 2 * L.owner + L.part + L.slist + L.scount + L.kpart + L.red + L.counters +
+    L.total = 2 * L.f + L.psi + L.rho + 2 * L.owner + L.part + L.pfast + L.slist + L.scount + L.rec + L.kpart + L.red + L.counters +
               L.health;
     return L;
 }
@@ -96,8 +99,10 @@ int setup_handle(lb_handle* h, const lb_params* prm, char* ws, size_t ws_bytes, 
     h->b.owner[0] = (uint32_t*)p; p += L.owner;
     h->b.owner[1] = (uint32_t*)p; p += L.owner;
     h->b.part = (double*)p; p += L.part;
+    h->b.pfast = (double*)p; p += L.pfast;
     h->b.slist = L.slist ? (uint2*)p : nullptr; p += L.slist;
     h->b.scount = L.scount ? (int*)p : nullptr; p += L.scount;
+    h->b.rec = L.rec ? (double*)p : nullptr; p += L.rec;
     h->b.kpart = (double*)p; p += L.kpart;
     h->b.red = (double*)p; p += L.red;
     h->b.counters = (double*)p; p += L.counters;
@@ -342,6 +347,7 @@ int lb_add_ellipsoids(lb_handle* h, int32_t n, const double* radii, const double
     LBE_HIP(h, hipMemcpyAsync(before, h->b.red + kRedBlocks * 8, 7 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     h->np += n;
     h->has_solid = true;
+    LBE_HIP(h, launch_pack_fast(h));
     LBE_HIP(h, launch_raster(h, h->b.owner[h->ocur], first, n));
     LBE_HIP(h, launch_remove_covered(h));
     LBE_HIP(h, launch_stats(h));
@@ -549,6 +555,7 @@ int lb_load_state(lb_handle* h, const void* host_buf, size_t bytes) {
     h->box.rref[1] = hdr[4];
     h->rmax = hdr[5];
     h->has_solid = h->np > 0;
+    LBE_HIP(h, launch_pack_fast(h));
     h->inited = true;
     h->dens_ready = false;
     batch_touch(h);
