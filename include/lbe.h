@@ -140,7 +140,10 @@ int lb_set_body_accel(lb_handle* h, const double a[3]);
 
 /* Checkpoint: lb_state_bytes() bytes of host memory hold the populations,
  * owner map, particle state and counters; lb_load_state restores them into a
- * handle created with the same parameters. */
+ * handle created with the same parameters. The populations are stored in
+ * plain form (each node's values in its own slots; between steps the values
+ * bounced into solid nodes are kept there): saving rewrites the device state
+ * into that form, which leaves every later result unchanged bit for bit. */
 size_t lb_state_bytes(const lb_handle* h);
 int lb_save_state(lb_handle* h, void* host_buf, size_t bytes);
 int lb_load_state(lb_handle* h, const void* host_buf, size_t bytes);

@@ -131,6 +131,8 @@ int refresh(lb_handle* h) {
         d.part = q->b.part;
         d.slist = q->b.slist;
         d.scount = q->b.scount;
+        d.bmask[0] = q->b.bmask[0];
+        d.bmask[1] = q->b.bmask[1];
         d.rec = q->b.rec;
         d.pfast = q->b.pfast;
         d.kpart = q->b.kpart;

@@ -52,34 +52,43 @@ enum PField : int {
 };
 
 // Population storage policies. S is the stored type, R the arithmetic type.
-// Deviation forms store f_i - w_i rho_ref^c.
+// Deviation forms store f_i - w_i rho_ref^c. enc / dec convert one value
+// (dec(enc(v)) is what a later load of the stored value returns).
 struct PolF64 {
     using S = double;
     using R = double;
     static constexpr bool dev = false;
-    __device__ static R ld(const S* p, R) { return *p; }
-    __device__ static void st(S* p, R v, R) { *p = v; }
+    __device__ static S enc(R v, R) { return v; }
+    __device__ static R dec(S s, R) { return s; }
+    __device__ static R ld(const S* p, R w) { return dec(*p, w); }
+    __device__ static void st(S* p, R v, R w) { *p = enc(v, w); }
 };
 struct PolF32 {
     using S = float;
     using R = float;
     static constexpr bool dev = false;
-    __device__ static R ld(const S* p, R) { return *p; }
-    __device__ static void st(S* p, R v, R) { *p = v; }
+    __device__ static S enc(R v, R) { return v; }
+    __device__ static R dec(S s, R) { return s; }
+    __device__ static R ld(const S* p, R w) { return dec(*p, w); }
+    __device__ static void st(S* p, R v, R w) { *p = enc(v, w); }
 };
 struct PolF16 {
     using S = __half;
     using R = float;
     static constexpr bool dev = true;
-    __device__ static R ld(const S* p, R wref) { return __half2float(*p) + wref; }
-    __device__ static void st(S* p, R v, R wref) { *p = __float2half_rn(v - wref); }
+    __device__ static S enc(R v, R wref) { return __float2half_rn(v - wref); }
+    __device__ static R dec(S s, R wref) { return __half2float(s) + wref; }
+    __device__ static R ld(const S* p, R w) { return dec(*p, w); }
+    __device__ static void st(S* p, R v, R w) { *p = enc(v, w); }
 };
 struct PolBF16 {
     using S = __hip_bfloat16;
     using R = float;
     static constexpr bool dev = true;
-    __device__ static R ld(const S* p, R wref) { return __bfloat162float(*p) + wref; }
-    __device__ static void st(S* p, R v, R wref) { *p = __float2bfloat16(v - wref); }
+    __device__ static S enc(R v, R wref) { return __float2bfloat16(v - wref); }
+    __device__ static R dec(S s, R wref) { return __bfloat162float(s) + wref; }
+    __device__ static R ld(const S* p, R w) { return dec(*p, w); }
+    __device__ static void st(S* p, R v, R w) { *p = enc(v, w); }
 };
 
 // Everything a kernel needs to know about one periodic box.
@@ -107,6 +116,15 @@ __device__ inline T* atw(T* base, uint32_t byte_off) {
 }
 
 __device__ inline int wrapc(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+// Streaming with solids: every node pushes all of its populations to
+// (i, n + c_i); a population sent into a solid node is stored there already
+// bounced back (Eq. (4)). The bounce mask of a fluid node has bit i set when
+// its neighbour n - c_i was solid at that push: population i after streaming
+// then sits in plane ibar at n - c_i (where the node sent its population ibar)
+// instead of in plane i at n. Node index of n - c_i:
+__device__ inline uint32_t upstream(int nx, int ny, int nz, int x, int y, int z, int i) {
+    return (uint32_t)(wrapc(x - cx(i), nx) + nx * (wrapc(y - cy(i), ny) + ny * wrapc(z - cz(i), nz)));
+}
 // periodic wrap of any integer coordinate
 __device__ inline int wrapc_any(int a, int n) {
     a %= n;
@@ -232,6 +250,7 @@ struct SysDev {
     void* psi;
     void* rho;
     uint32_t* owner[2];
+    uint32_t* bmask[2];  // bounce masks of population copy 0 / 1
     double* part;
     uint2* slist;
     int* scount;

@@ -28,6 +28,26 @@ __device__ inline R feq_i(int i, R rho, R ux, R uy, R uz, R uu) {
     return R(wq(i)) * rho * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
 }
 
+// Plane and node holding population i of fluid node n (coordinates x, y, z)
+// after streaming, given its bounce mask bm.
+__device__ inline void pop_src(const Box& bx, uint32_t n, int x, int y, int z, uint32_t bm, int i, int& plane,
+                               uint32_t& node) {
+    if ((bm >> i) & 1u) {
+        plane = opp(i);
+        node = upstream(bx.nx, bx.ny, bx.nz, x, y, z, i);
+    } else {
+        plane = i;
+        node = n;
+    }
+}
+__device__ inline void node_xyz(const Box& bx, uint32_t n, int& x, int& y, int& z) {
+    const uint32_t pl = (uint32_t)bx.nx * (uint32_t)bx.ny;
+    z = (int)(n / pl);
+    const uint32_t r = n - (uint32_t)z * pl;
+    y = (int)(r / (uint32_t)bx.nx);
+    x = (int)(r - (uint32_t)y * (uint32_t)bx.nx);
+}
+
 // ---------------------------------------------------------------- S1
 // rho^c(n) = sum_i f_i^c(n) on fluid nodes, stored as the effective mass
 // Psi^c(n) of Eq. (3) (what the force stencil reads) and, when the shell fill
@@ -38,20 +58,63 @@ template <class P, bool SOLID>
 __device__ inline void density_body(const Box& bx, const typename P::S* __restrict__ f,
                                     typename P::R* __restrict__ psi, typename P::R* __restrict__ rho,
                                     const uint32_t* __restrict__ owner, const uint32_t* __restrict__ owner_old,
-                                    int* __restrict__ health, int blk) {
+                                    const uint32_t* __restrict__ bmask, int* __restrict__ health, int blk) {
     using R = typename P::R;
     const uint32_t N = (uint32_t)bx.N;
     const uint32_t n = (uint32_t)blk * 256u + threadIdx.x;
     if (n >= N) return;
     if (SOLID && owner[n] != OWN_FLUID) return;
     if (owner_old && owner_old[n] != OWN_FLUID) return;
-    const uint32_t nb = n * (uint32_t)sizeof(typename P::S);
     const R ref0 = R(bx.rref[0]), ref1 = R(bx.rref[1]);
     R r0 = R(0), r1 = R(0);
+    const uint32_t bm = SOLID ? bmask[n] : 0u;
+    if (!SOLID || __ballot(bm != 0u) == 0ull) {
+        // no lane of the wave reads a bounced population: plane bases are
+        // wave-uniform, offsets 32-bit
+        const uint32_t nb = n * (uint32_t)sizeof(typename P::S);
 #pragma unroll
-    for (int i = 0; i < Q; i++) {
-        r0 += P::ld(at(f + (size_t)i * N, nb), R(wq(i)) * ref0);
-        r1 += P::ld(at(f + (size_t)(Q + i) * N, nb), R(wq(i)) * ref1);
+        for (int i = 0; i < Q; i++) {
+            r0 += P::ld(at(f + (size_t)i * N, nb), R(wq(i)) * ref0);
+            r1 += P::ld(at(f + (size_t)(Q + i) * N, nb), R(wq(i)) * ref1);
+        }
+    } else {
+        // population i from its own slot, or from plane ibar at n - c_i when
+        // bit i of the bounce mask is set
+        uint32_t up[Q];
+#pragma unroll
+        for (int i = 0; i < Q; i++) up[i] = n;
+        if (bm != 0u) {
+            const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
+            const uint32_t pl = (uint32_t)nx * (uint32_t)ny;
+            const int z = (int)(n / pl);
+            const uint32_t rem = n - (uint32_t)z * pl;
+            const int y = (int)(rem / (uint32_t)nx), x = (int)(rem - (uint32_t)y * (uint32_t)nx);
+            const uint32_t xs[3] = {(uint32_t)x, (uint32_t)(x + 1 == nx ? 0 : x + 1),
+                                    (uint32_t)(x == 0 ? nx - 1 : x - 1)};
+            const uint32_t ys[3] = {(uint32_t)(y * nx), (uint32_t)((y + 1 == ny ? 0 : y + 1) * nx),
+                                    (uint32_t)((y == 0 ? ny - 1 : y - 1) * nx)};
+            const uint32_t zs[3] = {(uint32_t)z * pl, (uint32_t)(z + 1 == nz ? 0 : z + 1) * pl,
+                                    (uint32_t)(z == 0 ? nz - 1 : z - 1) * pl};
+#define LBE_SEL(c) ((c) == 0 ? 0 : ((c) > 0 ? 1 : 2))
+#pragma unroll
+            for (int i = 1; i < Q; i++)
+                if ((bm >> i) & 1u) up[i] = xs[LBE_SEL(-cx(i))] + ys[LBE_SEL(-cy(i))] + zs[LBE_SEL(-cz(i))];
+#undef LBE_SEL
+        }
+        // every load issued before the in-order sums
+        R v0[Q], v1[Q];
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            const bool u = (bm >> i) & 1u;
+            const uint32_t ob = up[i] * (uint32_t)sizeof(typename P::S);
+            v0[i] = P::ld(at(u ? f + (size_t)opp(i) * N : f + (size_t)i * N, ob), R(wq(i)) * ref0);
+            v1[i] = P::ld(at(u ? f + (size_t)(Q + opp(i)) * N : f + (size_t)(Q + i) * N, ob), R(wq(i)) * ref1);
+        }
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            r0 += v0[i];
+            r1 += v1[i];
+        }
     }
     psi[n] = psi_of(r0, bx.psi_kind);
     psi[N + n] = psi_of(r1, bx.psi_kind);
@@ -65,8 +128,9 @@ template <class P, bool SOLID>
 __global__ __launch_bounds__(256) void k_density(Box bx, const typename P::S* __restrict__ f,
                                                  typename P::R* __restrict__ psi, typename P::R* __restrict__ rho,
                                                  const uint32_t* __restrict__ owner,
-                                                 const uint32_t* __restrict__ owner_old, int* __restrict__ health) {
-    density_body<P, SOLID>(bx, f, psi, rho, owner, owner_old, health, blockIdx.x);
+                                                 const uint32_t* __restrict__ owner_old,
+                                                 const uint32_t* __restrict__ bmask, int* __restrict__ health) {
+    density_body<P, SOLID>(bx, f, psi, rho, owner, owner_old, bmask, health, blockIdx.x);
 }
 // Batched: item = (system, block of 256 nodes); populations copy `c`, owner
 // copy `o` (and, if oo >= 0, old owner copy `oo`); rho is written where the
@@ -78,15 +142,17 @@ __global__ __launch_bounds__(256) void k_density_batch(const SysDev* __restrict_
     const SysDev& d = sd[w.sys];
     typename P::R* rho = (d.np > 0 && d.box.psi_kind != 0) ? (typename P::R*)d.rho : nullptr;
     density_body<P, true>(d.box, (const typename P::S*)d.f[c], (typename P::R*)d.psi, rho, d.owner[o],
-                          oo >= 0 ? d.owner[oo] : nullptr, d.health, w.local);
+                          oo >= 0 ? d.owner[oo] : nullptr, d.bmask[c], d.health, w.local);
 }
 
 // ---------------------------------------------------------------- S3-S6
 // Per fluid node: Shan-Chen force (Eq. (3)) from neighbour Psi, BGK collision
 // (Eq. (2)) with the common-velocity shift u^eq_c = u' + tau F^c/rho^c, then
 // push streaming (Eq. (1)). With solids present, a link i into a solid node
-// is replaced by moving bounce-back (Eq. (4)) in place:
-// f'_ibar(n) = f*_i(n) + C, C = 6 w_i rho^c(n) (u_b . c_ibar). For a rigid
+// is replaced by moving bounce-back (Eq. (4)): the value f*_i(n) + C,
+// C = 6 w_i rho^c(n) (u_b . c_ibar), becomes f'_ibar(n); it is pushed into
+// the solid node's slot (i, n + c_i) like any other population, and the
+// node's bounce mask tells the readers of f'_ibar(n) where it is. For a rigid
 // body the surface velocity at the link midpoint, V + W x (r_n + c_i/2), has
 // the same projection on c_i as U_n = V + W x r_n at the node (W x c_i is
 // normal to c_i), so C needs one U_n per node and particle. The particle's
@@ -152,8 +218,9 @@ __device__ inline void collide_node(const Box& bx, typename P::R (&f0)[Q], typen
 template <class P, bool SOLID, int BX, int BY>
 __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict__ fs, typename P::S* __restrict__ fd,
                                   const typename P::R* __restrict__ psi, const uint32_t* __restrict__ owner,
-                                  const double* __restrict__ pfast, double* __restrict__ rec, int rstride,
-                                  int tiles_x, int tiles_y, int tile) {
+                                  const uint32_t* __restrict__ bm_in, uint32_t* __restrict__ bm_out,
+                                  const double* __restrict__ pfast,
+                                  double* __restrict__ rec, int rstride, int tiles_x, int tiles_y, int tile) {
     using R = typename P::R;
     using S = typename P::S;
     static_assert(BX * BY == 256, "one node per thread");
@@ -173,18 +240,38 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
     const int x = x0 + lx, y = y0 + ly;
     const bool active = (x < nx) && (y < ny);
     const uint32_t n = active ? (uint32_t)(x + nx * (y + ny * z)) : 0u;
-    const bool fluid = active && (!SOLID || owner[n] == OWN_FLUID);
+    // owner code and bounce mask, both loaded before either is waited for
+    const uint32_t own_n = (SOLID && active) ? owner[n] : OWN_FLUID;
+    const uint32_t bm = (SOLID && active) ? bm_in[n] : 0u;
+    const bool fluid = active && own_n == OWN_FLUID;
     const uint32_t nb = n * (uint32_t)sizeof(S);  // byte offset of the node within a plane
     const R ref0 = R(bx.rref[0]), ref1 = R(bx.rref[1]);
+    // offsets of the neighbour rows / planes (periodic)
+    const int xs[3] = {x, x + 1 == nx ? 0 : x + 1, x == 0 ? nx - 1 : x - 1};
+    const uint32_t ys[3] = {(uint32_t)(y * nx), (uint32_t)((y + 1 == ny ? 0 : y + 1) * nx),
+                            (uint32_t)((y == 0 ? ny - 1 : y - 1) * nx)};
+    const uint32_t pl = (uint32_t)(nx * ny);
+    const uint32_t zs[3] = {(uint32_t)z * pl, (uint32_t)(z + 1 == nz ? 0 : z + 1) * pl,
+                            (uint32_t)(z == 0 ? nz - 1 : z - 1) * pl};
+#define LBE_SEL(c) ((c) == 0 ? 0 : ((c) > 0 ? 1 : 2))
+#define LBE_NB(i) ((uint32_t)xs[LBE_SEL(cx(i))] + ys[LBE_SEL(cy(i))] + zs[LBE_SEL(cz(i))])
 
-    // this node's 2 x 19 populations (in flight while the tile loads)
+    // this node's 2 x 19 populations after streaming (in flight while the
+    // tile loads); with solids, a set bit i of the bounce mask takes
+    // population i from plane ibar at n - c_i
     R f0[Q], f1[Q];
     if (fluid) {
 #pragma unroll
         for (int i = 0; i < Q; i++) {
-            f0[i] = P::ld(at(fs + (size_t)i * N, nb), R(wq(i)) * ref0);
-            f1[i] = P::ld(at(fs + (size_t)(Q + i) * N, nb), R(wq(i)) * ref1);
+            const bool up = SOLID && ((bm >> i) & 1u);
+            const int pi = up ? opp(i) : i;
+            const uint32_t ob = up ? LBE_NB(opp(i)) * (uint32_t)sizeof(S) : nb;
+            f0[i] = P::ld(at(fs + (size_t)pi * N, ob), R(wq(i)) * ref0);
+            f1[i] = P::ld(at(fs + (size_t)(Q + pi) * N, ob), R(wq(i)) * ref1);
         }
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; i++) f0[i] = f1[i] = R(0);
     }
     // halo tile: every load of this thread issued before any is waited for
     constexpr int NE = (3 * TP + 255) / 256;
@@ -219,17 +306,11 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
         }
     }
     __syncthreads();
-    if (!fluid) return;
+    // with solids, the lanes of solid nodes take part in the pushes (zeros),
+    // so that every slot of every plane is written exactly once
+    if (!(SOLID ? active : fluid)) return;
 
 #define LBE_LS(i) ((1 + cz(i)) * TP + (ly + 1 + cy(i)) * TX + (lx + 1 + cx(i)))
-    const int xs[3] = {x, x + 1 == nx ? 0 : x + 1, x == 0 ? nx - 1 : x - 1};
-    const uint32_t ys[3] = {(uint32_t)(y * nx), (uint32_t)((y + 1 == ny ? 0 : y + 1) * nx),
-                            (uint32_t)((y == 0 ? ny - 1 : y - 1) * nx)};
-    const uint32_t pl = (uint32_t)(nx * ny);
-    const uint32_t zs[3] = {(uint32_t)z * pl, (uint32_t)(z + 1 == nz ? 0 : z + 1) * pl,
-                            (uint32_t)(z == 0 ? nz - 1 : z - 1) * pl};
-#define LBE_SEL(c) ((c) == 0 ? 0 : ((c) > 0 ? 1 : 2))
-#define LBE_NB(i) ((uint32_t)xs[LBE_SEL(cx(i))] + ys[LBE_SEL(cy(i))] + zs[LBE_SEL(cz(i))])
     R q0[Q], q1[Q];
 #pragma unroll
     for (int i = 1; i < Q; i++) {
@@ -237,10 +318,10 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
         q1[i] = s_psi[1][LBE_LS(i)];
     }
     q0[0] = q1[0] = R(0);
-    R r0, r1;
-    collide_node<P>(bx, f0, f1, q0, q1, r0, r1);
-    P::st(atw(fd, nb), f0[0], R(wq(0)) * ref0);
-    P::st(atw(fd + (size_t)Q * N, nb), f1[0], R(wq(0)) * ref1);
+    R r0 = R(0), r1 = R(0);
+    if (fluid) collide_node<P>(bx, f0, f1, q0, q1, r0, r1);
+    P::st(atw(fd, nb), fluid ? f0[0] : R(0), R(wq(0)) * ref0);
+    P::st(atw(fd + (size_t)Q * N, nb), fluid ? f1[0] : R(0), R(wq(0)) * ref1);
     if constexpr (!SOLID) {
 #pragma unroll
         for (int i = 1; i < Q; i++) {
@@ -249,22 +330,25 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
             P::st(atw(fd + (size_t)(Q + i) * N, mb), f1[i], R(wq(i)) * ref1);
         }
     } else {
-        // Every fluid lane takes the general path (one store path per wave).
-        // U_n of the first two particles each lane links to: the wave visits
-        // the distinct particles among them one at a time, reading each one's
-        // centre and velocities with wave-uniform loads. Links to a third
-        // particle of the same node (rare) read it per lane. Walls do not
-        // move (C = 0).
+        // U_n of the first two particles each fluid lane links to: the wave
+        // visits the distinct particles among them one at a time, reading
+        // each one's centre and velocities with wave-uniform loads. Links to
+        // a third particle of the same node (rare) read it per lane. Walls do
+        // not move (C = 0).
         uint32_t on[Q];
         uint32_t p1 = OWN_FLUID;
+        uint32_t mask = 0u;  // the node's bounce mask in the written copy
 #pragma unroll
         for (int i = 1; i < Q; i++) {
             on[i] = s_own[LBE_LS(i)];
-            p1 = (p1 == OWN_FLUID && on[i] < OWN_WALL) ? on[i] : p1;
+            p1 = (fluid && p1 == OWN_FLUID && on[i] < OWN_WALL) ? on[i] : p1;
+            mask |= (on[i] != OWN_FLUID ? 1u : 0u) << opp(i);
         }
+        bm_out[n] = fluid ? mask : 0u;
         uint32_t p2 = OWN_FLUID;
 #pragma unroll
-        for (int i = 1; i < Q; i++) p2 = (p2 == OWN_FLUID && on[i] < OWN_WALL && on[i] != p1) ? on[i] : p2;
+        for (int i = 1; i < Q; i++)
+            p2 = (fluid && p2 == OWN_FLUID && on[i] < OWN_WALL && on[i] != p1) ? on[i] : p2;
         // per particle slot: surface velocity U_n at this node and the
         // node's cell in the particle's link records
         double Ux2 = 0.0, Uy2 = 0.0, Uz2 = 0.0;
@@ -306,15 +390,14 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
                 need2 = false;
             }
         }
-        // one store per direction: the push to (i, n + c_i) for a fluid
-        // target, the bounce-back value at (ibar, n) for a solid one; a
-        // particle link also writes its record slot
+        // one store per direction, to (i, n + c_i) on every lane: f*_i for a
+        // fluid target, the bounced f*_i + C for a solid one, zero from a
+        // solid lane; a particle link also writes its record slot
 #pragma unroll
         for (int i = 1; i < Q; i++) {
             const uint32_t o = on[i];
-            const bool sol = (o != OWN_FLUID);
             R C0 = R(0), C1 = R(0);
-            if (o < OWN_WALL) {
+            if (fluid && o < OWN_WALL) {
                 double Ux = o == p1 ? Ux1 : Ux2, Uy = o == p1 ? Uy1 : Uy2, Uz = o == p1 ? Uz1 : Uz2;
                 int cb = o == p1 ? cb1 : cb2;
                 if (o != p1 && o != p2) {
@@ -337,12 +420,9 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
                     rec[((size_t)o * rstride + cb) * kRec + (i - 1)] =
                         2.0 * ((double)f0[i] + (double)f1[i]) + ((double)C0 + (double)C1);
             }
-            const int b = opp(i);
-            const uint32_t mb = sol ? nb : LBE_NB(i) * (uint32_t)sizeof(S);
-            S* d0 = sol ? fd + (size_t)b * N : fd + (size_t)i * N;
-            S* d1 = sol ? fd + (size_t)(Q + b) * N : fd + (size_t)(Q + i) * N;
-            P::st(atw(d0, mb), f0[i] + C0, R(wq(i)) * ref0);  // w_ibar = w_i
-            P::st(atw(d1, mb), f1[i] + C1, R(wq(i)) * ref1);
+            const uint32_t mb = LBE_NB(i) * (uint32_t)sizeof(S);
+            P::st(atw(fd + (size_t)i * N, mb), fluid ? f0[i] + C0 : R(0), R(wq(i)) * ref0);
+            P::st(atw(fd + (size_t)(Q + i) * N, mb), fluid ? f1[i] + C1 : R(0), R(wq(i)) * ref1);
         }
     }
 #undef LBE_NB
@@ -352,9 +432,9 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
 template <class P, bool SOLID, int BX, int BY>
 __global__ __launch_bounds__(256, sizeof(typename P::R) == 8 ? 2 : 3) void k_fused(
     Box bx, const typename P::S* __restrict__ fs, typename P::S* __restrict__ fd, const typename P::R* __restrict__ psi,
-    const uint32_t* __restrict__ owner, const double* __restrict__ pfast, double* __restrict__ rec, int rstride,
-    int tiles_x, int tiles_y) {
-    fused_body<P, SOLID, BX, BY>(bx, fs, fd, psi, owner, pfast, rec, rstride, tiles_x, tiles_y,
+    const uint32_t* __restrict__ owner, const uint32_t* __restrict__ bm_in, uint32_t* __restrict__ bm_out,
+    const double* __restrict__ pfast, double* __restrict__ rec, int rstride, int tiles_x, int tiles_y) {
+    fused_body<P, SOLID, BX, BY>(bx, fs, fd, psi, owner, bm_in, bm_out, pfast, rec, rstride, tiles_x, tiles_y,
                                  xcd_remap(blockIdx.x, gridDim.x));
 }
 // Batched: item = (system, tile); SOLID for the systems with particles.
@@ -366,7 +446,7 @@ __global__ __launch_bounds__(256, sizeof(typename P::R) == 8 ? 2 : 3) void k_fus
     const WorkItem w = items[xcd_remap(blockIdx.x, gridDim.x)];
     const SysDev& d = sd[w.sys];
     fused_body<P, SOLID, BX, BY>(d.box, (const typename P::S*)d.f[c], (typename P::S*)d.f[1 - c],
-                                 (const typename P::R*)d.psi, d.owner[o], d.pfast, d.rec,
+                                 (const typename P::R*)d.psi, d.owner[o], d.bmask[c], d.bmask[1 - c], d.pfast, d.rec,
                                  d.kext * d.kext * d.kext, d.tiles_x, d.tiles_y, w.local);
 }
 
@@ -527,7 +607,8 @@ __global__ __launch_bounds__(256) void k_init(Box bx, typename P::S* __restrict_
 // ---------------------------------------------------------------- readout
 template <class P>
 __global__ __launch_bounds__(256) void k_fields(Box bx, const typename P::S* __restrict__ f,
-                                                const uint32_t* __restrict__ owner, double* __restrict__ out) {
+                                                const uint32_t* __restrict__ owner,
+                                                const uint32_t* __restrict__ bmask, double* __restrict__ out) {
     using R = typename P::R;
     const int64_t N = bx.N;
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -535,12 +616,18 @@ __global__ __launch_bounds__(256) void k_fields(Box bx, const typename P::S* __r
     double r[2] = {0.0, 0.0}, j[3] = {0.0, 0.0, 0.0};
     const bool fluid = owner[n] == OWN_FLUID;
     if (fluid) {
+        const uint32_t bm = bmask[n];
+        int x, y, z;
+        node_xyz(bx, (uint32_t)n, x, y, z);
 #pragma unroll
         for (int c = 0; c < 2; c++) {
             const R ref = R(bx.rref[c]);
 #pragma unroll
             for (int i = 0; i < Q; i++) {
-                const double v = (double)P::ld(f + (size_t)(c * Q + i) * N + n, R(wq(i)) * ref);
+                int pi;
+                uint32_t m;
+                pop_src(bx, (uint32_t)n, x, y, z, bm, i, pi, m);
+                const double v = (double)P::ld(f + (size_t)(c * Q + pi) * N + m, R(wq(i)) * ref);
                 r[c] += v;
                 j[0] += v * cx(i);
                 j[1] += v * cy(i);
@@ -558,20 +645,27 @@ __global__ __launch_bounds__(256) void k_fields(Box bx, const typename P::S* __r
 // Deterministic reduction: fixed grid, per-block LDS tree, then one ordered pass.
 template <class P>
 __global__ __launch_bounds__(256) void k_stats_partial(Box bx, const typename P::S* __restrict__ f,
-                                                       const uint32_t* __restrict__ owner, double* __restrict__ red) {
+                                                       const uint32_t* __restrict__ owner,
+                                                       const uint32_t* __restrict__ bmask, double* __restrict__ red) {
     using R = typename P::R;
     const int64_t N = bx.N;
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
         if (owner[n] != OWN_FLUID) continue;
         acc[5] += 1.0;
+        const uint32_t bm = bmask[n];
+        int x, y, z;
+        node_xyz(bx, (uint32_t)n, x, y, z);
 #pragma unroll
         for (int c = 0; c < 2; c++) {
             const R ref = R(bx.rref[c]);
             double r = 0.0;
 #pragma unroll
             for (int i = 0; i < Q; i++) {
-                const double v = (double)P::ld(f + (size_t)(c * Q + i) * N + n, R(wq(i)) * ref);
+                int pi;
+                uint32_t m;
+                pop_src(bx, (uint32_t)n, x, y, z, bm, i, pi, m);
+                const double v = (double)P::ld(f + (size_t)(c * Q + pi) * N + m, R(wq(i)) * ref);
                 r += v;
                 acc[2] += v * cx(i);
                 acc[3] += v * cy(i);
@@ -623,6 +717,36 @@ __global__ __launch_bounds__(256) void k_remove_covered(Box bx, typename P::S* _
     }
 }
 
+// Plain form: the populations of every fluid node, read where its bounce
+// mask puts them, copied into its own slots of the other population copy
+// (zeros on solid nodes); the masks are then all zero. Stored values are
+// copied bit for bit (w_ibar = w_i).
+template <class P>
+__global__ __launch_bounds__(256) void k_canonical(Box bx, const typename P::S* __restrict__ fs,
+                                                   typename P::S* __restrict__ fd, const uint32_t* __restrict__ owner,
+                                                   uint32_t* __restrict__ bmask) {
+    using S = typename P::S;
+    const int64_t N = bx.N;
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const bool fluid = owner[n] == OWN_FLUID;
+    const uint32_t bm = fluid ? bmask[n] : 0u;
+    int x, y, z;
+    node_xyz(bx, (uint32_t)n, x, y, z);
+    for (int c = 0; c < 2; c++) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            int pi;
+            uint32_t m;
+            pop_src(bx, (uint32_t)n, x, y, z, bm, i, pi, m);
+            const S v = fluid ? fs[(size_t)(c * Q + pi) * N + m]
+                              : P::enc(typename P::R(0), typename P::R(wq(i)) * typename P::R(bx.rref[c]));
+            fd[(size_t)(c * Q + i) * N + n] = v;
+        }
+    }
+    bmask[n] = 0u;
+}
+
 __global__ void k_copy16(const uint4* __restrict__ a, uint4* __restrict__ b, size_t n) {
     for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
         b[k] = a[k];
@@ -669,7 +793,9 @@ hipError_t launch_init(lb_handle* h, const double* ra, const double* rb, const d
     LBE_DISPATCH(h->prm.precision,
                  hipLaunchKernelGGL(k_init<P>, dim3(nblk(h->box.N)), dim3(256), 0, h->stream, h->box,
                                     (typename P::S*)h->b.f[h->cur], ra, rb, u, h->b.owner[h->ocur]));
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_fill_u32(h, h->b.bmask[h->cur], 0u, h->box.N);  // populations in plain form
 }
 
 // Densities of populations copy `c` on the nodes fluid in owner copy `o`
@@ -681,12 +807,13 @@ hipError_t launch_density(lb_handle* h, int c, int o, int oo) {
         LBE_DISPATCH(h->prm.precision,
                      hipLaunchKernelGGL((k_density<P, true>), dim3(nblk(h->box.N)), dim3(256), 0, h->stream, h->box,
                                         (const typename P::S*)h->b.f[c], (typename P::R*)h->b.psi,
-                                        (typename P::R*)rho_out, h->b.owner[o], own_old, h->b.health));
+                                        (typename P::R*)rho_out, h->b.owner[o], own_old, h->b.bmask[c],
+                                        h->b.health));
     } else {
         LBE_DISPATCH(h->prm.precision,
                      hipLaunchKernelGGL((k_density<P, false>), dim3(nblk(h->box.N)), dim3(256), 0, h->stream, h->box,
                                         (const typename P::S*)h->b.f[c], (typename P::R*)h->b.psi,
-                                        (typename P::R*)nullptr, h->b.owner[o], nullptr, h->b.health));
+                                        (typename P::R*)nullptr, h->b.owner[o], nullptr, nullptr, h->b.health));
     }
     return hipGetLastError();
 }
@@ -741,10 +868,12 @@ static void launch_fused_t(lb_handle* h, const Tiles& tl, unsigned grid) {
     const int rstride = ke * ke * ke;
     if (tl.BX == 64)
         hipLaunchKernelGGL((k_fused<P, SOLID, 64, 4>), dim3(grid), dim3(256), 0, h->stream, h->box, fs, fd, ps, ow,
-                           h->b.pfast, h->b.rec, rstride, tl.tiles_x, tl.tiles_y);
+                           h->b.bmask[h->cur], h->b.bmask[1 - h->cur], h->b.pfast, h->b.rec, rstride, tl.tiles_x,
+                           tl.tiles_y);
     else
         hipLaunchKernelGGL((k_fused<P, SOLID, 32, 8>), dim3(grid), dim3(256), 0, h->stream, h->box, fs, fd, ps, ow,
-                           h->b.pfast, h->b.rec, rstride, tl.tiles_x, tl.tiles_y);
+                           h->b.bmask[h->cur], h->b.bmask[1 - h->cur], h->b.pfast, h->b.rec, rstride, tl.tiles_x,
+                           tl.tiles_y);
 }
 
 hipError_t launch_fused(lb_handle* h) {
@@ -761,16 +890,33 @@ hipError_t launch_fused(lb_handle* h) {
 hipError_t launch_fields(lb_handle* h, double* out) {
     LBE_DISPATCH(h->prm.precision,
                  hipLaunchKernelGGL(k_fields<P>, dim3(nblk(h->box.N)), dim3(256), 0, h->stream, h->box,
-                                    (const typename P::S*)h->b.f[h->cur], h->b.owner[h->ocur], out));
+                                    (const typename P::S*)h->b.f[h->cur], h->b.owner[h->ocur], h->b.bmask[h->cur],
+                                    out));
     return hipGetLastError();
 }
 
 hipError_t launch_stats(lb_handle* h) {
     LBE_DISPATCH(h->prm.precision,
                  hipLaunchKernelGGL(k_stats_partial<P>, dim3(kRedBlocks), dim3(256), 0, h->stream, h->box,
-                                    (const typename P::S*)h->b.f[h->cur], h->b.owner[h->ocur], h->b.red));
+                                    (const typename P::S*)h->b.f[h->cur], h->b.owner[h->ocur], h->b.bmask[h->cur],
+                                    h->b.red));
     hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(64), 0, h->stream, h->b.red, kRedBlocks);
     return hipGetLastError();
+}
+
+hipError_t launch_canonical(lb_handle* h) {
+    if (!h->has_solid) return hipSuccess;  // no solids: every mask is zero
+    LBE_DISPATCH(h->prm.precision,
+                 hipLaunchKernelGGL(k_canonical<P>, dim3(nblk(h->box.N)), dim3(256), 0, h->stream, h->box,
+                                    (const typename P::S*)h->b.f[h->cur], (typename P::S*)h->b.f[1 - h->cur],
+                                    h->b.owner[h->ocur], h->b.bmask[h->cur]));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // back into the current copy: the copy index stays as it was (a batch's
+    // systems share one parity)
+    // (the copies are padded to 256 bytes, so the length rounds up to 16)
+    const size_t bytes = (2 * Q * (size_t)h->box.N * elem_bytes(h->prm.precision) + 15) / 16 * 16;
+    return launch_copy(h->b.f[h->cur], h->b.f[1 - h->cur], bytes, h->stream);
 }
 
 hipError_t launch_remove_covered(lb_handle* h) {

@@ -18,6 +18,7 @@ struct Buffers {
     void* psi = nullptr;               // Psi^c per node [2][N] (double for FP64, float otherwise)
     void* rho = nullptr;               // rho^c per node [2][N], for the shell fill (exponential Psi)
     uint32_t* owner[2] = {nullptr, nullptr};
+    uint32_t* bmask[2] = {nullptr, nullptr};  // bounce masks of population copy 0 / 1 (per node)
     double* part = nullptr;            // particle table, NPFIELD x cap
     uint2* slist = nullptr;            // surface list segments, cap x nseg x 64 (node, link mask)
     int* scount = nullptr;             // entries per surface list segment, cap x nseg
@@ -87,7 +88,7 @@ namespace lbe {
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
-    size_t f, psi, rho, owner, part, pfast, slist, scount, rec, kpart, red, counters, health, total;
+    size_t f, psi, rho, owner, bmask, part, pfast, slist, scount, rec, kpart, red, counters, health, total;
 };
 bool params_ok(const lb_params* p, std::string* why);
 Layout layout_of(const lb_params* p);
@@ -126,6 +127,9 @@ Tiles fused_tiles(int nx, int ny, bool solids, int precision);
 hipError_t launch_fields(lb_handle* h, double* d_out);       // rho_a, rho_b, u (5 x N doubles)
 hipError_t launch_stats(lb_handle* h);                       // totals into b.red[kRedBlocks*8 ...]
 hipError_t launch_remove_covered(lb_handle* h);
+// Populations into plain form (every value in its node's own slot, masks
+// zero), through the other population copy and back.
+hipError_t launch_canonical(lb_handle* h);
 hipError_t launch_bodies(lb_handle* h);
 hipError_t launch_pack_fast(lb_handle* h);  // packed particle copy from the particle table
 hipError_t launch_raster(lb_handle* h, uint32_t* owner, int first, int count);

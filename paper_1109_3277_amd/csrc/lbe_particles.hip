@@ -422,7 +422,8 @@ __device__ inline R feq_p(int i, R rho, R ux, R uy, R uz) {
 // the move; runs after the density pass of the next step (populations after
 // streaming, nodes fluid in both owner maps). Node n with old owner o and new
 // owner o2:
-//   o fluid, o2 == p : kill  -> J_p += sum_c j^c(n), H_p += r x that, f(n) = 0
+//   o fluid, o2 == p : kill  -> J_p += sum_c j^c(n), H_p += r x that (the node's
+//                      populations are dropped: a solid node's slots are not read)
 //   o == p, o2 fluid : fill  -> rho_new^c = mean rho^c of neighbours fluid
 //                      before and after (initial mean if none), u = V + W x r,
 //                      f = f^eq(rho_new^c, u), J_p -= sum_c rho_new^c u, H_p -= r x that;
@@ -435,36 +436,45 @@ __device__ inline R feq_p(int i, R rho, R ux, R uy, R uz) {
 template <class P>
 __device__ inline void killfill_node(const Box& bx, typename P::S* __restrict__ f,
                                      const uint32_t* __restrict__ own_old, const uint32_t* __restrict__ own_new,
-                                     typename P::R* __restrict__ psi, typename P::R* __restrict__ rho,
-                                     const double* __restrict__ part, int cap, int p, bool kill, int x, int y,
-                                     int z, int64_t n, const double (&Xn)[3], double (&acc)[8]) {
+                                     uint32_t* __restrict__ bmask, typename P::R* __restrict__ psi,
+                                     typename P::R* __restrict__ rho, const double* __restrict__ part, int cap, int p,
+                                     bool kill, int x, int y, int z, int64_t n, const double (&Xn)[3],
+                                     double (&acc)[8]) {
     using R = typename P::R;
     const int64_t N = bx.N;
     const int Ls[3] = {bx.nx, bx.ny, bx.nz};
     const double r[3] = {minimg((double)x - Xn[0], Ls[0]), minimg((double)y - Xn[1], Ls[1]),
                          minimg((double)z - Xn[2], Ls[2])};
+    double d[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // impulse, torque, killed, filled mass
     if (kill) {
+        // the node's populations after streaming, where its bounce mask puts them
+        const uint32_t bm = bmask[n];
         double j[3] = {0.0, 0.0, 0.0}, m = 0.0;
+#pragma unroll
         for (int cc = 0; cc < 2; cc++) {
-            const R ref = R(bx.rref[cc]);
+            R v[Q];  // a component's loads all issued before its in-order sums
 #pragma unroll
             for (int i = 0; i < Q; i++) {
-                typename P::S* ptr = f + (size_t)(cc * Q + i) * N + n;
-                const double v = (double)P::ld(ptr, R(wq(i)) * ref);
-                m += v;
-                j[0] += v * cx(i);
-                j[1] += v * cy(i);
-                j[2] += v * cz(i);
-                P::st(ptr, R(0), R(wq(i)) * ref);
+                const bool u = (bm >> i) & 1u;
+                const int64_t src = u ? (int64_t)upstream(Ls[0], Ls[1], Ls[2], x, y, z, i) : n;
+                v[i] = P::ld(f + (size_t)(cc * Q + (u ? opp(i) : i)) * N + src, R(wq(i)) * R(bx.rref[cc]));
+            }
+#pragma unroll
+            for (int i = 0; i < Q; i++) {
+                const double w = (double)v[i];
+                m += w;
+                j[0] += w * cx(i);
+                j[1] += w * cy(i);
+                j[2] += w * cz(i);
             }
         }
-        acc[0] += j[0];
-        acc[1] += j[1];
-        acc[2] += j[2];
-        acc[3] += r[1] * j[2] - r[2] * j[1];
-        acc[4] += r[2] * j[0] - r[0] * j[2];
-        acc[5] += r[0] * j[1] - r[1] * j[0];
-        acc[6] += m;
+        d[0] = j[0];
+        d[1] = j[1];
+        d[2] = j[2];
+        d[3] = r[1] * j[2] - r[2] * j[1];
+        d[4] = r[2] * j[0] - r[0] * j[2];
+        d[5] = r[0] * j[1] - r[1] * j[0];
+        d[6] = m;
     } else {
         const double V[3] = {part[VX * cap + p], part[VY * cap + p], part[VZ * cap + p]};
         const double W[3] = {part[WX * cap + p], part[WY * cap + p], part[WZ * cap + p]};
@@ -474,6 +484,7 @@ __device__ inline void killfill_node(const Box& bx, typename P::S* __restrict__ 
         double rn[2] = {0.0, 0.0};
         int cnt = 0;
         uint32_t oo[Q], on[Q];
+        uint32_t up[Q];
         R d0[Q], d1[Q];
 #pragma unroll
         for (int i = 1; i < Q; i++) {
@@ -482,6 +493,7 @@ __device__ inline void killfill_node(const Box& bx, typename P::S* __restrict__ 
             on[i] = own_new[m];
             d0[i] = dens[m];
             d1[i] = dens[N + m];
+            up[i] = upstream(Ls[0], Ls[1], Ls[2], x, y, z, i);
         }
 #pragma unroll
         for (int i = 1; i < Q; i++) {
@@ -490,43 +502,63 @@ __device__ inline void killfill_node(const Box& bx, typename P::S* __restrict__ 
             rn[1] += (double)d1[i];
             cnt++;
         }
+#pragma unroll
         for (int cc = 0; cc < 2; cc++) rn[cc] = cnt > 0 ? rn[cc] / (double)cnt : bx.rmean0[cc];
         const double ub[3] = {V[0] + (W[1] * r[2] - W[2] * r[1]), V[1] + (W[2] * r[0] - W[0] * r[2]),
                               V[2] + (W[0] * r[1] - W[1] * r[0])};
+        // Population i of the node goes to its own slot (i, n), unless the
+        // upstream neighbour n - c_i was fluid at the push: that neighbour's
+        // bounced population sits in (i, n), and the slot (ibar, n - c_i),
+        // which this node filled with a zero, takes the value instead (bit i
+        // of the node's bounce mask).
+        uint32_t bm = 0u;
+#pragma unroll
+        for (int i = 1; i < Q; i++)
+            if (oo[opp(i)] == OWN_FLUID) bm |= 1u << i;  // n + c_ibar = n - c_i
         double jm[3] = {0.0, 0.0, 0.0};
         R rs[2];
+#pragma unroll
         for (int cc = 0; cc < 2; cc++) {
             const R ref = R(bx.rref[cc]);
-#pragma unroll
-            for (int i = 0; i < Q; i++)
-                P::st(f + (size_t)(cc * Q + i) * N + n, R(feq_p<double>(i, rn[cc], ub[0], ub[1], ub[2])), R(wq(i)) * ref);
-            for (int d = 0; d < 3; d++) jm[d] += rn[cc] * ub[d];
-            // the node's density as the density pass forms it from the stored values
             R r = R(0);
 #pragma unroll
-            for (int i = 0; i < Q; i++) r += P::ld(f + (size_t)(cc * Q + i) * N + n, R(wq(i)) * ref);
+            for (int i = 0; i < Q; i++) {
+                const bool u = (bm >> i) & 1u;
+                typename P::S* dst = f + (size_t)(cc * Q + (u ? opp(i) : i)) * N + (u ? (int64_t)up[i] : n);
+                const typename P::S e = P::enc(R(feq_p<double>(i, rn[cc], ub[0], ub[1], ub[2])), R(wq(i)) * ref);
+                *dst = e;
+                // the node's density as the density pass forms it from the stored values
+                r += P::dec(e, R(wq(i)) * ref);
+            }
+            for (int d = 0; d < 3; d++) jm[d] += rn[cc] * ub[d];
             rs[cc] = r;
         }
+        bmask[n] = bm;
         psi[n] = psi_of(rs[0], bx.psi_kind);
         psi[N + n] = psi_of(rs[1], bx.psi_kind);
         if (bx.psi_kind != 0) {
             rho[n] = rs[0];
             rho[N + n] = rs[1];
         }
-        acc[0] -= jm[0];
-        acc[1] -= jm[1];
-        acc[2] -= jm[2];
-        acc[3] -= r[1] * jm[2] - r[2] * jm[1];
-        acc[4] -= r[2] * jm[0] - r[0] * jm[2];
-        acc[5] -= r[0] * jm[1] - r[1] * jm[0];
-        acc[7] += rn[0] + rn[1];
+        d[0] = -jm[0];
+        d[1] = -jm[1];
+        d[2] = -jm[2];
+        d[3] = -(r[1] * jm[2] - r[2] * jm[1]);
+        d[4] = -(r[2] * jm[0] - r[0] * jm[2]);
+        d[5] = -(r[0] * jm[1] - r[1] * jm[0]);
+        d[7] = rn[0] + rn[1];
     }
+    // every slot takes a term (zero where this kind has none), so the
+    // accumulator stays in registers
+#pragma unroll
+    for (int k = 0; k < 8; k++) acc[k] += d[k];
 }
 
 template <class P>
 __device__ inline void killfill_body(const Box& bx, typename P::S* __restrict__ f,
                                      const uint32_t* __restrict__ own_old, const uint32_t* __restrict__ own_new,
-                                     typename P::R* __restrict__ psi, typename P::R* __restrict__ rho,
+                                     uint32_t* __restrict__ bmask, typename P::R* __restrict__ psi,
+                                     typename P::R* __restrict__ rho,
                                      const double* __restrict__ part, int cap, int kext, double* __restrict__ kpart,
                                      int* __restrict__ health, int p) {
     const int Ls[3] = {bx.nx, bx.ny, bx.nz};
@@ -552,33 +584,38 @@ __device__ inline void killfill_body(const Box& bx, typename P::S* __restrict__ 
     const int total = ok ? sz[0] * sz[1] * sz[2] : 0;
     constexpr int U = 4;
     for (int base = 0; base < total; base += U * kPB) {
-        uint32_t oo[U], on[U];
-        int64_t nn[U];
-        int xs[U], ys[U], zs[U];
+        uint32_t oo[U], on[U];  // every owner load of this thread issued before any is used
 #pragma unroll
         for (int k = 0; k < U; k++) {
             const int t = base + k * kPB + threadIdx.x;
             oo[k] = on[k] = OWN_FLUID;
-            nn[k] = 0;
-            xs[k] = ys[k] = zs[k] = 0;
             if (t < total) {
                 int ix, iy, iz;
                 box_node(t, sz, ix, iy, iz);
-                xs[k] = wrapc_any(lo[0] + ix, Ls[0]);
-                ys[k] = wrapc_any(lo[1] + iy, Ls[1]);
-                zs[k] = wrapc_any(lo[2] + iz, Ls[2]);
-                nn[k] = node_index(bx, xs[k], ys[k], zs[k]);
-                oo[k] = own_old[nn[k]];
-                on[k] = own_new[nn[k]];
+                const int64_t n = node_index(bx, wrapc_any(lo[0] + ix, Ls[0]), wrapc_any(lo[1] + iy, Ls[1]),
+                                             wrapc_any(lo[2] + iz, Ls[2]));
+                oo[k] = own_old[n];
+                on[k] = own_new[n];
             }
         }
+        // one call site for the (rare) changing nodes: bit 2k marks a kill,
+        // bit 2k + 1 a fill of node k, whose coordinates are formed again
+        uint32_t todo = 0u;
 #pragma unroll
         for (int k = 0; k < U; k++) {
-            const bool kill = (oo[k] == OWN_FLUID && on[k] == (uint32_t)p);
-            const bool fill = (oo[k] == (uint32_t)p && on[k] == OWN_FLUID);
-            if (kill || fill)
-                killfill_node<P>(bx, f, own_old, own_new, psi, rho, part, cap, p, kill, xs[k], ys[k], zs[k], nn[k], Xn,
-                                 acc);
+            if (oo[k] == OWN_FLUID && on[k] == (uint32_t)p) todo |= 1u << (2 * k);
+            if (oo[k] == (uint32_t)p && on[k] == OWN_FLUID) todo |= 2u << (2 * k);
+        }
+#pragma unroll 1
+        for (int k = 0; k < U; k++) {
+            const uint32_t b = (todo >> (2 * k)) & 3u;
+            if (b == 0u) continue;
+            int ix, iy, iz;
+            box_node(base + k * kPB + threadIdx.x, sz, ix, iy, iz);
+            const int x = wrapc_any(lo[0] + ix, Ls[0]), y = wrapc_any(lo[1] + iy, Ls[1]),
+                      z = wrapc_any(lo[2] + iz, Ls[2]);
+            killfill_node<P>(bx, f, own_old, own_new, bmask, psi, rho, part, cap, p, b == 1u, x, y, z,
+                             node_index(bx, x, y, z), Xn, acc);
         }
     }
     double tot[8];
@@ -587,22 +624,22 @@ __device__ inline void killfill_body(const Box& bx, typename P::S* __restrict__ 
         for (int k = 0; k < 8; k++) kpart[(size_t)p * 8 + k] = tot[k];
 }
 template <class P>
-__global__ __launch_bounds__(kPB) void k_killfill(Box bx, typename P::S* __restrict__ f,
+__global__ __launch_bounds__(kPB, 3) void k_killfill(Box bx, typename P::S* __restrict__ f,
                                                   const uint32_t* __restrict__ own_old,
-                                                  const uint32_t* __restrict__ own_new, typename P::R* __restrict__ psi,
-                                                  typename P::R* __restrict__ rho, const double* __restrict__ part,
-                                                  int cap, int kext, double* __restrict__ kpart,
-                                                  int* __restrict__ health) {
-    killfill_body<P>(bx, f, own_old, own_new, psi, rho, part, cap, kext, kpart, health, blockIdx.x);
+                                                  const uint32_t* __restrict__ own_new, uint32_t* __restrict__ bmask,
+                                                  typename P::R* __restrict__ psi, typename P::R* __restrict__ rho,
+                                                  const double* __restrict__ part, int cap, int kext,
+                                                  double* __restrict__ kpart, int* __restrict__ health) {
+    killfill_body<P>(bx, f, own_old, own_new, bmask, psi, rho, part, cap, kext, kpart, health, blockIdx.x);
 }
 // Batched: item = (system, particle); owner copy `oo` is the old map, 1 - oo
 // the new one; populations copy `fd`.
 template <class P>
-__global__ __launch_bounds__(kPB) void k_killfill_batch(const SysDev* __restrict__ sd,
+__global__ __launch_bounds__(kPB, 3) void k_killfill_batch(const SysDev* __restrict__ sd,
                                                         const WorkItem* __restrict__ items, int oo, int fd) {
     const WorkItem w = items[blockIdx.x];
     const SysDev& d = sd[w.sys];
-    killfill_body<P>(d.box, (typename P::S*)d.f[fd], d.owner[oo], d.owner[1 - oo], (typename P::R*)d.psi,
+    killfill_body<P>(d.box, (typename P::S*)d.f[fd], d.owner[oo], d.owner[1 - oo], d.bmask[fd], (typename P::R*)d.psi,
                      (typename P::R*)d.rho, d.part, d.cap, d.kext, d.kpart, d.health, w.local);
 }
 
@@ -681,7 +718,8 @@ hipError_t launch_killfill(lb_handle* h) {
     const int kext = kill_ext(h);
     LBE_PDISPATCH(h->prm.precision,
                   hipLaunchKernelGGL(k_killfill<P>, dim3(h->np), dim3(kPB), 0, h->stream, h->box,
-                                     (typename P::S*)fn, oo, on, (typename P::R*)h->b.psi, (typename P::R*)h->b.rho,
+                                     (typename P::S*)fn, oo, on, h->b.bmask[1 - h->cur], (typename P::R*)h->b.psi,
+                                     (typename P::R*)h->b.rho,
                                      h->b.part, h->cap, kext, h->b.kpart, h->b.health));
     return hipGetLastError();
 }

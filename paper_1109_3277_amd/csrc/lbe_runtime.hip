@@ -55,6 +55,7 @@ Layout layout_of(const lb_params* p) {
     L.psi = align_up(2 * N * rho_elem_bytes(p->precision));
     L.rho = p->max_particles > 0 ? align_up(2 * N * rho_elem_bytes(p->precision)) : 0;
     L.owner = align_up(N * sizeof(uint32_t));
+    L.bmask = align_up(N * sizeof(uint32_t));
     L.part = align_up(NPFIELD * cap * sizeof(double));
     L.pfast = align_up(kPF * cap * sizeof(double));
     const double rmax = p->max_particles > 0 ? p->max_radius : 0.5;
@@ -67,8 +68,8 @@ Layout layout_of(const lb_params* p) {
     L.red = align_up((kRedBlocks + 1) * 8 * sizeof(double));
     L.counters = align_up(8 * sizeof(double));
     L.health = align_up(sizeof(int));
-    L.total = 2 * L.f + L.psi + L.rho + 2 * L.owner + L.part + L.pfast + L.slist + L.scount + L.rec + L.kpart + L.red + L.counters +
-              L.health;
+    L.total = 2 * L.f + L.psi + L.rho + 2 * L.owner + 2 * L.bmask + L.part + L.pfast + L.slist + L.scount +
+              L.rec + L.kpart + L.red + L.counters + L.health;
     return L;
 }
 
@@ -98,6 +99,8 @@ int setup_handle(lb_handle* h, const lb_params* prm, char* ws, size_t ws_bytes, 
     h->b.rho = L.rho ? p : nullptr; p += L.rho;
     h->b.owner[0] = (uint32_t*)p; p += L.owner;
     h->b.owner[1] = (uint32_t*)p; p += L.owner;
+    h->b.bmask[0] = (uint32_t*)p; p += L.bmask;
+    h->b.bmask[1] = (uint32_t*)p; p += L.bmask;
     h->b.part = (double*)p; p += L.part;
     h->b.pfast = (double*)p; p += L.pfast;
     h->b.slist = L.slist ? (uint2*)p : nullptr; p += L.slist;
@@ -113,6 +116,8 @@ int setup_handle(lb_handle* h, const lb_params* prm, char* ws, size_t ws_bytes, 
     };
     chk(launch_fill_u32(h, h->b.owner[0], OWN_FLUID, b.N), "clear owner");
     chk(launch_fill_u32(h, h->b.owner[1], OWN_FLUID, b.N), "clear owner");
+    chk(launch_fill_u32(h, h->b.bmask[0], 0u, b.N), "clear bounce masks");
+    chk(launch_fill_u32(h, h->b.bmask[1], 0u, b.N), "clear bounce masks");
     chk(launch_fill_f64(h, h->b.part, 0.0, (int64_t)NPFIELD * h->cap), "clear particles");
     chk(launch_fill_f64(h, h->b.kpart, 0.0, (int64_t)(L.kpart / sizeof(double))), "clear impulse slots");
     h->kpart_len = (int64_t)(L.kpart / sizeof(double));
@@ -305,6 +310,9 @@ int lb_add_ellipsoids(lb_handle* h, int32_t n, const double* radii, const double
     // pending kill/fill impulses move into the particle table before the
     // partial-slot layout (set by the largest radius) can change
     LBE_HIP(h, launch_fold_impulses(h));
+    // plain form first: the removal below clears every solid node's slots,
+    // where bounced populations of fluid neighbours may sit
+    LBE_HIP(h, launch_canonical(h));
     std::vector<double> t((size_t)NPFIELD * n, 0.0);
     auto F = [&](int field, int k) -> double& { return t[(size_t)field * n + k]; };
     for (int k = 0; k < n; k++) {
@@ -497,6 +505,7 @@ int lb_save_state(lb_handle* h, void* host_buf, size_t bytes) {
     if (!h->inited) return fail(h, LB_ESTATE, "fields not initialised");
     if (bytes < lb_state_bytes(h)) return fail(h, LB_EINVAL, "buffer too small");
     LBE_HIP(h, launch_fold_impulses(h));
+    LBE_HIP(h, launch_canonical(h));  // the state is stored in plain form
     const size_t N = (size_t)h->box.N;
     char* p = (char*)host_buf;
     double hdr[8] = {(double)h->np, h->box.rmean0[0], h->box.rmean0[1], h->box.rref[0], h->box.rref[1], h->rmax,
@@ -546,6 +555,7 @@ int lb_load_state(lb_handle* h, const void* host_buf, size_t bytes) {
     p += pb;
     LBE_HIP(h, hipMemcpyAsync(h->b.counters, p, 8 * sizeof(double), hipMemcpyHostToDevice, h->stream));
     LBE_HIP(h, launch_fill_u32(h, (uint32_t*)h->b.health, 0u, 1));
+    LBE_HIP(h, launch_fill_u32(h, h->b.bmask[h->cur], 0u, (int64_t)N));  // stored in plain form
     LBE_HIP(h, launch_fill_f64(h, h->b.kpart, 0.0, h->kpart_len));
     LBE_HIP(h, hipStreamSynchronize(h->stream));
     h->np = (int)hdr[0];

@@ -186,6 +186,55 @@ def test_checkpoint_roundtrip():
         assert np.array_equal(pa[k], pb[k]), k
 
 
+def test_checkpoint_save_leaves_run_unchanged():
+    """Saving stores the populations in plain form (each value in its node's
+    own slot, the values bounced into solid nodes copied out bit for bit); a
+    run with a save in the middle matches one without, bit for bit."""
+    from paper_1109_3277_amd.binding import Lattice
+
+    s = W.bijel_system(dims=(32, 32, 32), seed=23, phi=0.12)
+    log(f"case save-neutral dims={s.dims} np={s.n_particles}")
+
+    def fresh():
+        g = Lattice(s.dims, s.tau, s.g_br, max_particles=s.n_particles, max_radius=s.max_radius)
+        g.init_fields(s.rho_a, s.rho_b)
+        g.add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
+        return g
+
+    a = fresh()
+    a.step(25)
+    a.save_state()
+    a.step(25)
+    b = fresh()
+    b.step(50)
+    fa, fb = a.read_fields(), b.read_fields()
+    for k in range(4):
+        assert np.array_equal(fa[k], fb[k])
+    pa, pb = a.read_particles(), b.read_particles()
+    for k in pa:
+        assert np.array_equal(pa[k], pb[k]), k
+
+
+def test_particles_added_mid_run_fp64():
+    """A second set of particles placed after 30 steps, into a lattice whose
+    bounced populations sit in solid nodes, against the oracle doing the same."""
+    import oracle
+    from paper_1109_3277_amd.binding import Lattice
+
+    s = W.bijel_system(dims=(40, 40, 40), seed=29, phi=0.1)
+    h = s.n_particles // 2
+    log(f"case mid-run placement dims={s.dims} np={h}+{s.n_particles - h}")
+    o = oracle.Oracle(s.dims, s.tau, s.g_br)
+    g = Lattice(s.dims, s.tau, s.g_br, max_particles=s.n_particles, max_radius=s.max_radius)
+    for x in (o, g):
+        x.init_fields(s.rho_a, s.rho_b)
+        x.add_ellipsoids(s.radii[:h], s.pos[:h], s.quat[:h], s.delta_rho[:h], s.density[:h])
+        x.step(30)
+        x.add_ellipsoids(s.radii[h:], s.pos[h:], s.quat[h:], s.delta_rho[h:], s.density[h:])
+        x.step(30)
+    _check_fp64(compare(o, g, s.dims))
+
+
 def test_node_touching_three_particles_fp64():
     """A fluid node whose links end in three different particles (the most
     the kernel sums per node), the particles carrying different colours."""
