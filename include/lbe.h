@@ -138,6 +138,17 @@ int lb_stats(lb_handle* h, double out[8]);
  * (test and channel-flow use; default 0). */
 int lb_set_body_accel(lb_handle* h, const double a[3]);
 
+/* Static solid (wall) nodes, for channel tests (Couette / Poiseuille):
+ * mask[n] != 0 (N bytes, x fastest) marks node n as a wall; wall_u (3
+ * doubles, NULL for resting walls) is the velocity of every wall node.
+ * Links into a wall node take the moving bounce-back of Eq. (4) with that
+ * velocity. A wall node next to fluid takes, like a particle node, the mean
+ * density of its fluid neighbours (Eq. (10), colour 0). Walls never move or
+ * change; particles are not rasterised onto them. Must come before
+ * lb_init_fields (LB_ESTATE otherwise), which leaves wall nodes empty. The
+ * wall velocity is a property of the handle, not of a checkpoint. */
+int lb_set_static_solid(lb_handle* h, const uint8_t* mask, const double* wall_u);
+
 /* Checkpoint: lb_state_bytes() bytes of host memory hold the populations,
  * owner map, particle state and counters; lb_load_state restores them into a
  * handle created with the same parameters. The populations are stored in

@@ -19,7 +19,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "fp16_dev": 2, "bf16_dev": 3}
 EXPORTED = [
     "lb_workspace_bytes", "lb_create", "lb_destroy", "lb_init_fields", "lb_add_ellipsoids", "lb_step",
     "lb_step_async", "lb_read_fields", "lb_num_particles", "lb_read_particles", "lb_stats",
-    "lb_set_body_accel", "lb_state_bytes", "lb_save_state", "lb_load_state", "lb_last_error",
+    "lb_set_body_accel", "lb_set_static_solid", "lb_state_bytes", "lb_save_state", "lb_load_state", "lb_last_error",
     "lb_profile_enable", "lb_profile_read", "lb_probe_copy", "lb_batch_workspace_bytes", "lb_batch_create",
     "lb_batch_size", "lb_batch_system", "lb_batch_tune",
 ]
@@ -65,6 +65,7 @@ def load_library():
     L.lb_read_particles.argtypes = [vp, dp, dp, dp, dp, dp, dp]
     L.lb_stats.argtypes = [vp, dp]
     L.lb_set_body_accel.argtypes = [vp, dp]
+    L.lb_set_static_solid.argtypes = [vp, C.POINTER(C.c_uint8), dp]
     L.lb_state_bytes.restype = C.c_size_t
     L.lb_state_bytes.argtypes = [vp]
     L.lb_save_state.argtypes = [vp, vp, C.c_size_t]
@@ -183,6 +184,16 @@ class Lattice:
     def set_body_accel(self, a):
         aa = _f64(a, 3)
         self._check(load_library().lb_set_body_accel(self._h, _dp(aa)))
+
+    def set_static_solid(self, mask, wall_u=None):
+        """Wall nodes (mask, N entries, x fastest) with one velocity wall_u
+        (3 values, None for resting walls); before init_fields."""
+        m = np.ascontiguousarray(np.asarray(mask).reshape(-1) != 0, dtype=np.uint8)
+        if m.size != self.N:
+            raise ValueError("mask needs one entry per node")
+        wu = None if wall_u is None else _f64(wall_u, 3)
+        self._check(load_library().lb_set_static_solid(self._h, m.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                                     None if wu is None else _dp(wu)))
 
     def read_fields(self):
         ra, rb, u = np.zeros(self.N), np.zeros(self.N), np.zeros(3 * self.N)

@@ -27,6 +27,7 @@ struct BatchState {
     int bx = 64;      // fused tile width in use
     int parity = 0;   // index of the current population and owner copies, shared by all systems
     bool dens_ready = false;  // every system's Psi / rho match its current populations
+    bool walls = false;       // some system has wall nodes
     hipStream_t own = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraph_t graph[2] = {nullptr, nullptr};
@@ -117,11 +118,13 @@ int refresh(lb_handle* h) {
     BatchState* B = h->batch;
     const int nsys = (int)B->subs.size();
     B->h_sys.resize(nsys);
+    B->walls = false;
     for (int k = 0; k < BI_COUNT; k++) B->h_items[k].clear();
     for (int s = 0; s < nsys; s++) {
         lb_handle* q = B->subs[s];
         SysDev& d = B->h_sys[s];
         d.box = q->box;
+        B->walls = B->walls || q->box.walls != 0;
         d.f[0] = q->b.f[0];
         d.f[1] = q->b.f[1];
         d.psi = q->b.psi;
@@ -175,6 +178,7 @@ hipError_t enqueue_batch_step(BatchState* B, hipStream_t st, int c) {
     const int prec = B->precision;
     hipError_t e;
     if ((e = launch_batch_shell(bl, prec, st, c)) != hipSuccess) return e;
+    if (B->walls && (e = launch_batch_wall_shell(bl, prec, st, c)) != hipSuccess) return e;
     if ((e = launch_batch_fused(bl, prec, st, c, c)) != hipSuccess) return e;
     if ((e = launch_batch_forces(bl, st)) != hipSuccess) return e;
     if ((e = launch_batch_bodies(bl, st)) != hipSuccess) return e;

@@ -102,6 +102,8 @@ struct Box {
     double ax, ay, az;  // body acceleration
     double rref[2];  // deviation reference density per component
     double rmean0[2];  // initial global mean density per component
+    double uw[3];    // velocity of the static-solid (wall) nodes
+    int walls;       // 0: no wall nodes, 1: resting walls, 2: moving walls
 };
 
 // Element at a 32-bit byte offset from a uniform base (lets the compiler use a

@@ -419,6 +419,11 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
                 if (cb >= 0)
                     rec[((size_t)o * rstride + cb) * kRec + (i - 1)] =
                         2.0 * ((double)f0[i] + (double)f1[i]) + ((double)C0 + (double)C1);
+            } else if (bx.walls == 2 && fluid && o == OWN_WALL) {
+                // a moving wall: the same term with the wall velocity
+                const double cu = bx.uw[0] * cx(i) + bx.uw[1] * cy(i) + bx.uw[2] * cz(i);
+                C0 = R(-6.0 * wq(i) * cu) * r0;
+                C1 = R(-6.0 * wq(i) * cu) * r1;
             }
             const uint32_t mb = LBE_NB(i) * (uint32_t)sizeof(S);
             P::st(atw(fd + (size_t)i * N, mb), fluid ? f0[i] + C0 : R(0), R(wq(i)) * ref0);
@@ -770,7 +775,61 @@ __global__ __launch_bounds__(256) void k_clear_owner_batch(const SysDev* __restr
     const WorkItem w = items[blockIdx.x];
     const SysDev& d = sd[w.sys];
     const int64_t n = (int64_t)w.local * 256 + threadIdx.x;
-    if (n < d.box.N) d.owner[o][n] = OWN_FLUID;
+    if (n < d.box.N) d.owner[o][n] = (d.box.walls && d.owner[1 - o][n] == OWN_WALL) ? OWN_WALL : OWN_FLUID;
+}
+// Eq. (10) for wall nodes (colour 0): a wall node with fluid neighbours
+// (over the 18 links) takes their mean density, stored as Psi; 0 without
+// fluid neighbours. Densities of fluid nodes: the stored rho where kept, else
+// Psi itself (Psi = rho) or recovered from it.
+template <class R>
+__device__ inline void wall_shell_node(const Box& bx, R* __restrict__ psi, const R* __restrict__ rho,
+                                       const uint32_t* __restrict__ owner, int64_t n) {
+    if (owner[n] != OWN_WALL) return;
+    const int64_t N = bx.N;
+    int x, y, z;
+    node_xyz(bx, (uint32_t)n, x, y, z);
+    R s0 = R(0), s1 = R(0);
+    int k = 0;
+    for (int i = 1; i < Q; i++) {
+        const uint32_t m = upstream(bx.nx, bx.ny, bx.nz, x, y, z, opp(i));  // n + c_i
+        if (owner[m] != OWN_FLUID) continue;
+        R d0, d1;
+        if (bx.psi_kind == 0) {
+            d0 = psi[m];
+            d1 = psi[N + m];
+        } else if (rho) {
+            d0 = rho[m];
+            d1 = rho[N + m];
+        } else {
+            d0 = rho_of_psi(psi[m], 1);
+            d1 = rho_of_psi(psi[N + m], 1);
+        }
+        s0 += d0;
+        s1 += d1;
+        k++;
+    }
+    psi[n] = k == 0 ? R(0) : psi_of(s0 / R(k), bx.psi_kind);
+    psi[N + n] = k == 0 ? R(0) : psi_of(s1 / R(k), bx.psi_kind);
+}
+template <class R>
+__global__ __launch_bounds__(256) void k_wall_shell(Box bx, R* __restrict__ psi, const R* __restrict__ rho,
+                                                    const uint32_t* __restrict__ owner) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < bx.N) wall_shell_node<R>(bx, psi, rho, owner, n);
+}
+template <class R>
+__global__ __launch_bounds__(256) void k_wall_shell_batch(const SysDev* __restrict__ sd,
+                                                          const WorkItem* __restrict__ items, int o) {
+    const WorkItem w = items[blockIdx.x];
+    const SysDev& d = sd[w.sys];
+    if (d.box.walls == 0) return;
+    const int64_t n = (int64_t)w.local * 256 + threadIdx.x;
+    if (n < d.box.N) wall_shell_node<R>(d.box, (R*)d.psi, (const R*)d.rho, d.owner[o], n);
+}
+// Owner copy cleared for re-rasterisation, wall nodes kept (from the current copy).
+__global__ void k_clear_keep_walls(uint32_t* __restrict__ dst, const uint32_t* __restrict__ cur, int64_t n) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        dst[k] = cur[k] == OWN_WALL ? OWN_WALL : OWN_FLUID;
 }
 __global__ void k_fill_f64(double* __restrict__ p, double v, int64_t n) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
@@ -931,6 +990,33 @@ hipError_t launch_fill_u32(lb_handle* h, uint32_t* p, uint32_t v, int64_t n) {
     if (g > 65536) g = 65536;
     if (g == 0) g = 1;
     hipLaunchKernelGGL(k_fill_u32, dim3(g), dim3(256), 0, h->stream, p, v, n);
+    return hipGetLastError();
+}
+hipError_t launch_wall_shell(lb_handle* h) {
+    if (!h->box.walls) return hipSuccess;
+    const void* rho = (h->has_solid && h->prm.psi_kind != 0) ? h->b.rho : nullptr;
+    if (h->prm.precision == LB_FP64)
+        hipLaunchKernelGGL(k_wall_shell<double>, dim3(nblk(h->box.N)), dim3(256), 0, h->stream, h->box,
+                           (double*)h->b.psi, (const double*)rho, h->b.owner[h->ocur]);
+    else
+        hipLaunchKernelGGL(k_wall_shell<float>, dim3(nblk(h->box.N)), dim3(256), 0, h->stream, h->box,
+                           (float*)h->b.psi, (const float*)rho, h->b.owner[h->ocur]);
+    return hipGetLastError();
+}
+hipError_t launch_batch_wall_shell(const BatchLaunch& bl, int precision, hipStream_t st, int o) {
+    if (precision == LB_FP64)
+        hipLaunchKernelGGL(k_wall_shell_batch<double>, dim3(bl.n[BI_NODE]), dim3(256), 0, st, bl.sys,
+                           bl.items[BI_NODE], o);
+    else
+        hipLaunchKernelGGL(k_wall_shell_batch<float>, dim3(bl.n[BI_NODE]), dim3(256), 0, st, bl.sys,
+                           bl.items[BI_NODE], o);
+    return hipGetLastError();
+}
+hipError_t launch_clear_keep_walls(lb_handle* h, uint32_t* dst, const uint32_t* cur) {
+    unsigned g = nblk(h->box.N);
+    if (g > 65536) g = 65536;
+    if (g == 0) g = 1;
+    hipLaunchKernelGGL(k_clear_keep_walls, dim3(g), dim3(256), 0, h->stream, dst, cur, h->box.N);
     return hipGetLastError();
 }
 hipError_t launch_fill_f64(lb_handle* h, double* p, double v, int64_t n) {

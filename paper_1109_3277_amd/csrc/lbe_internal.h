@@ -106,6 +106,7 @@ void batch_touch(lb_handle* sub);  // a system changed: its batch refreshes its 
 hipError_t launch_batch_density(const BatchLaunch& bl, int precision, hipStream_t st, int c, int o, int oo);
 hipError_t launch_batch_fused(const BatchLaunch& bl, int precision, hipStream_t st, int c, int o);
 hipError_t launch_batch_clear_owner(const BatchLaunch& bl, hipStream_t st, int o);
+hipError_t launch_batch_wall_shell(const BatchLaunch& bl, int precision, hipStream_t st, int o);
 hipError_t launch_batch_shell(const BatchLaunch& bl, int precision, hipStream_t st, int o);
 hipError_t launch_batch_forces(const BatchLaunch& bl, hipStream_t st);
 hipError_t launch_batch_bodies(const BatchLaunch& bl, hipStream_t st);
@@ -134,6 +135,8 @@ hipError_t launch_bodies(lb_handle* h);
 hipError_t launch_pack_fast(lb_handle* h);  // packed particle copy from the particle table
 hipError_t launch_raster(lb_handle* h, uint32_t* owner, int first, int count);
 hipError_t launch_clear_owner(lb_handle* h, uint32_t* owner);
+hipError_t launch_clear_keep_walls(lb_handle* h, uint32_t* dst, const uint32_t* cur);  // walls copied from cur
+hipError_t launch_wall_shell(lb_handle* h);  // Psi of wall nodes next to fluid
 hipError_t launch_killfill(lb_handle* h);
 hipError_t launch_fold_impulses(lb_handle* h);
 int raster_extent(int nx, int ny, int nz, double rb);

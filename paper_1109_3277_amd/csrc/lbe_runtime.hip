@@ -92,6 +92,8 @@ int setup_handle(lb_handle* h, const lb_params* prm, char* ws, size_t ws_bytes, 
     b.ax = b.ay = b.az = 0.0;
     b.rref[0] = b.rref[1] = 0.0;
     b.rmean0[0] = b.rmean0[1] = 0.0;
+    b.uw[0] = b.uw[1] = b.uw[2] = 0.0;
+    b.walls = 0;
     char* p = h->ws;
     h->b.f[0] = p; p += L.f;
     h->b.f[1] = p; p += L.f;
@@ -171,13 +173,17 @@ int enqueue_step(lb_handle* h) {
     if (!h->dens_ready) LBE_PHASE(h, 0, launch_density(h, h->cur, h->ocur, -1));
     h->dens_ready = false;
     if (h->np > 0) LBE_PHASE(h, 1, launch_shell(h));
+    if (h->box.walls) LBE_PHASE(h, 1, launch_wall_shell(h));
     LBE_PHASE(h, 2, launch_fused(h));
     if (h->np > 0) {
         LBE_PHASE(h, 3, launch_forces(h));
         LBE_PHASE(h, 4, launch_bodies(h));
         uint32_t* on = h->b.owner[1 - h->ocur];
         LBE_HIP(h, mark(h, 5, true));
-        LBE_HIP(h, launch_clear_owner(h, on));
+        if (h->box.walls)
+            LBE_HIP(h, launch_clear_keep_walls(h, on, h->b.owner[h->ocur]));
+        else
+            LBE_HIP(h, launch_clear_owner(h, on));
         LBE_HIP(h, launch_raster(h, on, 0, h->np));
         LBE_HIP(h, mark(h, 5, false));
         LBE_PHASE(h, 0, launch_density(h, 1 - h->cur, 1 - h->ocur, h->ocur));
@@ -491,6 +497,33 @@ int lb_set_body_accel(lb_handle* h, const double a[3]) {
     return LB_OK;
 }
 
+int lb_set_static_solid(lb_handle* h, const uint8_t* mask, const double* wall_u) {
+    if (!h || !mask) return LB_EINVAL;
+    LBE_NOT_BATCH(h);
+    if (h->inited) return fail(h, LB_ESTATE, "lb_set_static_solid must come before lb_init_fields");
+    double u[3] = {0.0, 0.0, 0.0};
+    if (wall_u)
+        for (int d = 0; d < 3; d++) {
+            if (!isfinite(wall_u[d])) return fail(h, LB_EINVAL, "non-finite wall velocity");
+            u[d] = wall_u[d];
+        }
+    const size_t N = (size_t)h->box.N;
+    std::vector<uint32_t> ow(N);
+    bool any = false;
+    for (size_t n = 0; n < N; n++) {
+        ow[n] = mask[n] ? OWN_WALL : OWN_FLUID;
+        any = any || mask[n];
+    }
+    for (int k = 0; k < 2; k++)
+        LBE_HIP(h, hipMemcpyAsync(h->b.owner[k], ow.data(), N * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream));
+    LBE_HIP(h, hipStreamSynchronize(h->stream));
+    for (int d = 0; d < 3; d++) h->box.uw[d] = u[d];
+    h->box.walls = !any ? 0 : ((u[0] != 0.0 || u[1] != 0.0 || u[2] != 0.0) ? 2 : 1);
+    h->has_solid = h->np > 0 || any;
+    batch_touch(h);
+    return LB_OK;
+}
+
 // State image: [header 8 doubles][populations][owner][particle table][counters 8].
 size_t lb_state_bytes(const lb_handle* h) {
     if (!h) return 0;
@@ -531,6 +564,7 @@ int lb_load_state(lb_handle* h, const void* host_buf, size_t bytes) {
     if (bytes < lb_state_bytes(h)) return fail(h, LB_EINVAL, "buffer too small");
     const size_t N = (size_t)h->box.N;
     const char* p = (const char*)host_buf;
+    bool any_wall = false;
     double hdr[8];
     memcpy(hdr, p, sizeof hdr);
     p += sizeof hdr;
@@ -542,9 +576,11 @@ int lb_load_state(lb_handle* h, const void* host_buf, size_t bytes) {
         // owner codes must be fluid, wall, or an index below the particle count
         const uint32_t* ow = (const uint32_t*)(p + fb);
         const uint32_t np = (uint32_t)hdr[0];
-        for (size_t n = 0; n < N; n++)
+        for (size_t n = 0; n < N; n++) {
             if (ow[n] != OWN_FLUID && ow[n] != OWN_WALL && ow[n] >= np)
                 return fail(h, LB_EINVAL, "state holds an invalid owner code");
+            any_wall = any_wall || ow[n] == OWN_WALL;
+        }
     }
     LBE_HIP(h, hipMemcpyAsync(h->b.f[h->cur], p, fb, hipMemcpyHostToDevice, h->stream));
     p += fb;
@@ -564,7 +600,10 @@ int lb_load_state(lb_handle* h, const void* host_buf, size_t bytes) {
     h->box.rref[0] = hdr[3];
     h->box.rref[1] = hdr[4];
     h->rmax = hdr[5];
-    h->has_solid = h->np > 0;
+    // wall nodes come with the owner map; their velocity is the handle's own
+    const bool moving = h->box.uw[0] != 0.0 || h->box.uw[1] != 0.0 || h->box.uw[2] != 0.0;
+    h->box.walls = !any_wall ? 0 : (moving ? 2 : 1);
+    h->has_solid = h->np > 0 || any_wall;
     LBE_HIP(h, launch_pack_fast(h));
     h->inited = true;
     h->dens_ready = false;
