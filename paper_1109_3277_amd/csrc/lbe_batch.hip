@@ -132,8 +132,6 @@ int refresh(lb_handle* h) {
         d.owner[0] = q->b.owner[0];
         d.owner[1] = q->b.owner[1];
         d.part = q->b.part;
-        d.slist = q->b.slist;
-        d.scount = q->b.scount;
         d.bmask[0] = q->b.bmask[0];
         d.bmask[1] = q->b.bmask[1];
         d.rec = q->b.rec;
@@ -143,7 +141,6 @@ int refresh(lb_handle* h) {
         d.cap = q->cap;
         d.np = q->np;
         tiles_for(q->prm, B->bx, d.tiles_x, d.tiles_y);
-        d.nseg = surf_nseg(q);
         d.kext = kill_ext(q);
         const int nnode = (int)((q->box.N + 255) / 256);
         const int ntile = d.tiles_x * d.tiles_y * q->box.nz;
@@ -384,8 +381,9 @@ int lb_batch_tune(lb_handle* h, int32_t* tile_width) {
     BatchState* B = h->batch;
     int rc = check_ready(h);
     if (rc != LB_OK) return rc;
-    // the fused launch only writes the next population copy, which the next
-    // step rewrites whole: timing it leaves the state untouched
+    // the fused launch only writes the next population copy and its masks,
+    // which the next step rewrites whole, and link records (cleared below):
+    // timing it leaves the state untouched
     const int c = B->parity;
     hipEvent_t e0, e1;
     LBE_HIP_OR_FAIL(h, hipEventCreate(&e0));
@@ -413,6 +411,12 @@ int lb_batch_tune(lb_handle* h, int32_t* tile_width) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != LB_OK) return rc;
+    // the timed launches also wrote link records, which the force pass would
+    // otherwise have read and cleared: clear them
+    for (lb_handle* q : B->subs) {
+        const size_t rb = layout_of(&q->prm).rec;
+        if (rb) LBE_HIP_OR_FAIL(h, launch_fill_f64(h, q->b.rec, 0.0, (int64_t)(rb / sizeof(double))));
+    }
     B->bx = best_bx;
     rc = refresh(h);
     if (rc != LB_OK) return rc;

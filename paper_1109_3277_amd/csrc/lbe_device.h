@@ -202,22 +202,17 @@ struct Tiles {
 };
 
 // Per-particle kernels run one block of kPB threads per particle, looping
-// over the nodes of the particle's box in chunks of kPB nodes. The surface
-// list of a particle is split into segments of 64 entries, one per (chunk,
-// wave); a box of edge at most `ext` needs surf_segments(ext) segments.
+// over the nodes of the particle's box in chunks of kPB nodes.
 constexpr int kPB = 256;
-__host__ __device__ inline int surf_segments(int ext) {
-    const int cells = ext * ext * ext;
-    return (kPB / 64) * ((cells + kPB - 1) / kPB);
-}
 
 // Link records of a particle: one record of kRec doubles per node of its
 // record box (its bounding box grown by one node on every side, each edge at
-// most the lattice edge; x fastest). Slot i - 1 of the record of fluid node n
-// holds the momentum exchange 2 f*_i(n) + C of the link n -> n + c_i, summed
-// over both components, when n + c_i is a node of the particle; only the
-// slots of the current step's links are live.
-constexpr int kRec = 18;
+// most the lattice edge; x fastest). The record of fluid node n holds the
+// node's momentum-exchange force on the particle, the sum over its links
+// n -> n + c_i into the particle of (2 f*_i + C) c_i over both components.
+// Records are zero between steps: the fused kernel writes those of its links,
+// the force pass reads and clears them.
+constexpr int kRec = 3;
 
 // Record cell of node xyz for a particle whose bounding box is (lo, sz), or
 // -1 when the node lies outside the record box.
@@ -254,15 +249,12 @@ struct SysDev {
     uint32_t* owner[2];
     uint32_t* bmask[2];  // bounce masks of population copy 0 / 1
     double* part;
-    uint2* slist;
-    int* scount;
     double* rec;
     double* pfast;
     double* kpart;
     int* health;
     int cap, np;
     int tiles_x, tiles_y;
-    int nseg;  // surface-list segments per particle
     int kext;  // largest kill/fill box edge of a normal step
 };
 

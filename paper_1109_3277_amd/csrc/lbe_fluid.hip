@@ -156,9 +156,9 @@ __global__ __launch_bounds__(256) void k_density_batch(const SysDev* __restrict_
 // body the surface velocity at the link midpoint, V + W x (r_n + c_i/2), has
 // the same projection on c_i as U_n = V + W x r_n at the node (W x c_i is
 // normal to c_i), so C needs one U_n per node and particle. The particle's
-// share (2 f*_i + C) c_i of Eq. (5) is not summed here: each link writes
-// 2 f*_i + C (both components) into slot i of node n's record of that
-// particle; k_linkforce sums the records.
+// share (2 f*_i + C) c_i of Eq. (5) is summed per node and particle and
+// written into node n's record of that particle; k_linkforce sums the
+// records (force, and torque r_n x force).
 
 // Moments, Shan-Chen velocity shift and BGK relaxation of one node, in place
 // on f0 / f1 (component A / B). q0[i], q1[i]: Psi^A, Psi^B of neighbour i.
@@ -392,7 +392,10 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
         }
         // one store per direction, to (i, n + c_i) on every lane: f*_i for a
         // fluid target, the bounced f*_i + C for a solid one, zero from a
-        // solid lane; a particle link also writes its record slot
+        // solid lane. A particle link adds its momentum exchange
+        // (2 f*_i + C) c_i to the node's force on that particle: in registers
+        // for the first two particles, in the record itself for others.
+        double F1[3] = {0.0, 0.0, 0.0}, F2[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int i = 1; i < Q; i++) {
             const uint32_t o = on[i];
@@ -416,9 +419,21 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
                 const double cu = Ux * cx(i) + Uy * cy(i) + Uz * cz(i);
                 C0 = R(-6.0 * wq(i) * cu) * r0;
                 C1 = R(-6.0 * wq(i) * cu) * r1;
-                if (cb >= 0)
-                    rec[((size_t)o * rstride + cb) * kRec + (i - 1)] =
-                        2.0 * ((double)f0[i] + (double)f1[i]) + ((double)C0 + (double)C1);
+                const double mag = 2.0 * ((double)f0[i] + (double)f1[i]) + ((double)C0 + (double)C1);
+                if (o == p1) {
+                    F1[0] += mag * cx(i);
+                    F1[1] += mag * cy(i);
+                    F1[2] += mag * cz(i);
+                } else if (o == p2) {
+                    F2[0] += mag * cx(i);
+                    F2[1] += mag * cy(i);
+                    F2[2] += mag * cz(i);
+                } else if (cb >= 0) {  // a third particle (rare): this lane alone updates the record
+                    double* r = rec + ((size_t)o * rstride + cb) * kRec;
+                    r[0] += mag * cx(i);
+                    r[1] += mag * cy(i);
+                    r[2] += mag * cz(i);
+                }
             } else if (bx.walls == 2 && fluid && o == OWN_WALL) {
                 // a moving wall: the same term with the wall velocity
                 const double cu = bx.uw[0] * cx(i) + bx.uw[1] * cy(i) + bx.uw[2] * cz(i);
@@ -428,6 +443,18 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
             const uint32_t mb = LBE_NB(i) * (uint32_t)sizeof(S);
             P::st(atw(fd + (size_t)i * N, mb), fluid ? f0[i] + C0 : R(0), R(wq(i)) * ref0);
             P::st(atw(fd + (size_t)(Q + i) * N, mb), fluid ? f1[i] + C1 : R(0), R(wq(i)) * ref1);
+        }
+        if (fluid && p1 < OWN_WALL && cb1 >= 0) {
+            double* r = rec + ((size_t)p1 * rstride + cb1) * kRec;
+            r[0] = F1[0];
+            r[1] = F1[1];
+            r[2] = F1[2];
+        }
+        if (fluid && p2 < OWN_WALL && cb2 >= 0) {
+            double* r = rec + ((size_t)p2 * rstride + cb2) * kRec;
+            r[0] = F2[0];
+            r[1] = F2[1];
+            r[2] = F2[2];
         }
     }
 #undef LBE_NB

@@ -20,8 +20,6 @@ struct Buffers {
     uint32_t* owner[2] = {nullptr, nullptr};
     uint32_t* bmask[2] = {nullptr, nullptr};  // bounce masks of population copy 0 / 1 (per node)
     double* part = nullptr;            // particle table, NPFIELD x cap
-    uint2* slist = nullptr;            // surface list segments, cap x nseg x 64 (node, link mask)
-    int* scount = nullptr;             // entries per surface list segment, cap x nseg
     double* rec = nullptr;             // link records, cap x kext^3 cells x kRec
     double* pfast = nullptr;           // packed particle copy read by the fused kernel, cap x kPF
     double* kpart = nullptr;           // kill/fill impulse and masses of the last step, cap x 8
@@ -88,7 +86,7 @@ namespace lbe {
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
-    size_t f, psi, rho, owner, bmask, part, pfast, slist, scount, rec, kpart, red, counters, health, total;
+    size_t f, psi, rho, owner, bmask, part, pfast, rec, kpart, red, counters, health, total;
 };
 bool params_ok(const lb_params* p, std::string* why);
 Layout layout_of(const lb_params* p);
@@ -112,7 +110,6 @@ hipError_t launch_batch_forces(const BatchLaunch& bl, hipStream_t st);
 hipError_t launch_batch_bodies(const BatchLaunch& bl, hipStream_t st);
 hipError_t launch_batch_raster(const BatchLaunch& bl, hipStream_t st, int o);
 hipError_t launch_batch_killfill(const BatchLaunch& bl, int precision, hipStream_t st, int oo, int fd);
-int surf_nseg(const lb_handle* h);    // surface-list segments per particle at the current largest radius
 int kill_ext(const lb_handle* h);     // kill/fill box edge bound at the current largest radius
 
 size_t elem_bytes(int precision);

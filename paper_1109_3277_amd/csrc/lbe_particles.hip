@@ -97,187 +97,136 @@ __global__ __launch_bounds__(kPB) void k_raster_batch(const SysDev* __restrict__
 // takes their mean density; the particle colour is added to A if positive,
 // its magnitude to B if negative. Densities are recovered from the stored
 // Psi and the result is stored as Psi.
-// The same pass lists p's surface: every node of p with a fluid neighbour, as
-// (node, mask) with bit i set when the node's neighbour at -c_i is fluid.
-// One block loops over p's box in chunks of kPB nodes; each wave of a chunk
-// writes its own segment of 64 entries (lane order) and its count, for every
-// one of the nseg segments (so stale segments read as empty).
+// One block loops over p's box; only nodes of p change.
 template <class R>
 __device__ inline void shell_body(const Box& bx, R* __restrict__ psi, const R* __restrict__ rho,
                                   const uint32_t* __restrict__ owner, const double* __restrict__ part, int cap,
-                                  int nseg, uint2* __restrict__ slist, int* __restrict__ scount, int p) {
+                                  int p) {
     const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
     const int64_t N = bx.N;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int lo[3], sz[3];
     const int total = particle_box(bx, part, cap, p, lo, sz) ? sz[0] * sz[1] * sz[2] : 0;
     // densities of fluid nodes: the stored rho (Psi itself when Psi = rho)
     const R* dens = bx.psi_kind == 0 ? psi : rho;
     const double dr = part[DRHO * cap + p];
-    const int nchunk = nseg / (kPB / 64);
-    for (int c = 0; c < nchunk; c++) {
-        const int t = c * kPB + threadIdx.x;
-        uint32_t mask = 0u;
-        int64_t n = 0;
-        if (t < total) {
-            int ix, iy, iz;
-            box_node(t, sz, ix, iy, iz);
-            const int x = wrapc_any(lo[0] + ix, nx), y = wrapc_any(lo[1] + iy, ny), z = wrapc_any(lo[2] + iz, nz);
-            n = node_index(bx, x, y, z);
-            if (owner[n] == (uint32_t)p) {
-                uint32_t on[Q];
-                R d0[Q], d1[Q];
+    for (int t = threadIdx.x; t < total; t += kPB) {
+        int ix, iy, iz;
+        box_node(t, sz, ix, iy, iz);
+        const int x = wrapc_any(lo[0] + ix, nx), y = wrapc_any(lo[1] + iy, ny), z = wrapc_any(lo[2] + iz, nz);
+        const int64_t n = node_index(bx, x, y, z);
+        if (owner[n] != (uint32_t)p) continue;
+        uint32_t on[Q];
+        R d0[Q], d1[Q];
 #pragma unroll
-                for (int i = 1; i < Q; i++) {
-                    const int64_t m =
-                        node_index(bx, wrapc(x + cx(i), nx), wrapc(y + cy(i), ny), wrapc(z + cz(i), nz));
-                    on[i] = owner[m];
-                    d0[i] = dens[m];
-                    d1[i] = dens[N + m];
-                }
-                R s0 = R(0), s1 = R(0);
-                int k = 0;
+        for (int i = 1; i < Q; i++) {
+            const int64_t m = node_index(bx, wrapc(x + cx(i), nx), wrapc(y + cy(i), ny), wrapc(z + cz(i), nz));
+            on[i] = owner[m];
+            d0[i] = dens[m];
+            d1[i] = dens[N + m];
+        }
+        R s0 = R(0), s1 = R(0);
+        int k = 0;
 #pragma unroll
-                for (int i = 1; i < Q; i++) {
-                    if (on[i] != OWN_FLUID) continue;
-                    s0 += d0[i];
-                    s1 += d1[i];
-                    k++;
-                    mask |= 1u << opp(i);
-                }
-                if (k == 0) {
-                    psi[n] = R(0);
-                    psi[N + n] = R(0);
-                } else {
-                    R a = s0 / R(k), b = s1 / R(k);
-                    if (dr > 0.0) a += R(dr);
-                    else if (dr < 0.0) b += R(-dr);
-                    psi[n] = psi_of(a, bx.psi_kind);
-                    psi[N + n] = psi_of(b, bx.psi_kind);
-                }
-            }
+        for (int i = 1; i < Q; i++) {
+            if (on[i] != OWN_FLUID) continue;
+            s0 += d0[i];
+            s1 += d1[i];
+            k++;
         }
-        const unsigned long long bal = __ballot(mask != 0u);
-        const size_t seg = (size_t)p * nseg + c * (kPB / 64) + w;
-        if (mask != 0u) {
-            const int pos = __popcll(bal & ((1ull << lane) - 1ull));
-            slist[seg * 64 + pos] = make_uint2((uint32_t)n, mask);
+        if (k == 0) {
+            psi[n] = R(0);
+            psi[N + n] = R(0);
+        } else {
+            R a = s0 / R(k), b = s1 / R(k);
+            if (dr > 0.0) a += R(dr);
+            else if (dr < 0.0) b += R(-dr);
+            psi[n] = psi_of(a, bx.psi_kind);
+            psi[N + n] = psi_of(b, bx.psi_kind);
         }
-        if (lane == 0) scount[seg] = __popcll(bal);
     }
 }
 template <class R>
 __global__ __launch_bounds__(kPB) void k_shell(Box bx, R* __restrict__ psi, const R* __restrict__ rho,
                                                const uint32_t* __restrict__ owner, const double* __restrict__ part,
-                                               int cap, int nseg, uint2* __restrict__ slist,
-                                               int* __restrict__ scount) {
-    shell_body<R>(bx, psi, rho, owner, part, cap, nseg, slist, scount, blockIdx.x);
+                                               int cap) {
+    shell_body<R>(bx, psi, rho, owner, part, cap, blockIdx.x);
 }
 template <class R>
 __global__ __launch_bounds__(kPB) void k_shell_batch(const SysDev* __restrict__ sd, const WorkItem* __restrict__ items,
                                                      int o) {
     const WorkItem w = items[blockIdx.x];
     const SysDev& d = sd[w.sys];
-    shell_body<R>(d.box, (R*)d.psi, (const R*)d.rho, d.owner[o], d.part, d.cap, d.nseg, d.slist, d.scount, w.local);
+    shell_body<R>(d.box, (R*)d.psi, (const R*)d.rho, d.owner[o], d.part, d.cap, w.local);
 }
 
 // ---------------------------------------------------------------- S6 forces
-// Bounce-back force and torque of particle p (Eq. (5)), link by link from the
-// solid end. A surface node m of p and a direction i whose source n = m - c_i
-// is fluid form the link n -> m; the fused kernel wrote the link's momentum
-// exchange 2 f*_i(n) + C (both components, C = -6 w_i rho^c(n) (U_n . c_i))
-// into slot i of n's record of p, so the force is the sum of record * c_i and
-// the torque the sum of r_n x (record * c_i). One block per particle walks
-// p's surface list (the shell pass wrote it for the same owner map): entry e
-// goes to thread e mod 256, entries and links in increasing order, then a
-// fixed block sum, so the result is reproducible bit for bit.
-__device__ inline void linkforce_body(const Box& bx, const double* __restrict__ rec, int rstride,
-                                      double* __restrict__ part, int cap, int nseg,
-                                      const uint2* __restrict__ slist, const int* __restrict__ scount, int p) {
-    __shared__ int s_pre[257];
-    __shared__ int s_wsum[4];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
-    const int Ls[3] = {nx, ny, nz};
+// Bounce-back force and torque of particle p (Eq. (5)). The fused kernel left,
+// for every fluid node n linked to p, the node's force F_n = sum over its
+// links into p of (2 f*_i + C) c_i (both components) in p's record cell of n.
+// The force is the sum of the F_n and the torque the sum of r_n x F_n. One
+// block per particle walks the record box: cell c goes to thread c mod kPB,
+// each thread's cells in increasing order, then a fixed block sum, so the
+// result is reproducible bit for bit. Records read are cleared for the next
+// step.
+__device__ inline void linkforce_body(const Box& bx, double* __restrict__ rec, int rstride,
+                                      double* __restrict__ part, int cap, int p) {
+    const int Ls[3] = {bx.nx, bx.ny, bx.nz};
     const double X[3] = {part[PX * cap + p], part[PY * cap + p], part[PZ * cap + p]};
-    int lo[3], sz[3];
+    int lo[3], sz[3], esz[3];
     const bool ok = particle_box(bx, part, cap, p, lo, sz);
+    for (int d = 0; d < 3; d++) esz[d] = min(sz[d] + 2, Ls[d]);
+    const int cells = ok ? esz[0] * esz[1] * esz[2] : 0;
+    double* rp = rec + (size_t)p * rstride * kRec;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int c0 = 0; ok && c0 < nseg; c0 += 256) {
-        const int nc = min(256, nseg - c0);
-        // exclusive prefix of the segment counts of this chunk
-        const int cnt = tid < nc ? scount[(size_t)p * nseg + c0 + tid] : 0;
-        int v = cnt;
-        for (int off = 1; off < 64; off <<= 1) {
-            const int u = __shfl_up(v, off, 64);
-            if (lane >= off) v += u;
-        }
-        if (lane == 63) s_wsum[w] = v;
-        __syncthreads();
-        int base = 0;
-        for (int j = 0; j < w; j++) base += s_wsum[j];
-        s_pre[tid] = base + v - cnt;
-        if (tid == 255) s_pre[256] = base + v;
-        __syncthreads();
-        const int total = s_pre[256];
-        for (int e = tid; e < total; e += 256) {
-            int a = 0, b = nc - 1;  // last segment whose prefix is <= e
-            while (a < b) {
-                const int mid = (a + b + 1) >> 1;
-                if (s_pre[mid] <= e) a = mid;
-                else b = mid - 1;
-            }
-            const uint2 ent = slist[((size_t)p * nseg + c0 + a) * 64 + (e - s_pre[a])];
-            const uint32_t m = ent.x, mask = ent.y;
-            const int mz = (int)(m / (uint32_t)(nx * ny));
-            const int rem = (int)(m - (uint32_t)mz * (uint32_t)(nx * ny));
-            const int my = rem / nx, mx = rem - my * nx;
-            double g[Q - 1];
-            int nn[Q - 1][3];
+    constexpr int U = 4;  // cells per thread in flight
+    for (int base = 0; base < cells; base += U * kPB) {
+        double F[U][3];
 #pragma unroll
-            for (int i = 1; i < Q; i++) {
-                nn[i - 1][0] = wrapc(mx - cx(i), nx);
-                nn[i - 1][1] = wrapc(my - cy(i), ny);
-                nn[i - 1][2] = wrapc(mz - cz(i), nz);
-                const int cb = (mask & (1u << i)) ? rec_cell(nn[i - 1], lo, sz, Ls) : -1;
-                g[i - 1] = cb >= 0 ? rec[((size_t)p * rstride + cb) * kRec + (i - 1)] : 0.0;
-            }
-#pragma unroll
-            for (int i = 1; i < Q; i++) {
-                if (!(mask & (1u << i))) continue;
-                const double rx = minimg((double)nn[i - 1][0] - X[0], nx);
-                const double ry = minimg((double)nn[i - 1][1] - X[1], ny);
-                const double rz = minimg((double)nn[i - 1][2] - X[2], nz);
-                const double mag = g[i - 1];
-                const double Fx = mag * cx(i), Fy = mag * cy(i), Fz = mag * cz(i);
-                acc[0] += Fx;
-                acc[1] += Fy;
-                acc[2] += Fz;
-                acc[3] += ry * Fz - rz * Fy;
-                acc[4] += rz * Fx - rx * Fz;
-                acc[5] += rx * Fy - ry * Fx;
+        for (int k = 0; k < U; k++) {
+            const int c = base + k * kPB + (int)threadIdx.x;
+            F[k][0] = F[k][1] = F[k][2] = 0.0;
+            if (c < cells) {
+                F[k][0] = rp[(size_t)c * kRec];
+                F[k][1] = rp[(size_t)c * kRec + 1];
+                F[k][2] = rp[(size_t)c * kRec + 2];
             }
         }
-        __syncthreads();  // s_pre / s_wsum are rewritten by the next chunk
+#pragma unroll
+        for (int k = 0; k < U; k++) {
+            if (F[k][0] == 0.0 && F[k][1] == 0.0 && F[k][2] == 0.0) continue;
+            const int c = base + k * kPB + (int)threadIdx.x;
+            rp[(size_t)c * kRec] = 0.0;
+            rp[(size_t)c * kRec + 1] = 0.0;
+            rp[(size_t)c * kRec + 2] = 0.0;
+            const int ox = c % esz[0], oy = (c / esz[0]) % esz[1], oz = c / (esz[0] * esz[1]);
+            const double rx = minimg((double)wrapc_any(lo[0] - 1 + ox, Ls[0]) - X[0], Ls[0]);
+            const double ry = minimg((double)wrapc_any(lo[1] - 1 + oy, Ls[1]) - X[1], Ls[1]);
+            const double rz = minimg((double)wrapc_any(lo[2] - 1 + oz, Ls[2]) - X[2], Ls[2]);
+            acc[0] += F[k][0];
+            acc[1] += F[k][1];
+            acc[2] += F[k][2];
+            acc[3] += ry * F[k][2] - rz * F[k][1];
+            acc[4] += rz * F[k][0] - rx * F[k][2];
+            acc[5] += rx * F[k][1] - ry * F[k][0];
+        }
     }
     double tot[6];
     block_sum<6>(acc, tot);
-    if (tid == 0) {
+    if (threadIdx.x == 0) {
         const int fld[6] = {FX, FY, FZ, TX, TY, TZ};
         for (int k = 0; k < 6; k++) part[fld[k] * cap + p] = tot[k];
     }
 }
-__global__ __launch_bounds__(256) void k_linkforce(Box bx, const double* __restrict__ rec, int rstride,
-                                                   double* __restrict__ part, int cap, int nseg,
-                                                   const uint2* __restrict__ slist, const int* __restrict__ scount) {
-    linkforce_body(bx, rec, rstride, part, cap, nseg, slist, scount, blockIdx.x);
+__global__ __launch_bounds__(kPB) void k_linkforce(Box bx, double* __restrict__ rec, int rstride,
+                                                   double* __restrict__ part, int cap) {
+    linkforce_body(bx, rec, rstride, part, cap, blockIdx.x);
 }
 // Batched: item = (system, particle).
-__global__ __launch_bounds__(256) void k_linkforce_batch(const SysDev* __restrict__ sd,
+__global__ __launch_bounds__(kPB) void k_linkforce_batch(const SysDev* __restrict__ sd,
                                                          const WorkItem* __restrict__ items) {
     const WorkItem w = items[blockIdx.x];
     const SysDev& d = sd[w.sys];
-    linkforce_body(d.box, d.rec, d.kext * d.kext * d.kext, d.part, d.cap, d.nseg, d.slist, d.scount, w.local);
+    linkforce_body(d.box, d.rec, d.kext * d.kext * d.kext, d.part, d.cap, w.local);
 }
 
 // ---------------------------------------------------------------- S7
@@ -656,30 +605,24 @@ int killfill_extent(int nx, int ny, int nz, double rb) {
     const int L = std::max(nx, std::max(ny, nz));
     return std::min(raster_extent(nx, ny, nz, rb) + 2, L);
 }
-int surf_nseg(const lb_handle* h) {
-    return surf_segments(raster_extent(h->box.nx, h->box.ny, h->box.nz, h->rmax));
-}
 int kill_ext(const lb_handle* h) { return killfill_extent(h->box.nx, h->box.ny, h->box.nz, h->rmax); }
 
 hipError_t launch_shell(lb_handle* h) {
     if (h->np <= 0) return hipSuccess;
-    const int nseg = surf_nseg(h);
     if (h->prm.precision == LB_FP64)
         hipLaunchKernelGGL(k_shell<double>, dim3(h->np), dim3(kPB), 0, h->stream, h->box, (double*)h->b.psi,
-                           (const double*)h->b.rho, h->b.owner[h->ocur], h->b.part, h->cap, nseg, h->b.slist,
-                           h->b.scount);
+                           (const double*)h->b.rho, h->b.owner[h->ocur], h->b.part, h->cap);
     else
         hipLaunchKernelGGL(k_shell<float>, dim3(h->np), dim3(kPB), 0, h->stream, h->box, (float*)h->b.psi,
-                           (const float*)h->b.rho, h->b.owner[h->ocur], h->b.part, h->cap, nseg, h->b.slist,
-                           h->b.scount);
+                           (const float*)h->b.rho, h->b.owner[h->ocur], h->b.part, h->cap);
     return hipGetLastError();
 }
 
 hipError_t launch_forces(lb_handle* h) {
     if (h->np <= 0) return hipSuccess;
-    const int nseg = surf_nseg(h), ke = kill_ext(h);
-    hipLaunchKernelGGL(k_linkforce, dim3(h->np), dim3(256), 0, h->stream, h->box, h->b.rec, ke * ke * ke, h->b.part,
-                       h->cap, nseg, h->b.slist, h->b.scount);
+    const int ke = kill_ext(h);
+    hipLaunchKernelGGL(k_linkforce, dim3(h->np), dim3(kPB), 0, h->stream, h->box, h->b.rec, ke * ke * ke, h->b.part,
+                       h->cap);
     return hipGetLastError();
 }
 hipError_t launch_bodies(lb_handle* h) {
@@ -737,7 +680,7 @@ hipError_t launch_batch_shell(const BatchLaunch& bl, int precision, hipStream_t 
 
 hipError_t launch_batch_forces(const BatchLaunch& bl, hipStream_t st) {
     if (bl.n[BI_PART] == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_linkforce_batch, dim3(bl.n[BI_PART]), dim3(256), 0, st, bl.sys, bl.items[BI_PART]);
+    hipLaunchKernelGGL(k_linkforce_batch, dim3(bl.n[BI_PART]), dim3(kPB), 0, st, bl.sys, bl.items[BI_PART]);
     return hipGetLastError();
 }
 

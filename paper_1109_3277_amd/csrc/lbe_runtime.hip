@@ -59,17 +59,14 @@ Layout layout_of(const lb_params* p) {
     L.part = align_up(NPFIELD * cap * sizeof(double));
     L.pfast = align_up(kPF * cap * sizeof(double));
     const double rmax = p->max_particles > 0 ? p->max_radius : 0.5;
-    const size_t nseg = (size_t)surf_segments(raster_extent(p->nx, p->ny, p->nz, rmax));
-    L.slist = p->max_particles > 0 ? align_up(cap * nseg * 64 * sizeof(uint2)) : 0;
-    L.scount = p->max_particles > 0 ? align_up(cap * nseg * sizeof(int)) : 0;
     const size_t kext = (size_t)killfill_extent(p->nx, p->ny, p->nz, rmax);
     L.rec = p->max_particles > 0 ? align_up(cap * kext * kext * kext * kRec * sizeof(double)) : 0;
     L.kpart = align_up(cap * 8 * sizeof(double));
     L.red = align_up((kRedBlocks + 1) * 8 * sizeof(double));
     L.counters = align_up(8 * sizeof(double));
     L.health = align_up(sizeof(int));
-    L.total = 2 * L.f + L.psi + L.rho + 2 * L.owner + 2 * L.bmask + L.part + L.pfast + L.slist + L.scount +
-              L.rec + L.kpart + L.red + L.counters + L.health;
+    L.total = 2 * L.f + L.psi + L.rho + 2 * L.owner + 2 * L.bmask + L.part + L.pfast + L.rec + L.kpart + L.red +
+              L.counters + L.health;
     return L;
 }
 
@@ -105,8 +102,6 @@ int setup_handle(lb_handle* h, const lb_params* prm, char* ws, size_t ws_bytes, 
     h->b.bmask[1] = (uint32_t*)p; p += L.bmask;
     h->b.part = (double*)p; p += L.part;
     h->b.pfast = (double*)p; p += L.pfast;
-    h->b.slist = L.slist ? (uint2*)p : nullptr; p += L.slist;
-    h->b.scount = L.scount ? (int*)p : nullptr; p += L.scount;
     h->b.rec = L.rec ? (double*)p : nullptr; p += L.rec;
     h->b.kpart = (double*)p; p += L.kpart;
     h->b.red = (double*)p; p += L.red;
@@ -122,6 +117,7 @@ int setup_handle(lb_handle* h, const lb_params* prm, char* ws, size_t ws_bytes, 
     chk(launch_fill_u32(h, h->b.bmask[1], 0u, b.N), "clear bounce masks");
     chk(launch_fill_f64(h, h->b.part, 0.0, (int64_t)NPFIELD * h->cap), "clear particles");
     chk(launch_fill_f64(h, h->b.kpart, 0.0, (int64_t)(L.kpart / sizeof(double))), "clear impulse slots");
+    if (L.rec) chk(launch_fill_f64(h, h->b.rec, 0.0, (int64_t)(L.rec / sizeof(double))), "clear link records");
     h->kpart_len = (int64_t)(L.kpart / sizeof(double));
     chk(launch_fill_f64(h, h->b.counters, 0.0, 8), "clear counters");
     chk(launch_fill_u32(h, (uint32_t*)h->b.health, 0u, 1), "clear health");
