@@ -167,7 +167,11 @@ __global__ __launch_bounds__(kPB) void k_shell_batch(const SysDev* __restrict__ 
 // block per particle walks the record box: cell c goes to thread c mod kPB,
 // each thread's cells in increasing order, then a fixed block sum, so the
 // result is reproducible bit for bit. Records read are cleared for the next
-// step.
+// step. A linked fluid node lies within sqrt(2) of a node of p. In
+// coordinates scaled by the semi-axes that is a step of at most
+// sqrt(2) / min(R_par, R_perp), so the node lies inside p's ellipsoid scaled
+// about its centre by 1 + 1.5 / min(R_par, R_perp): cells outside that are
+// never written and are not read.
 __device__ inline void linkforce_body(const Box& bx, double* __restrict__ rec, int rstride,
                                       double* __restrict__ part, int cap, int p) {
     const int Ls[3] = {bx.nx, bx.ny, bx.nz};
@@ -176,19 +180,31 @@ __device__ inline void linkforce_body(const Box& bx, double* __restrict__ rec, i
     const bool ok = particle_box(bx, part, cap, p, lo, sz);
     for (int d = 0; d < 3; d++) esz[d] = min(sz[d] + 2, Ls[d]);
     const int cells = ok ? esz[0] * esz[1] * esz[2] : 0;
+    double Rm[3][3];
+    qrot(part[QW * cap + p], part[QX * cap + p], part[QY * cap + p], part[QZ * cap + p], Rm);
+    const double rpar = part[RPAR * cap + p], rperp = part[RPERP * cap + p];
+    const double sc = 1.0 + 1.5 / (rpar < rperp ? rpar : rperp);
+    const double ga = sc * rperp, gc = sc * rpar;
     double* rp = rec + (size_t)p * rstride * kRec;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     constexpr int U = 4;  // cells per thread in flight
     for (int base = 0; base < cells; base += U * kPB) {
-        double F[U][3];
+        double F[U][3], r[U][3];
 #pragma unroll
         for (int k = 0; k < U; k++) {
             const int c = base + k * kPB + (int)threadIdx.x;
             F[k][0] = F[k][1] = F[k][2] = 0.0;
+            r[k][0] = r[k][1] = r[k][2] = 0.0;
             if (c < cells) {
-                F[k][0] = rp[(size_t)c * kRec];
-                F[k][1] = rp[(size_t)c * kRec + 1];
-                F[k][2] = rp[(size_t)c * kRec + 2];
+                const int ox = c % esz[0], oy = (c / esz[0]) % esz[1], oz = c / (esz[0] * esz[1]);
+                r[k][0] = minimg((double)wrapc_any(lo[0] - 1 + ox, Ls[0]) - X[0], Ls[0]);
+                r[k][1] = minimg((double)wrapc_any(lo[1] - 1 + oy, Ls[1]) - X[1], Ls[1]);
+                r[k][2] = minimg((double)wrapc_any(lo[2] - 1 + oz, Ls[2]) - X[2], Ls[2]);
+                if (inside_test(Rm, r[k][0], r[k][1], r[k][2], gc, ga)) {
+                    F[k][0] = rp[(size_t)c * kRec];
+                    F[k][1] = rp[(size_t)c * kRec + 1];
+                    F[k][2] = rp[(size_t)c * kRec + 2];
+                }
             }
         }
 #pragma unroll
@@ -198,10 +214,7 @@ __device__ inline void linkforce_body(const Box& bx, double* __restrict__ rec, i
             rp[(size_t)c * kRec] = 0.0;
             rp[(size_t)c * kRec + 1] = 0.0;
             rp[(size_t)c * kRec + 2] = 0.0;
-            const int ox = c % esz[0], oy = (c / esz[0]) % esz[1], oz = c / (esz[0] * esz[1]);
-            const double rx = minimg((double)wrapc_any(lo[0] - 1 + ox, Ls[0]) - X[0], Ls[0]);
-            const double ry = minimg((double)wrapc_any(lo[1] - 1 + oy, Ls[1]) - X[1], Ls[1]);
-            const double rz = minimg((double)wrapc_any(lo[2] - 1 + oz, Ls[2]) - X[2], Ls[2]);
+            const double rx = r[k][0], ry = r[k][1], rz = r[k][2];
             acc[0] += F[k][0];
             acc[1] += F[k][1];
             acc[2] += F[k][2];

@@ -1,0 +1,58 @@
+"""The force pass reads a particle's record cells only inside its ellipsoid
+scaled about its centre by 1 + 1.5 / min(R_par, R_perp). Every fluid node
+linked to the particle (a node n with n + c_i inside the ellipsoid, |c_i| <=
+sqrt 2) must lie inside that region, or its record would be skipped. Checked
+here on random ellipsoids, including thin disks and long needles."""
+import numpy as np
+
+LINKS = [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1) if 0 < abs(a) + abs(b) + abs(c) <= 2]
+
+
+def _rot(q):
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def _form(p, X, R, ra, rc):
+    b = (p - X) @ R  # body frame: b = R^T (p - X)
+    return (b[:, 0] ** 2 + b[:, 1] ** 2) / ra ** 2 + b[:, 2] ** 2 / rc ** 2
+
+
+def test_linked_nodes_lie_in_scaled_ellipsoid():
+    rng = np.random.default_rng(7)
+    checked = 0
+    for _ in range(120):
+        rpar, rperp = rng.uniform(0.5, 9.0), rng.uniform(0.5, 9.0)
+        if rng.random() < 0.3:  # extreme aspect ratios
+            rperp = rpar * rng.choice([0.08, 12.0])
+            rperp = min(rperp, 9.0)
+        q = rng.normal(size=4)
+        R = _rot(q / np.linalg.norm(q))
+        X = rng.uniform(0.0, 1.0, 3)
+        L = int(2 * max(rpar, rperp)) + 4
+        g = np.stack(np.meshgrid(*[np.arange(-L, L + 1)] * 3, indexing="ij"), -1).reshape(-1, 3).astype(float)
+        inside = g[_form(g, X, R, rperp, rpar) <= 1.0]
+        s = 1.0 + 1.5 / min(rpar, rperp)
+        for c in LINKS:
+            n = inside - np.array(c, dtype=float)
+            assert (_form(n, X, R, s * rperp, s * rpar) <= 1.0).all()
+            checked += len(n)
+    assert checked > 100000
+
+
+def test_growing_each_axis_is_not_enough():
+    """The plain alternative (every semi-axis grown by the link length) misses
+    links near the tip of an elongated body, which is why the scaled form is
+    used."""
+    R = np.eye(3)
+    X = np.zeros(3)
+    rpar, rperp = 10.0, 0.6
+    g = np.stack(np.meshgrid(*[np.arange(-14, 15)] * 3, indexing="ij"), -1).reshape(-1, 3).astype(float)
+    inside = g[_form(g, X, R, rperp, rpar) <= 1.0]
+    missed = 0
+    for c in LINKS:
+        n = inside - np.array(c, dtype=float)
+        missed += int((_form(n, X, R, rperp + 1.5, rpar + 1.5) > 1.0).sum())
+    assert missed > 0
