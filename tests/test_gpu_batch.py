@@ -159,3 +159,60 @@ def test_batch_mixed_kinds_equals_lone_handles():
         for k in range(3):
             assert _same(bt[k], lone[k]), f"system {k} differs"
             assert np.array_equal(bt[k].stats(), lone[k].stats())
+
+
+def test_batch_with_walled_systems_equals_lone_handles():
+    """Systems with wall nodes (one moving-wall channel, one resting-wall
+    channel with a particle) batched with a plain ensemble system: the batched
+    wall shell and the wall-keeping owner clear match lone handles bit for
+    bit."""
+    from paper_1109_3277_amd.binding import Lattice
+
+    base = _small_ensemble(1)[0]
+
+    def walls(dims):
+        nx, ny, nz = dims
+        z = np.repeat(np.arange(nz), nx * ny)
+        return (z == 0) | (z == nz - 1)
+
+    d1, d2 = (16, 8, 14), (24, 20, 24)
+    ra1, rb1 = W.layered_fields(d1, 51)
+    ra2, rb2 = W.uniform_fields(d2, 52, 0.7, 0.7, 0.01)
+    part = (np.array([[6.0, 3.0]]), np.array([[11.3, 9.6, 8.2]]), np.array([[0.9, 0.2, 0.3, 0.1]]),
+            np.array([0.1]), np.array([1.0]))
+    specs = [
+        dict(dims=d1, ra=ra1, rb=rb1, wall_u=[0.01, 0.0, 0.0], parts=None, accel=None),
+        dict(dims=d2, ra=ra2, rb=rb2, wall_u=None, parts=part, accel=[2e-5, 1e-5, 0.0]),
+    ]
+    log(f"case batch with walls: {[s['dims'] for s in specs]} + {base.dims}")
+    from paper_1109_3277_amd.binding import Batch
+
+    plist = [{"dims": s["dims"], "tau": 1.0, "g_br": 0.08, "psi_kind": 1,
+              "max_particles": 0 if s["parts"] is None else 1, "max_radius": 6.0} for s in specs]
+    plist.append({"dims": base.dims, "tau": base.tau, "g_br": base.g_br, "psi_kind": base.psi_kind,
+                  "max_particles": base.n_particles, "max_radius": base.max_radius})
+    b = Batch(plist, "fp64")
+    lone = []
+    for k, s in enumerate(specs):
+        g = Lattice(s["dims"], 1.0, 0.08, 1, "fp64", max_particles=plist[k]["max_particles"], max_radius=6.0)
+        for h in (b[k], g):
+            h.set_static_solid(walls(s["dims"]), s["wall_u"])
+            h.init_fields(s["ra"], s["rb"])
+            if s["accel"] is not None:
+                h.set_body_accel(s["accel"])
+            if s["parts"] is not None:
+                h.add_ellipsoids(*s["parts"])
+        lone.append(g)
+    b[2].init_fields(base.rho_a, base.rho_b)
+    b[2].add_ellipsoids(base.radii, base.pos, base.quat, base.delta_rho, base.density)
+    g = Lattice(base.dims, base.tau, base.g_br, base.psi_kind, "fp64", max_particles=base.n_particles,
+                max_radius=base.max_radius)
+    g.init_fields(base.rho_a, base.rho_b)
+    g.add_ellipsoids(base.radii, base.pos, base.quat, base.delta_rho, base.density)
+    lone.append(g)
+    b.step(7)
+    for g in lone:
+        g.step(7)
+    for k, g in enumerate(lone):
+        assert _same(b[k], g), f"system {k} differs"
+    assert np.abs(lone[1].read_particles()["pos"] - part[1]).max() > 0
