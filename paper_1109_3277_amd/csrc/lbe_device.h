@@ -238,6 +238,45 @@ __device__ inline void box_node(int t, const int sz[3], int& ix, int& iy, int& i
     iz = r / sz[1];
 }
 
+// Walk over a box of nodes (sz nodes from node lo, x fastest, periodic):
+// box index t = t0, t0 + step, ... without a division per node. The step is
+// split once into mixed-radix digits and added with carries; coordinates wrap
+// with one compare (the origin is wrapped once).
+struct BoxWalk {
+    int s0, s1, a0, a1, a2;  // box extents along x and y, digits of the step
+    int ix, iy, iz;          // offsets of the current node in the box
+    int b[3], L[3];          // wrapped origin, lattice extents
+    __device__ BoxWalk(const int lo[3], const int sz[3], const int Ls[3], int t0, int step) {
+        s0 = max(sz[0], 1);
+        s1 = max(sz[1], 1);
+        a0 = step % s0;
+        const int q = step / s0;
+        a1 = q % s1;
+        a2 = q / s1;
+        ix = t0 % s0;
+        const int r = t0 / s0;
+        iy = r % s1;
+        iz = r / s1;
+        for (int d = 0; d < 3; d++) {
+            b[d] = wrapc_any(lo[d], Ls[d]);
+            L[d] = Ls[d];
+        }
+    }
+    __device__ void next() {
+        ix += a0;
+        int c = ix >= s0 ? 1 : 0;
+        ix -= c * s0;
+        iy += a1 + c;
+        c = iy >= s1 ? 1 : 0;
+        iy -= c * s1;
+        iz += a2 + c;
+    }
+    // coordinates of the current node (offsets below the lattice extents)
+    __device__ int x() const { return b[0] + ix >= L[0] ? b[0] + ix - L[0] : b[0] + ix; }
+    __device__ int y() const { return b[1] + iy >= L[1] ? b[1] + iy - L[1] : b[1] + iy; }
+    __device__ int z() const { return b[2] + iz >= L[2] ? b[2] + iz - L[2] : b[2] + iz; }
+};
+
 // One system as the batched kernels see it: its box, its buffers (both
 // population and owner copies; the launch names the current ones), its
 // particle table and its launch geometry.

@@ -67,10 +67,10 @@ __device__ inline void raster_body(const Box& bx, const double* __restrict__ par
     qrot(part[QW * cap + p], part[QX * cap + p], part[QY * cap + p], part[QZ * cap + p], R);
     const double rpar = part[RPAR * cap + p], rperp = part[RPERP * cap + p];
     const int total = sz[0] * sz[1] * sz[2];
-    for (int t = threadIdx.x; t < total; t += blockDim.x) {
-        int ix, iy, iz;
-        box_node(t, sz, ix, iy, iz);
-        const int x = wrapc_any(lo[0] + ix, bx.nx), y = wrapc_any(lo[1] + iy, bx.ny), z = wrapc_any(lo[2] + iz, bx.nz);
+    const int Ls[3] = {bx.nx, bx.ny, bx.nz};
+    BoxWalk w(lo, sz, Ls, threadIdx.x, kPB);
+    for (int t = threadIdx.x; t < total; t += kPB, w.next()) {
+        const int x = w.x(), y = w.y(), z = w.z();
         const double dx = minimg((double)x - X[0], bx.nx);
         const double dy = minimg((double)y - X[1], bx.ny);
         const double dz = minimg((double)z - X[2], bx.nz);
@@ -104,15 +104,15 @@ __device__ inline void shell_body(const Box& bx, R* __restrict__ psi, const R* _
                                   int p) {
     const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
     const int64_t N = bx.N;
-    int lo[3], sz[3];
+    int lo[3] = {0, 0, 0}, sz[3] = {0, 0, 0};
     const int total = particle_box(bx, part, cap, p, lo, sz) ? sz[0] * sz[1] * sz[2] : 0;
     // densities of fluid nodes: the stored rho (Psi itself when Psi = rho)
     const R* dens = bx.psi_kind == 0 ? psi : rho;
     const double dr = part[DRHO * cap + p];
-    for (int t = threadIdx.x; t < total; t += kPB) {
-        int ix, iy, iz;
-        box_node(t, sz, ix, iy, iz);
-        const int x = wrapc_any(lo[0] + ix, nx), y = wrapc_any(lo[1] + iy, ny), z = wrapc_any(lo[2] + iz, nz);
+    const int Ls[3] = {nx, ny, nz};
+    BoxWalk w(lo, sz, Ls, threadIdx.x, kPB);
+    for (int t = threadIdx.x; t < total; t += kPB, w.next()) {
+        const int x = w.x(), y = w.y(), z = w.z();
         const int64_t n = node_index(bx, x, y, z);
         if (owner[n] != (uint32_t)p) continue;
         uint32_t on[Q];
@@ -176,7 +176,7 @@ __device__ inline void linkforce_body(const Box& bx, double* __restrict__ rec, i
                                       double* __restrict__ part, int cap, int p) {
     const int Ls[3] = {bx.nx, bx.ny, bx.nz};
     const double X[3] = {part[PX * cap + p], part[PY * cap + p], part[PZ * cap + p]};
-    int lo[3], sz[3], esz[3];
+    int lo[3] = {0, 0, 0}, sz[3] = {0, 0, 0}, esz[3];
     const bool ok = particle_box(bx, part, cap, p, lo, sz);
     for (int d = 0; d < 3; d++) esz[d] = min(sz[d] + 2, Ls[d]);
     const int cells = ok ? esz[0] * esz[1] * esz[2] : 0;
@@ -188,18 +188,19 @@ __device__ inline void linkforce_body(const Box& bx, double* __restrict__ rec, i
     double* rp = rec + (size_t)p * rstride * kRec;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     constexpr int U = 4;  // cells per thread in flight
+    const int elo[3] = {lo[0] - 1, lo[1] - 1, lo[2] - 1};
+    BoxWalk w(elo, esz, Ls, threadIdx.x, kPB);
     for (int base = 0; base < cells; base += U * kPB) {
         double F[U][3], r[U][3];
 #pragma unroll
-        for (int k = 0; k < U; k++) {
+        for (int k = 0; k < U; k++, w.next()) {
             const int c = base + k * kPB + (int)threadIdx.x;
             F[k][0] = F[k][1] = F[k][2] = 0.0;
             r[k][0] = r[k][1] = r[k][2] = 0.0;
             if (c < cells) {
-                const int ox = c % esz[0], oy = (c / esz[0]) % esz[1], oz = c / (esz[0] * esz[1]);
-                r[k][0] = minimg((double)wrapc_any(lo[0] - 1 + ox, Ls[0]) - X[0], Ls[0]);
-                r[k][1] = minimg((double)wrapc_any(lo[1] - 1 + oy, Ls[1]) - X[1], Ls[1]);
-                r[k][2] = minimg((double)wrapc_any(lo[2] - 1 + oz, Ls[2]) - X[2], Ls[2]);
+                r[k][0] = minimg((double)w.x() - X[0], Ls[0]);
+                r[k][1] = minimg((double)w.y() - X[1], Ls[1]);
+                r[k][2] = minimg((double)w.z() - X[2], Ls[2]);
                 if (inside_test(Rm, r[k][0], r[k][1], r[k][2], gc, ga)) {
                     F[k][0] = rp[(size_t)c * kRec];
                     F[k][1] = rp[(size_t)c * kRec + 1];
