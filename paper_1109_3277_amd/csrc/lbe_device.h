@@ -199,6 +199,7 @@ __device__ inline void pack_fast(const double* part, int cap, int p, double* __r
 // block (or, for the row kernel, BY whole x-rows of BX = nx nodes).
 struct Tiles {
     int BX, BY, tiles_x, tiles_y;
+    bool zrun = false;  // tile kernel: walk z before y (see fused_body)
 };
 
 // Per-particle kernels run one block of kPB threads per particle, looping

@@ -14,8 +14,8 @@
 namespace lbe {
 
 // Workgroups are dispatched round-robin over the 8 XCDs. Remap the block index
-// so each XCD walks a contiguous range of tiles (whole z-slabs): the rows a
-// tile reads from its y / z neighbours then sit in the same L2.
+// so each XCD walks a contiguous range of tiles: the rows a tile reads from
+// its neighbours then sit in the same L2.
 __device__ inline int xcd_remap(int b, int nb) {
     if ((nb & 7) != 0) return b;
     int per = nb >> 3;
@@ -220,7 +220,8 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
                                   const typename P::R* __restrict__ psi, const uint32_t* __restrict__ owner,
                                   const uint32_t* __restrict__ bm_in, uint32_t* __restrict__ bm_out,
                                   const double* __restrict__ pfast,
-                                  double* __restrict__ rec, int rstride, int tiles_x, int tiles_y, int tile) {
+                                  double* __restrict__ rec, int rstride, int tiles_x, int tiles_y, int tile,
+                                  bool zrun) {
     using R = typename P::R;
     using S = typename P::S;
     static_assert(BX * BY == 256, "one node per thread");
@@ -230,11 +231,22 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
 
     const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
     const uint32_t N = (uint32_t)bx.N;
-    const int txy = tiles_x * tiles_y;
-    const int z = tile / txy;
-    const int rem = tile - z * txy;
-    const int ty = rem / tiles_x;
-    const int tx = rem - ty * tiles_x;
+    // tile order: x fastest, then y, then z; or, with zrun, x, then z, then y,
+    // so a tile's z-neighbours are a few tiles away in dispatch order and
+    // their rows (halo Psi and owners, redirected loads) are still in L2
+    int tx, ty, z;
+    if (zrun) {
+        const int tq = tile / tiles_x;
+        tx = tile - tq * tiles_x;
+        ty = tq / nz;
+        z = tq - ty * nz;
+    } else {
+        const int txy = tiles_x * tiles_y;
+        z = tile / txy;
+        const int rem = tile - z * txy;
+        ty = rem / tiles_x;
+        tx = rem - ty * tiles_x;
+    }
     const int lx = threadIdx.x % BX, ly = threadIdx.x / BX;
     const int x0 = tx * BX, y0 = ty * BY;
     const int x = x0 + lx, y = y0 + ly;
@@ -465,9 +477,9 @@ template <class P, bool SOLID, int BX, int BY>
 __global__ __launch_bounds__(256, sizeof(typename P::R) == 8 ? 2 : 3) void k_fused(
     Box bx, const typename P::S* __restrict__ fs, typename P::S* __restrict__ fd, const typename P::R* __restrict__ psi,
     const uint32_t* __restrict__ owner, const uint32_t* __restrict__ bm_in, uint32_t* __restrict__ bm_out,
-    const double* __restrict__ pfast, double* __restrict__ rec, int rstride, int tiles_x, int tiles_y) {
+    const double* __restrict__ pfast, double* __restrict__ rec, int rstride, int tiles_x, int tiles_y, int zrun) {
     fused_body<P, SOLID, BX, BY>(bx, fs, fd, psi, owner, bm_in, bm_out, pfast, rec, rstride, tiles_x, tiles_y,
-                                 xcd_remap(blockIdx.x, gridDim.x));
+                                 xcd_remap(blockIdx.x, gridDim.x), zrun != 0);
 }
 // Batched: item = (system, tile); SOLID for the systems with particles.
 // Items of one system are contiguous, so the XCD remap keeps neighbouring
@@ -479,7 +491,7 @@ __global__ __launch_bounds__(256, sizeof(typename P::R) == 8 ? 2 : 3) void k_fus
     const SysDev& d = sd[w.sys];
     fused_body<P, SOLID, BX, BY>(d.box, (const typename P::S*)d.f[c], (typename P::S*)d.f[1 - c],
                                  (const typename P::R*)d.psi, d.owner[o], d.bmask[c], d.bmask[1 - c], d.pfast, d.rec,
-                                 d.kext * d.kext * d.kext, d.tiles_x, d.tiles_y, w.local);
+                                 d.kext * d.kext * d.kext, d.tiles_x, d.tiles_y, w.local, false);
 }
 
 // Row kernel for boxes without solids (nx a multiple of 64): a block holds
@@ -922,6 +934,12 @@ Tiles fused_tiles(int nx, int ny, bool solids, int precision) {
     t.BY = 256 / t.BX;
     t.tiles_x = (nx + t.BX - 1) / t.BX;
     t.tiles_y = (ny + t.BY - 1) / t.BY;
+    // z-runs pay for 8- and 4-byte populations on planes of many tiles
+    // (256^3 bijel: fused kernel -9 % FP64, -4 % FP32). On a plane of few
+    // tiles (128^3: 64) the z-neighbours are in flight together anyway and
+    // z-runs only move the y-neighbours away (FP64 +40 %); 2-byte planes are
+    // small enough that the plane-by-plane order finds them in L2.
+    t.zrun = (precision == LB_FP64 || precision == LB_FP32) && t.tiles_x * t.tiles_y >= 256;
     return t;
 }
 
@@ -955,11 +973,11 @@ static void launch_fused_t(lb_handle* h, const Tiles& tl, unsigned grid) {
     if (tl.BX == 64)
         hipLaunchKernelGGL((k_fused<P, SOLID, 64, 4>), dim3(grid), dim3(256), 0, h->stream, h->box, fs, fd, ps, ow,
                            h->b.bmask[h->cur], h->b.bmask[1 - h->cur], h->b.pfast, h->b.rec, rstride, tl.tiles_x,
-                           tl.tiles_y);
+                           tl.tiles_y, tl.zrun ? 1 : 0);
     else
         hipLaunchKernelGGL((k_fused<P, SOLID, 32, 8>), dim3(grid), dim3(256), 0, h->stream, h->box, fs, fd, ps, ow,
                            h->b.bmask[h->cur], h->b.bmask[1 - h->cur], h->b.pfast, h->b.rec, rstride, tl.tiles_x,
-                           tl.tiles_y);
+                           tl.tiles_y, tl.zrun ? 1 : 0);
 }
 
 hipError_t launch_fused(lb_handle* h) {

@@ -42,6 +42,22 @@ def test_fluid_ragged_tiles_fp64():
     _check_fp64(res)
 
 
+def test_tile_z_runs_ragged_fp64():
+    """Planes of 2 x 129 tiles, ragged in x and y: enough tiles per plane that
+    the fused kernel takes them in z-runs (x, then z, then y), with particles."""
+    s = W.bijel_system(dims=(70, 516, 12), seed=21, phi=0.1, rpar=4.5, rperp=2.5)
+    assert s.n_particles > 100
+    _, _, res = _run(s, 30)
+    _check_fp64(res)
+
+
+def test_tile_z_runs_fp32():
+    s = W.bijel_system(dims=(70, 516, 12), seed=22, phi=0.1, rpar=4.5, rperp=2.5)
+    _, _, res = _run(s, 30, "fp32")
+    log(f"  fp32 {res}")
+    assert res["owner_equal"] and res["e_rho"] <= 1e-5, res
+
+
 def test_zero_steps_and_minimum_box():
     s = W.spinodal_system(dims=(3, 3, 3), seed=12)
     o, g, res = _run(s, 0)
