@@ -97,7 +97,13 @@ __global__ __launch_bounds__(kPB) void k_raster_batch(const SysDev* __restrict__
 // takes their mean density; the particle colour is added to A if positive,
 // its magnitude to B if negative. Densities are recovered from the stored
 // Psi and the result is stored as Psi.
-// One block loops over p's box; only nodes of p change.
+// One block per particle; only nodes of p change. The block takes p's box in
+// segments of kShellSeg nodes: it loads the owner codes of a whole segment
+// (kShellPT per thread, all in flight), lists p's nodes in LDS, then gives
+// each listed node to one thread for its 18 neighbour gathers. A node's
+// result depends on its neighbours only, so the list order does not matter.
+constexpr int kShellPT = 20;
+constexpr int kShellSeg = kShellPT * kPB;
 template <class R>
 __device__ inline void shell_body(const Box& bx, R* __restrict__ psi, const R* __restrict__ rho,
                                   const uint32_t* __restrict__ owner, const double* __restrict__ part, int cap,
@@ -110,39 +116,60 @@ __device__ inline void shell_body(const Box& bx, R* __restrict__ psi, const R* _
     const R* dens = bx.psi_kind == 0 ? psi : rho;
     const double dr = part[DRHO * cap + p];
     const int Ls[3] = {nx, ny, nz};
-    BoxWalk w(lo, sz, Ls, threadIdx.x, kPB);
-    for (int t = threadIdx.x; t < total; t += kPB, w.next()) {
-        const int x = w.x(), y = w.y(), z = w.z();
-        const int64_t n = node_index(bx, x, y, z);
-        if (owner[n] != (uint32_t)p) continue;
-        uint32_t on[Q];
-        R d0[Q], d1[Q];
+    __shared__ uint32_t s_list[kShellSeg];
+    __shared__ int s_cnt;
+    for (int base = 0; base < total; base += kShellSeg) {
+        if (threadIdx.x == 0) s_cnt = 0;
+        __syncthreads();
+        {
+            BoxWalk w(lo, sz, Ls, base + (int)threadIdx.x, kPB);
+            uint32_t ow[kShellPT];
 #pragma unroll
-        for (int i = 1; i < Q; i++) {
-            const int64_t m = node_index(bx, wrapc(x + cx(i), nx), wrapc(y + cy(i), ny), wrapc(z + cz(i), nz));
-            on[i] = owner[m];
-            d0[i] = dens[m];
-            d1[i] = dens[N + m];
-        }
-        R s0 = R(0), s1 = R(0);
-        int k = 0;
+            for (int k = 0; k < kShellPT; k++) {
+                ow[k] = OWN_FLUID;
+                if (base + (int)threadIdx.x + k * kPB < total) ow[k] = owner[node_index(bx, w.x(), w.y(), w.z())];
+                w.next();
+            }
 #pragma unroll
-        for (int i = 1; i < Q; i++) {
-            if (on[i] != OWN_FLUID) continue;
-            s0 += d0[i];
-            s1 += d1[i];
-            k++;
+            for (int k = 0; k < kShellPT; k++)
+                if (ow[k] == (uint32_t)p) s_list[atomicAdd(&s_cnt, 1)] = (uint32_t)(base + (int)threadIdx.x + k * kPB);
         }
-        if (k == 0) {
-            psi[n] = R(0);
-            psi[N + n] = R(0);
-        } else {
-            R a = s0 / R(k), b = s1 / R(k);
-            if (dr > 0.0) a += R(dr);
-            else if (dr < 0.0) b += R(-dr);
-            psi[n] = psi_of(a, bx.psi_kind);
-            psi[N + n] = psi_of(b, bx.psi_kind);
+        __syncthreads();
+        const int listed = s_cnt;
+        for (int j = threadIdx.x; j < listed; j += kPB) {
+            const BoxWalk w(lo, sz, Ls, (int)s_list[j], 1);
+            const int x = w.x(), y = w.y(), z = w.z();
+            const int64_t n = node_index(bx, x, y, z);
+            uint32_t on[Q];
+            R d0[Q], d1[Q];
+#pragma unroll
+            for (int i = 1; i < Q; i++) {
+                const int64_t m = node_index(bx, wrapc(x + cx(i), nx), wrapc(y + cy(i), ny), wrapc(z + cz(i), nz));
+                on[i] = owner[m];
+                d0[i] = dens[m];
+                d1[i] = dens[N + m];
+            }
+            R s0 = R(0), s1 = R(0);
+            int k = 0;
+#pragma unroll
+            for (int i = 1; i < Q; i++) {
+                if (on[i] != OWN_FLUID) continue;
+                s0 += d0[i];
+                s1 += d1[i];
+                k++;
+            }
+            if (k == 0) {
+                psi[n] = R(0);
+                psi[N + n] = R(0);
+            } else {
+                R a = s0 / R(k), b = s1 / R(k);
+                if (dr > 0.0) a += R(dr);
+                else if (dr < 0.0) b += R(-dr);
+                psi[n] = psi_of(a, bx.psi_kind);
+                psi[N + n] = psi_of(b, bx.psi_kind);
+            }
         }
+        __syncthreads();  // the list is read before the next segment resets it
     }
 }
 template <class R>
