@@ -63,21 +63,25 @@ __device__ inline void density_body(const Box& bx, const typename P::S* __restri
     const uint32_t N = (uint32_t)bx.N;
     const uint32_t n = (uint32_t)blk * 256u + threadIdx.x;
     if (n >= N) return;
-    if (SOLID && owner[n] != OWN_FLUID) return;
-    if (owner_old && owner_old[n] != OWN_FLUID) return;
+    // densities of fluid nodes (not just filled); the other lanes store zero
+    // so that every line of Psi is written whole (the shell and fill passes
+    // write those nodes before anything reads them)
+    const bool live = (!SOLID || owner[n] == OWN_FLUID) && (!owner_old || owner_old[n] == OWN_FLUID);
     const R ref0 = R(bx.rref[0]), ref1 = R(bx.rref[1]);
     R r0 = R(0), r1 = R(0);
-    const uint32_t bm = SOLID ? bmask[n] : 0u;
+    const uint32_t bm = (SOLID && live) ? bmask[n] : 0u;
     if (!SOLID || __ballot(bm != 0u) == 0ull) {
         // no lane of the wave reads a bounced population: plane bases are
         // wave-uniform, offsets 32-bit
         const uint32_t nb = n * (uint32_t)sizeof(typename P::S);
+        if (live) {
 #pragma unroll
-        for (int i = 0; i < Q; i++) {
-            r0 += P::ld(at(f + (size_t)i * N, nb), R(wq(i)) * ref0);
-            r1 += P::ld(at(f + (size_t)(Q + i) * N, nb), R(wq(i)) * ref1);
+            for (int i = 0; i < Q; i++) {
+                r0 += P::ld(at(f + (size_t)i * N, nb), R(wq(i)) * ref0);
+                r1 += P::ld(at(f + (size_t)(Q + i) * N, nb), R(wq(i)) * ref1);
+            }
         }
-    } else {
+    } else if (live) {
         // population i from its own slot, or from plane ibar at n - c_i when
         // bit i of the bounce mask is set
         uint32_t up[Q];
@@ -116,13 +120,13 @@ __device__ inline void density_body(const Box& bx, const typename P::S* __restri
             r1 += v1[i];
         }
     }
-    psi[n] = psi_of(r0, bx.psi_kind);
-    psi[N + n] = psi_of(r1, bx.psi_kind);
+    psi[n] = live ? psi_of(r0, bx.psi_kind) : R(0);
+    psi[N + n] = live ? psi_of(r1, bx.psi_kind) : R(0);
     if (rho) {  // densities themselves, for the shell fill (exponential Psi only)
         rho[n] = r0;
         rho[N + n] = r1;
     }
-    if (!(r0 >= R(0)) || !(r1 >= R(0))) atomicOr(health, 1);
+    if (live && (!(r0 >= R(0)) || !(r1 >= R(0)))) atomicOr(health, 1);
 }
 template <class P, bool SOLID>
 __global__ __launch_bounds__(256) void k_density(Box bx, const typename P::S* __restrict__ f,
