@@ -51,6 +51,17 @@ __device__ inline bool inside_test(const double R[3][3], double dx, double dy, d
     return q <= 1.0;
 }
 
+// The same quadratic form with the reciprocal squared semi-axes ia2 =
+// 1 / R_perp^2 and ic2 = 1 / R_par^2 (no divisions). It differs from the one
+// inside_test compares with 1 by a few ulp.
+__device__ inline double q_fast(const double R[3][3], double dx, double dy, double dz, double ia2, double ic2) {
+#pragma clang fp contract(off)
+    const double bx = R[0][0] * dx + R[1][0] * dy + R[2][0] * dz;
+    const double by = R[0][1] * dx + R[1][1] * dy + R[2][1] * dz;
+    const double bz = R[0][2] * dx + R[1][2] * dy + R[2][2] * dz;
+    return (bx * bx + by * by) * ia2 + (bz * bz) * ic2;
+}
+
 __device__ inline int64_t node_index(const Box& bx, int x, int y, int z) {
     return x + (int64_t)bx.nx * (y + (int64_t)bx.ny * z);
 }
@@ -66,6 +77,7 @@ __device__ inline void raster_body(const Box& bx, const double* __restrict__ par
     double R[3][3];
     qrot(part[QW * cap + p], part[QX * cap + p], part[QY * cap + p], part[QZ * cap + p], R);
     const double rpar = part[RPAR * cap + p], rperp = part[RPERP * cap + p];
+    const double ia2 = 1.0 / (rperp * rperp), ic2 = 1.0 / (rpar * rpar);
     const int total = sz[0] * sz[1] * sz[2];
     const int Ls[3] = {bx.nx, bx.ny, bx.nz};
     BoxWalk w(lo, sz, Ls, threadIdx.x, kPB);
@@ -74,7 +86,12 @@ __device__ inline void raster_body(const Box& bx, const double* __restrict__ par
         const double dx = minimg((double)x - X[0], bx.nx);
         const double dy = minimg((double)y - X[1], bx.ny);
         const double dz = minimg((double)z - X[2], bx.nz);
-        if (!inside_test(R, dx, dy, dz, rpar, rperp)) continue;
+        // the division-free form decides unless it lies within 1e-9 of the
+        // surface, where the exact test (the one the owner map is defined by)
+        // does; the two differ by a few ulp
+        const double q = q_fast(R, dx, dy, dz, ia2, ic2);
+        if (q > 1.0 + 1e-9) continue;
+        if (q >= 1.0 - 1e-9 && !inside_test(R, dx, dy, dz, rpar, rperp)) continue;
         const int64_t n = node_index(bx, x, y, z);
         if (owner[n] == OWN_WALL) continue;
         atomicMin(owner + n, (uint32_t)p);
@@ -212,6 +229,9 @@ __device__ inline void linkforce_body(const Box& bx, double* __restrict__ rec, i
     const double rpar = part[RPAR * cap + p], rperp = part[RPERP * cap + p];
     const double sc = 1.0 + 1.5 / (rpar < rperp ? rpar : rperp);
     const double ga = sc * rperp, gc = sc * rpar;
+    // a filter only: linked nodes lie strictly inside the scaled ellipsoid,
+    // by far more than rounding, so the division-free form serves
+    const double ia2 = 1.0 / (ga * ga), ic2 = 1.0 / (gc * gc);
     double* rp = rec + (size_t)p * rstride * kRec;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     constexpr int U = 4;  // cells per thread in flight
@@ -228,7 +248,7 @@ __device__ inline void linkforce_body(const Box& bx, double* __restrict__ rec, i
                 r[k][0] = minimg((double)w.x() - X[0], Ls[0]);
                 r[k][1] = minimg((double)w.y() - X[1], Ls[1]);
                 r[k][2] = minimg((double)w.z() - X[2], Ls[2]);
-                if (inside_test(Rm, r[k][0], r[k][1], r[k][2], gc, ga)) {
+                if (q_fast(Rm, r[k][0], r[k][1], r[k][2], ia2, ic2) <= 1.0) {
                     F[k][0] = rp[(size_t)c * kRec];
                     F[k][1] = rp[(size_t)c * kRec + 1];
                     F[k][2] = rp[(size_t)c * kRec + 2];
@@ -572,7 +592,7 @@ __device__ inline void killfill_body(const Box& bx, typename P::S* __restrict__ 
         if (sz[d] > kext && threadIdx.x == 0) atomicOr(health, 2);
     }
     const int total = ok ? sz[0] * sz[1] * sz[2] : 0;
-    constexpr int U = 4;
+    constexpr int U = 8;  // nodes per thread with owner loads in flight (4: +6 %, 12: +3 % time)
     for (int base = 0; base < total; base += U * kPB) {
         uint32_t oo[U], on[U];  // every owner load of this thread issued before any is used
 #pragma unroll
