@@ -164,11 +164,31 @@ __global__ __launch_bounds__(256) void k_density_batch(const SysDev* __restrict_
 // written into node n's record of that particle; k_linkforce sums the
 // records (force, and torque r_n x force).
 
+// Neighbour sums S^c = sum_i Psi^c(n + c_i) c_i over the 18 links, in link
+// order; ps0(i) / ps1(i) give Psi^A / Psi^B of neighbour i. Formed straight
+// from the staged tile so that the 36 neighbour values are never all live.
+template <class R, class F0, class F1>
+__device__ inline void psi_sums(F0 ps0, F1 ps1, R (&s0)[3], R (&s1)[3]) {
+    R s0x = R(0), s0y = R(0), s0z = R(0), s1x = R(0), s1y = R(0), s1z = R(0);
+#pragma unroll
+    for (int i = 1; i < Q; i++) {
+        const R p0 = ps0(i), p1 = ps1(i);
+        if (cx(i) > 0) { s0x += p0; s1x += p1; }
+        if (cx(i) < 0) { s0x -= p0; s1x -= p1; }
+        if (cy(i) > 0) { s0y += p0; s1y += p1; }
+        if (cy(i) < 0) { s0y -= p0; s1y -= p1; }
+        if (cz(i) > 0) { s0z += p0; s1z += p1; }
+        if (cz(i) < 0) { s0z -= p0; s1z -= p1; }
+    }
+    s0[0] = s0x; s0[1] = s0y; s0[2] = s0z;
+    s1[0] = s1x; s1[1] = s1y; s1[2] = s1z;
+}
+
 // Moments, Shan-Chen velocity shift and BGK relaxation of one node, in place
-// on f0 / f1 (component A / B). q0[i], q1[i]: Psi^A, Psi^B of neighbour i.
+// on f0 / f1 (component A / B). S0, S1: the neighbour sums of Psi^A, Psi^B.
 template <class P>
 __device__ inline void collide_node(const Box& bx, typename P::R (&f0)[Q], typename P::R (&f1)[Q],
-                                    const typename P::R (&q0)[Q], const typename P::R (&q1)[Q],
+                                    const typename P::R (&S0)[3], const typename P::R (&S1)[3],
                                     typename P::R& r0, typename P::R& r1) {
     using R = typename P::R;
     R jx = R(0), jy = R(0), jz = R(0);
@@ -186,18 +206,7 @@ __device__ inline void collide_node(const Box& bx, typename P::R (&f0)[Q], typen
         if (cz(i) > 0) jz += s;
         if (cz(i) < 0) jz -= s;
     }
-    // neighbour sums S^c = sum_i Psi^c(n + c_i) c_i
-    R s0x = R(0), s0y = R(0), s0z = R(0), s1x = R(0), s1y = R(0), s1z = R(0);
-#pragma unroll
-    for (int i = 1; i < Q; i++) {
-        const R p0 = q0[i], p1 = q1[i];
-        if (cx(i) > 0) { s0x += p0; s1x += p1; }
-        if (cx(i) < 0) { s0x -= p0; s1x -= p1; }
-        if (cy(i) > 0) { s0y += p0; s1y += p1; }
-        if (cy(i) < 0) { s0y -= p0; s1y -= p1; }
-        if (cz(i) > 0) { s0z += p0; s1z += p1; }
-        if (cz(i) < 0) { s0z -= p0; s1z -= p1; }
-    }
+    const R s0x = S0[0], s0y = S0[1], s0z = S0[2], s1x = S1[0], s1y = S1[1], s1z = S1[2];
     const int kind = bx.psi_kind;
     const R tau = R(bx.tau);
     const R irt = R(1) / (r0 + r1);
@@ -327,15 +336,10 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
     if (!(SOLID ? active : fluid)) return;
 
 #define LBE_LS(i) ((1 + cz(i)) * TP + (ly + 1 + cy(i)) * TX + (lx + 1 + cx(i)))
-    R q0[Q], q1[Q];
-#pragma unroll
-    for (int i = 1; i < Q; i++) {
-        q0[i] = s_psi[0][LBE_LS(i)];
-        q1[i] = s_psi[1][LBE_LS(i)];
-    }
-    q0[0] = q1[0] = R(0);
+    R S0[3], S1[3];
+    psi_sums<R>([&](int i) { return s_psi[0][LBE_LS(i)]; }, [&](int i) { return s_psi[1][LBE_LS(i)]; }, S0, S1);
     R r0 = R(0), r1 = R(0);
-    if (fluid) collide_node<P>(bx, f0, f1, q0, q1, r0, r1);
+    if (fluid) collide_node<P>(bx, f0, f1, S0, S1, r0, r1);
     P::st(atw(fd, nb), fluid ? f0[0] : R(0), R(wq(0)) * ref0);
     P::st(atw(fd + (size_t)Q * N, nb), fluid ? f1[0] : R(0), R(wq(0)) * ref1);
     if constexpr (!SOLID) {
@@ -505,7 +509,7 @@ __global__ __launch_bounds__(256, sizeof(typename P::R) == 8 ? 2 : 3) void k_fus
 // edges through LDS, rows wrapping periodically inside the block). Psi of the
 // rows y-1 .. y+ROWS in planes z-1..z+1 is staged in LDS.
 template <class P, int NXT, int ROWS>
-__global__ __launch_bounds__(NXT * ROWS, NXT * ROWS == 256 ? (sizeof(typename P::R) == 8 ? 2 : 4) : 1) void k_fused_rows(
+__global__ __launch_bounds__(NXT * ROWS, NXT * ROWS == 256 ? (sizeof(typename P::R) == 8 ? 3 : 4) : 1) void k_fused_rows(
     Box bx, const typename P::S* __restrict__ fs, typename P::S* __restrict__ fd,
     const typename P::R* __restrict__ psi) {
     using R = typename P::R;
@@ -568,14 +572,9 @@ __global__ __launch_bounds__(NXT * ROWS, NXT * ROWS == 256 ? (sizeof(typename P:
 #define LBE_LS(i) (((1 + cz(i)) * (ROWS + 2) + (r + 1 + cy(i))) * NXT + (cx(i) == 0 ? x : (cx(i) > 0 ? xp : xm)))
     R r0, r1;
     {
-        R q0[Q], q1[Q];
-#pragma unroll
-        for (int i = 1; i < Q; i++) {
-            q0[i] = s_psi[0][LBE_LS(i)];
-            q1[i] = s_psi[1][LBE_LS(i)];
-        }
-        q0[0] = q1[0] = R(0);
-        collide_node<P>(bx, f0, f1, q0, q1, r0, r1);
+        R S0[3], S1[3];
+        psi_sums<R>([&](int i) { return s_psi[0][LBE_LS(i)]; }, [&](int i) { return s_psi[1][LBE_LS(i)]; }, S0, S1);
+        collide_node<P>(bx, f0, f1, S0, S1, r0, r1);
     }
 #undef LBE_LS
     // publish the wave-edge values: lane 63 for c_ix = +1, lane 0 for c_ix = -1
@@ -923,10 +922,12 @@ hipError_t launch_density(lb_handle* h, int c, int o, int oo) {
 Tiles fused_tiles(int nx, int ny, bool solids, int precision) {
     Tiles t;
     // Boxes without solids whose rows fill whole blocks use the row kernel
-    // (aligned stores) for 4- and 2-byte populations; FP64 populations and
-    // boxes with solids use the tile kernel (measured faster: the FP64 row
-    // kernel is held to two waves per SIMD by its registers).
-    if (!solids && precision != LB_FP64 && ((nx == 64 && ny % 4 == 0) || (nx == 128 && ny % 2 == 0) || nx == 256 || nx == 512)) {
+    // (aligned stores) for 4- and 2-byte populations, and for FP64 on rows of
+    // up to 128 nodes (three waves per SIMD; 128^3: 0.236 against 0.245 ms).
+    // Wider FP64 rows and boxes with solids use the tile kernel (256^3 FP64:
+    // 2.09 against 2.17 ms for the row kernel).
+    if (!solids && (precision != LB_FP64 || nx <= 128) &&
+        ((nx == 64 && ny % 4 == 0) || (nx == 128 && ny % 2 == 0) || nx == 256 || nx == 512)) {
         // row kernel: whole x-rows per block
         t.BX = nx;
         t.BY = nx >= 256 ? 1 : 256 / nx;

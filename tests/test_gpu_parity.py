@@ -298,9 +298,9 @@ def test_node_touching_five_particles_fp64():
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16_dev"])
 @pytest.mark.parametrize("particles", [False, True])
 def test_row_kernel_widths(nx, prec, particles):
-    """Box widths whose x-rows fill whole blocks: without particles and with
-    4- or 2-byte populations they run the aligned-store row kernel (wave-edge
-    exchange, periodic seam); FP64 and boxes with small particles crossing
+    """Box widths whose x-rows fill whole blocks: without particles they run
+    the aligned-store row kernel (wave-edge exchange, periodic seam), in FP64
+    up to width 128; wider FP64 boxes and boxes with small particles crossing
     wave boundaries and the seam run the tile kernel."""
     from paper_1109_3277_amd.workloads import System, uniform_fields
 
