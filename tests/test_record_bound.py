@@ -56,3 +56,54 @@ def test_growing_each_axis_is_not_enough():
         n = inside - np.array(c, dtype=float)
         missed += int((_form(n, X, R, rperp + 1.5, rpar + 1.5) > 1.0).sum())
     assert missed > 0
+
+
+def test_linked_nodes_clear_the_scaled_surface_by_a_margin():
+    """The force pass evaluates the scaled-ellipsoid filter with reciprocals of
+    the squared semi-axes instead of divisions, which moves the form by a few
+    ulp. That is safe because linked nodes lie inside by far more: their form
+    stays below ((1 + sqrt 2 / m) / (1 + 1.5 / m))^2, m = min(R)."""
+    rng = np.random.default_rng(11)
+    worst = 0.0
+    for _ in range(60):
+        rpar, rperp = rng.uniform(0.5, 9.0), rng.uniform(0.5, 9.0)
+        q = rng.normal(size=4)
+        R = _rot(q / np.linalg.norm(q))
+        X = rng.uniform(0.0, 1.0, 3)
+        L = int(2 * max(rpar, rperp)) + 4
+        g = np.stack(np.meshgrid(*[np.arange(-L, L + 1)] * 3, indexing="ij"), -1).reshape(-1, 3).astype(float)
+        inside = g[_form(g, X, R, rperp, rpar) <= 1.0]
+        m = min(rpar, rperp)
+        s = 1.0 + 1.5 / m
+        bound = ((1.0 + np.sqrt(2.0) / m) / s) ** 2
+        for c in LINKS:
+            n = inside - np.array(c, dtype=float)
+            f = _form(n, X, R, s * rperp, s * rpar)
+            assert (f <= bound * (1 + 1e-12)).all()
+            worst = max(worst, float(f.max()) if len(f) else 0.0)
+    assert worst < 1.0 - 1e-4
+
+
+def test_reciprocal_form_stays_within_the_raster_band():
+    """The raster decides inside / outside with the division-free form unless
+    it lies within 1e-9 of 1, and with the exact form (divisions) otherwise.
+    The two forms must differ by far less than that band."""
+    rng = np.random.default_rng(12)
+    worst = 0.0
+    for _ in range(40):
+        rpar, rperp = rng.uniform(0.5, 40.0), rng.uniform(0.5, 40.0)
+        q = rng.normal(size=4)
+        R = _rot(q / np.linalg.norm(q))
+        d = rng.uniform(-45.0, 45.0, (20000, 3))
+        b = d @ R
+        exact = (b[:, 0] * b[:, 0] + b[:, 1] * b[:, 1]) / (rperp * rperp) + (b[:, 2] * b[:, 2]) / (rpar * rpar)
+        ia2, ic2 = 1.0 / (rperp * rperp), 1.0 / (rpar * rpar)
+        fast = (b[:, 0] * b[:, 0] + b[:, 1] * b[:, 1]) * ia2 + (b[:, 2] * b[:, 2]) * ic2
+        near = np.abs(exact - 1.0) < 0.5
+        if near.any():
+            worst = max(worst, float(np.abs(fast - exact)[near].max()))
+        # decisions taken by the fast form outside the band agree with the exact form
+        out = fast > 1.0 + 1e-9
+        inn = fast < 1.0 - 1e-9
+        assert (exact[out] > 1.0).all() and (exact[inn] <= 1.0).all()
+    assert worst < 1e-13
