@@ -216,7 +216,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU: the whole periodic box lives on one MI355X and this build "
+        print(f"bench.py runs on exactly one GPU: the whole periodic box lives on one MI355X and the library "
               f"has no multi-GPU path (asked for --gpus {args.gpus}).", file=sys.stderr)
         sys.exit(2)
 
