@@ -157,14 +157,23 @@ __device__ inline void shell_body(const Box& bx, R* __restrict__ psi, const R* _
             const BoxWalk w(lo, sz, Ls, (int)s_list[j], 1);
             const int x = w.x(), y = w.y(), z = w.z();
             const int64_t n = node_index(bx, x, y, z);
+            // owner codes first; densities only of the fluid neighbours (the
+            // gathers, not their latency, bound this loop)
             uint32_t on[Q];
+            int64_t mm[Q];
             R d0[Q], d1[Q];
 #pragma unroll
             for (int i = 1; i < Q; i++) {
-                const int64_t m = node_index(bx, wrapc(x + cx(i), nx), wrapc(y + cy(i), ny), wrapc(z + cz(i), nz));
-                on[i] = owner[m];
-                d0[i] = dens[m];
-                d1[i] = dens[N + m];
+                mm[i] = node_index(bx, wrapc(x + cx(i), nx), wrapc(y + cy(i), ny), wrapc(z + cz(i), nz));
+                on[i] = owner[mm[i]];
+            }
+#pragma unroll
+            for (int i = 1; i < Q; i++) {
+                d0[i] = d1[i] = R(0);
+                if (on[i] == OWN_FLUID) {
+                    d0[i] = dens[mm[i]];
+                    d1[i] = dens[N + mm[i]];
+                }
             }
             R s0 = R(0), s1 = R(0);
             int k = 0;
