@@ -93,7 +93,7 @@ __device__ inline void raster_body(const Box& bx, const double* __restrict__ par
         if (q > 1.0 + 1e-9) continue;
         if (q >= 1.0 - 1e-9 && !inside_test(R, dx, dy, dz, rpar, rperp)) continue;
         const int64_t n = node_index(bx, x, y, z);
-        if (owner[n] == OWN_WALL) continue;
+        if (bx.walls && owner[n] == OWN_WALL) continue;  // walls keep their code
         atomicMin(owner + n, (uint32_t)p);
     }
 }
