@@ -25,26 +25,34 @@ _LIB = os.path.join(_HERE, "_lb_oracle.so")
 NQ = 19
 
 
-def build(force: bool = True) -> str:
-    """Compile lb_oracle.c with gcc (FP64, no FMA contraction, OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+def _lib_path(plant: int) -> str:
+    return _LIB if plant == 0 else os.path.join(_HERE, f"_lb_oracle_plant{plant}.so")
+
+
+def build(force: bool = True, plant: int = 0) -> str:
+    """Compile lb_oracle.c with gcc (FP64, no FMA contraction, OpenMP).
+    plant > 0 builds a separate copy with one planted mistake (ORC_PLANT in
+    lb_oracle.c), used only by the tests that show a pin catches it."""
+    out = _lib_path(plant)
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp"
         cmd = ["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
-               "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"]
+               "-fopenmp", "-fPIC", "-shared", f"-DORC_PLANT={int(plant)}", _SRC, "-o", tmp, "-lm"]
         subprocess.check_call(cmd)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, out)
+    return out
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = C.CDLL(_LIB)
+def lib(plant: int = 0):
+    L = _libs.get(plant)
+    if L is None:
+        path = _lib_path(plant)
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            build(force=True, plant=plant)
+        L = C.CDLL(path)
         P = C.c_void_p
         dp = C.POINTER(C.c_double)
         ip = C.POINTER(C.c_int)
@@ -79,8 +87,8 @@ def lib():
         L.orc_read_owner.argtypes = [P, ip]
         L.orc_num_threads.restype = C.c_int
         L.orc_num_threads.argtypes = []
-        _lib = L
-    return _lib
+        _libs[plant] = L
+    return L
 
 
 def _d(a):
@@ -124,17 +132,18 @@ def feq(rho: float, u) -> np.ndarray:
 class Oracle:
     """One periodic nx*ny*nz system (fields indexed [z][y][x], x fastest)."""
 
-    def __init__(self, dims, tau: float, g_br: float, psi_kind: int = 1):
+    def __init__(self, dims, tau: float, g_br: float, psi_kind: int = 1, plant: int = 0):
         nx, ny, nz = (int(v) for v in dims)
         self.dims = (nx, ny, nz)
         self.N = nx * ny * nz
-        self._h = lib().orc_create(nx, ny, nz, float(tau), float(g_br), int(psi_kind))
+        self._L = lib(plant)
+        self._h = self._L.orc_create(nx, ny, nz, float(tau), float(g_br), int(psi_kind))
         if not self._h:
             raise ValueError("invalid oracle parameters")
 
     def close(self):
         if self._h:
-            lib().orc_destroy(self._h)
+            self._L.orc_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -148,17 +157,17 @@ class Oracle:
         ra = _f64(rho_a, self.N)
         rb = _f64(rho_b, self.N)
         uu = _f64(u, 3 * self.N)
-        lib().orc_init_fields(self._h, _d(ra), _d(rb), _d(uu))
+        self._L.orc_init_fields(self._h, _d(ra), _d(rb), _d(uu))
 
     def set_walls(self, mask, wall_u=None):
         m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
         assert m.size == self.N
         wu = _f64(wall_u, 3 * self.N)
-        lib().orc_set_walls(self._h, m.ctypes.data_as(C.POINTER(C.c_ubyte)), _d(wu))
+        self._L.orc_set_walls(self._h, m.ctypes.data_as(C.POINTER(C.c_ubyte)), _d(wu))
 
     def set_accel(self, a):
         aa = _f64(a, 3)
-        lib().orc_set_accel(self._h, _d(aa))
+        self._L.orc_set_accel(self._h, _d(aa))
 
     def add_ellipsoids(self, radii, pos, quat, delta_rho=None, density=None):
         radii = _f64(radii)
@@ -167,19 +176,19 @@ class Oracle:
         quat = _f64(quat, 4 * n)
         dr = _f64(delta_rho, n) if delta_rho is not None else None
         de = _f64(density, n) if density is not None else None
-        rc = lib().orc_add_ellipsoids(self._h, n, _d(radii), _d(pos), _d(quat), _d(dr), _d(de))
+        rc = self._L.orc_add_ellipsoids(self._h, n, _d(radii), _d(pos), _d(quat), _d(dr), _d(de))
         if rc != 0:
             raise ValueError(f"orc_add_ellipsoids failed ({rc})")
 
     # -- stepping
     def step(self, n: int = 1):
-        lib().orc_step(self._h, int(n))
+        self._L.orc_step(self._h, int(n))
 
     def stage(self, name: str):
-        getattr(lib(), "orc_stage_" + name)(self._h)
+        getattr(self._L, "orc_stage_" + name)(self._h)
 
     def stream_only(self):
-        lib().orc_stream_only(self._h)
+        self._L.orc_stream_only(self._h)
 
     # -- readout
     def read_fields(self):
@@ -187,67 +196,67 @@ class Oracle:
         rb = np.zeros(self.N)
         u = np.zeros(3 * self.N)
         own = np.zeros(self.N, dtype=np.int32)
-        lib().orc_read_fields(self._h, _d(ra), _d(rb), _d(u), own.ctypes.data_as(C.POINTER(C.c_int)))
+        self._L.orc_read_fields(self._h, _d(ra), _d(rb), _d(u), own.ctypes.data_as(C.POINTER(C.c_int)))
         return ra, rb, u.reshape(-1, 3), own
 
     def num_particles(self) -> int:
-        return lib().orc_num_particles(self._h)
+        return self._L.orc_num_particles(self._h)
 
     def read_particles(self):
         n = self.num_particles()
         out = {k: np.zeros((n, 3)) for k in ("pos", "vel", "omega", "force", "torque")}
         out["quat"] = np.zeros((n, 4))
-        lib().orc_read_particles(self._h, _d(out["pos"]), _d(out["quat"]), _d(out["vel"]),
+        self._L.orc_read_particles(self._h, _d(out["pos"]), _d(out["quat"]), _d(out["vel"]),
                                  _d(out["omega"]), _d(out["force"]), _d(out["torque"]))
         return out
 
     def particle_extra(self, k: int):
         o = np.zeros(20)
-        lib().orc_read_particle_extra(self._h, int(k), _d(o))
+        self._L.orc_read_particle_extra(self._h, int(k), _d(o))
         return {"L": o[0:3], "J": o[3:6], "H": o[6:9], "F_links": o[9:12], "T_links": o[12:15],
                 "M": o[15], "Iperp": o[16], "Ipar": o[17], "drho": o[18], "dens": o[19]}
 
     def set_particle_motion(self, k, V=None, L=None, W=None):
-        lib().orc_set_particle_motion(self._h, int(k), _d(_f64(V, 3)), _d(_f64(L, 3)), _d(_f64(W, 3)))
+        self._L.orc_set_particle_motion(self._h, int(k), _d(_f64(V, 3)), _d(_f64(L, 3)), _d(_f64(W, 3)))
 
     def set_particle_accum(self, k, F, T):
-        lib().orc_set_particle_accum(self._h, int(k), _d(_f64(F, 3)), _d(_f64(T, 3)))
+        self._L.orc_set_particle_accum(self._h, int(k), _d(_f64(F, 3)), _d(_f64(T, 3)))
 
     def stats(self):
         o = np.zeros(8)
-        lib().orc_stats(self._h, _d(o))
+        self._L.orc_stats(self._h, _d(o))
         return o
 
     def ledger(self):
         o = np.zeros(3)
-        lib().orc_step_ledger(self._h, _d(o))
+        self._L.orc_step_ledger(self._h, _d(o))
         return {"link_C": o[0], "kill": o[1], "fill": o[2]}
 
     def get_pops(self, c: int) -> np.ndarray:
         o = np.zeros(NQ * self.N)
-        lib().orc_get_pops(self._h, int(c), _d(o))
+        self._L.orc_get_pops(self._h, int(c), _d(o))
         return o.reshape(NQ, self.N)
 
     def set_pops(self, c: int, f):
         a = _f64(f, NQ * self.N)
-        lib().orc_set_pops(self._h, int(c), _d(a))
+        self._L.orc_set_pops(self._h, int(c), _d(a))
 
     def rho_internal(self):
         ra = np.zeros(self.N)
         rb = np.zeros(self.N)
-        lib().orc_get_rho_internal(self._h, _d(ra), _d(rb))
+        self._L.orc_get_rho_internal(self._h, _d(ra), _d(rb))
         return ra, rb
 
     def set_rho_internal(self, ra, rb):
-        lib().orc_set_rho_internal(self._h, _d(_f64(ra, self.N)), _d(_f64(rb, self.N)))
+        self._L.orc_set_rho_internal(self._h, _d(_f64(ra, self.N)), _d(_f64(rb, self.N)))
 
     def sc_force(self):
         fa = np.zeros(3 * self.N)
         fb = np.zeros(3 * self.N)
-        lib().orc_sc_force(self._h, _d(fa), _d(fb))
+        self._L.orc_sc_force(self._h, _d(fa), _d(fb))
         return fa.reshape(-1, 3), fb.reshape(-1, 3)
 
     def owner(self):
         o = np.zeros(self.N, dtype=np.int32)
-        lib().orc_read_owner(self._h, o.ctypes.data_as(C.POINTER(C.c_int)))
+        self._L.orc_read_owner(self._h, o.ctypes.data_as(C.POINTER(C.c_int)))
         return o

@@ -59,6 +59,20 @@
 #define OWN_FLUID (-1)
 #define OWN_WALL (-2)
 
+/* Planted mistakes. The test suite builds separate copies of this file with
+ * -DORC_PLANT=k to show that its pins catch each of these errors; the
+ * checker itself is built with ORC_PLANT = 0 (none):
+ *   1  torque arm of a bounce-back link taken from the centre the particle
+ *      reaches at the coming body update (X + V) instead of its current one
+ *   2  twice the rotational part W x r of the surface velocity in C (Eq. (4))
+ *   3  angular impulse of a kill / fill taken about the centre before the
+ *      body update instead of the moved centre
+ *   4  Shan-Chen force with the neighbour sum of the component itself
+ *      instead of the other one (Eq. (3)) */
+#ifndef ORC_PLANT
+#define ORC_PLANT 0
+#endif
+
 /* D3Q19 velocity set: rest, 6 axis links, 12 face diagonals. Opposite pairs
  * sit next to each other (1,2), (3,4), ..., (17,18). */
 static const int CX[NQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
@@ -78,6 +92,7 @@ static int opp(int i) {
 
 typedef struct {
     double X[3];      /* centre, in [0, L) */
+    double Xold[3];   /* centre before the last body update */
     double q[4];      /* orientation (w, x, y, z), body -> space */
     double V[3];      /* velocity */
     double W[3];      /* angular velocity (space frame) */
@@ -516,6 +531,9 @@ void orc_stage_collide(orc_t *s) {
             for (int k = 0; k < 3; k++) up[k] = (s->jm[0][3 * n + k] + s->jm[1][3 * n + k]) / rt;
             for (int c = 0; c < 2; c++) {
                 int o = 1 - c;
+#if ORC_PLANT == 4
+                o = c;
+#endif
                 double pr = psi_over_rho(s, s->rho[c][n]);
                 double ueq[3];
                 for (int k = 0; k < 3; k++) {
@@ -545,6 +563,11 @@ static double link_C(const orc_t *s, long n, int i, int c, long m, double r[3]) 
         coords(s, n, &x, &y, &z);
         double mid[3] = {x + 0.5 * CX[i], y + 0.5 * CY[i], z + 0.5 * CZ[i]};
         surf_vel(s, &s->P[o], mid, r, ub);
+#if ORC_PLANT == 2
+        ub[0] += s->P[o].W[1] * r[2] - s->P[o].W[2] * r[1];
+        ub[1] += s->P[o].W[2] * r[0] - s->P[o].W[0] * r[2];
+        ub[2] += s->P[o].W[0] * r[1] - s->P[o].W[1] * r[0];
+#endif
     } else if (o == OWN_WALL && s->wall_u) {
         ub[0] = s->wall_u[3 * m];
         ub[1] = s->wall_u[3 * m + 1];
@@ -610,6 +633,9 @@ void orc_stage_stream(orc_t *s) {
                 double mag = 2.0 * s->f[c][i * N + n] + C;
                 double dF[3] = {mag * CX[i], mag * CY[i], mag * CZ[i]};
                 for (int d = 0; d < 3; d++) p->F[d] += dF[d];
+#if ORC_PLANT == 1
+                for (int d = 0; d < 3; d++) r[d] -= p->V[d];
+#endif
                 p->T[0] += r[1] * dF[2] - r[2] * dF[1];
                 p->T[1] += r[2] * dF[0] - r[0] * dF[2];
                 p->T[2] += r[0] * dF[1] - r[1] * dF[0];
@@ -619,8 +645,8 @@ void orc_stage_stream(orc_t *s) {
 }
 
 /* ---------------------------------------------------------------- S7 */
-/* Newton-Euler update with dt = 1 (Sec. 2, "Newton's equation ... classical
- * molecular dynamics"; integrator R18):
+/* Newton-Euler update with dt = 1 (Sec. 2: the particles obey Newton's
+ * equations, integrated as in molecular dynamics; integrator R18):
  *   F = F_links + J, T = T_links + H, J = H = 0
  *   V += F / M, X = wrap(X + V), L += T
  *   W = R(q) I_b^-1 R(q)^T L  (old q)
@@ -637,6 +663,7 @@ void orc_stage_bodies(orc_t *s) {
             p->lastT[d] = T[d];
         }
         for (int d = 0; d < 3; d++) {
+            p->Xold[d] = p->X[d];
             p->V[d] += F[d] / p->M;
             double L = d == 0 ? s->nx : (d == 1 ? s->ny : s->nz);
             double x = p->X[d] + p->V[d];
@@ -708,6 +735,9 @@ void orc_stage_raster_killfill(orc_t *s) {
                 }
             double pos[3] = {x, y, z}, r[3], ub[3];
             surf_vel(s, p, pos, r, ub);
+#if ORC_PLANT == 3
+            for (int d = 0; d < 3; d++) r[d] += p->X[d] - p->Xold[d];
+#endif
             for (int d = 0; d < 3; d++) p->J[d] += j[d];
             p->H[0] += r[1] * j[2] - r[2] * j[1];
             p->H[1] += r[2] * j[0] - r[0] * j[2];
@@ -737,6 +767,9 @@ void orc_stage_raster_killfill(orc_t *s) {
                 s->fill_mass += rn[c];
                 for (int d = 0; d < 3; d++) jm[d] += rn[c] * ub[d];
             }
+#if ORC_PLANT == 3
+            for (int d = 0; d < 3; d++) r[d] += p->X[d] - p->Xold[d];
+#endif
             for (int d = 0; d < 3; d++) p->J[d] -= jm[d];
             p->H[0] -= r[1] * jm[2] - r[2] * jm[1];
             p->H[1] -= r[2] * jm[0] - r[0] * jm[2];
