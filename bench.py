@@ -1,13 +1,16 @@
 """Benchmark: MLUPS of the full two-component D3Q19 Shan-Chen step with moving
-ellipsoids on one MI355X, its HBM roofline fraction, the reduced-precision
-forms on the same workload, and the CPU FP64 oracle timed on the host.
+ellipsoids on one MI355X, the HBM roofline fraction of its dominant kernel,
+the reduced-precision forms on the same workload with their errors against
+FP64, the smaller workloads, the batched ensemble, and the CPU FP64 oracle
+timed on the host.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload bijel]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload mixed]
 
 Prints one JSON line. A step is one full time step of the method (densities,
 shell fill, Shan-Chen force, BGK collision, streaming with moving bounce-back
 and particle force/torque, rigid-body update, re-rasterisation with kill/fill)
-over the whole box, inputs resident in HBM.
+over the whole box, inputs resident in HBM. The headline workload is the
+largest single-GPU one: 512^3 with 41,802 ellipsoids in FP64.
 """
 from __future__ import annotations
 
@@ -27,6 +30,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 METRIC = "MLUPS (2-comp D3Q19+ellipsoids) FP64 vs mixed-prec; % HBM peak GB/s"
 STORE = {"fp64": 8, "fp32": 4, "fp16_dev": 2, "bf16_dev": 2}
 RHO = {"fp64": 8, "fp32": 4, "fp16_dev": 4, "bf16_dev": 4}
+DTYPE = {"fp64": "f64", "fp32": "f32", "fp16_dev": "f16-storage/f32", "bf16_dev": "bf16-storage/f32"}
+PROFILE_STEPS = 20  # event-timed steps for the per-kernel roofline (after the timed region)
 
 
 def log(msg):
@@ -50,7 +55,12 @@ def step_bytes_per_node(prec: str) -> int:
 def make_workload(name: str):
     from paper_1109_3277_amd import workloads as W
 
-    if name == "bijel":
+    if name == "mixed":
+        s = W.mixed_system()
+        desc = (f"mixed-precision domain: 512^3 periodic, two components 0.7 +- 0.01 noise, g_br=0.08, tau=1, "
+                f"{s.n_particles} ellipsoids R_perp=4, aspect U[0.5,2], colour U[-0.3,0.3], volume fraction 0.1, "
+                f"particle density 8")
+    elif name == "bijel":
         s = W.bijel_system()
         desc = (f"bijel: 256^3 periodic, two components 50/50 (0.7 +- 0.01 noise), g_br=0.08, tau=1, "
                 f"{s.n_particles} prolate ellipsoids Rpar=8 Rperp=4 (volume fraction 0.15), colour 0")
@@ -65,36 +75,48 @@ def make_workload(name: str):
     return s, desc
 
 
-def run_gpu(s, prec, steps, warmup, profile=True):
-    import torch
-
+def _lattice(s, prec):
     from paper_1109_3277_amd.binding import Lattice
 
     g = Lattice(s.dims, s.tau, s.g_br, s.psi_kind, prec, max_particles=s.n_particles, max_radius=s.max_radius)
     g.init_fields(s.rho_a, s.rho_b)
     if s.n_particles:
         g.add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
+    return g
+
+
+def run_gpu(s, prec, steps, warmup, profile_steps=PROFILE_STEPS, keep_fields=False):
+    """Warm-up, then `steps` timed steps with per-kernel profiling off, then
+    `profile_steps` steps with HIP events around every launch (per-kernel
+    average durations for the roofline)."""
+    import torch
+
+    g = _lattice(s, prec)
+    m0 = g.stats()[:2].copy()
     g.step(warmup)
     torch.cuda.synchronize()
-    if profile:
-        g.profile(True)
     t0 = time.perf_counter()
     g.step_async(steps)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = g.profile_read() if profile else None
-    g.profile(False)
-    st = g.stats()
+    sec = time.perf_counter() - t0
     g.step(0)  # health check of the timed steps
-    sec = t1 - t0
-    out = {"mlups": s.N * steps / sec / 1e6, "ms_per_step": 1e3 * sec / steps, "prof": prof, "stats": st}
-    if profile:  # one host readout of rho_a, rho_b, u and the owner map (PCIe-inclusive figure)
-        t2 = time.perf_counter()
-        g.read_fields()
-        out["readout_ms"] = 1e3 * (time.perf_counter() - t2)
+    out = {"mlups": s.N * steps / sec / 1e6, "ms_per_step": 1e3 * sec / steps}
+    fields = None
+    if keep_fields:  # densities and owner map after warm-up + timed steps
+        ra, rb, _, own = g.read_fields()
+        fields = (ra, rb, own)
+        out["mass_change"] = ((g.stats()[:2] - m0) / m0).tolist()
+    if profile_steps:
+        g.profile(True)
+        g.step_async(profile_steps)
+        torch.cuda.synchronize()
+        out["prof"] = g.profile_read()
+        g.profile(False)
+        g.step(0)
+    g.close()
     del g
     torch.cuda.empty_cache()
-    return out
+    return out, fields
 
 
 def roofline_of(s, prec, res, traffic):
@@ -104,7 +126,8 @@ def roofline_of(s, prec, res, traffic):
     achieved = per_launch / avg_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "k_fused",
-            "algorithmic_bytes_per_launch": per_launch, "avg_launch_ms": round(ms / launches, 5)}
+            "algorithmic_bytes_per_launch": per_launch, "avg_launch_ms": round(ms / launches, 5),
+            "launches_timed": launches}
 
 
 def measured_traffic(workload: str, prec: str):
@@ -121,10 +144,45 @@ def measured_traffic(workload: str, prec: str):
     return rec.get("bytes_per_launch")
 
 
-def run_batch(steps, warmup):
-    """The 64-system interface ensemble (FP32 fluid, FP64 particles): batched
-    (one launch per phase over all systems, two-step HIP graphs, tuned tile
-    shape) against the same systems stepped one after another."""
+def form_errors(ref, fields, s):
+    """Densities of a form against FP64 after the same steps, on nodes fluid
+    in both runs (RMS and max over max |rho|), owner codes that differ."""
+    RA, RB, OWN = ref
+    ra, rb, own = fields
+    both = (own == -1) & (OWN == -1)
+    sc = max(np.abs(RA).max(), np.abs(RB).max())
+    d = np.concatenate([(ra - RA)[both], (rb - RB)[both]])
+    return {"rho_rms": float(np.sqrt(np.mean(d * d)) / sc), "rho_max": float(np.abs(d).max() / sc),
+            "owner_diff": int((own != OWN).sum())}
+
+
+def run_forms(s, workload, steps, warmup, main_prec, main_res, main_fields):
+    forms = {}
+    for prec in ("fp64", "fp32", "fp16_dev", "bf16_dev"):
+        if prec == main_prec:
+            r, fields = main_res, main_fields
+        else:
+            log(f"timing {workload} {prec}")
+            r, fields = run_gpu(s, prec, steps, warmup, keep_fields=main_fields is not None)
+        f = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+             "fused_roofline_frac": roofline_of(s, prec, r, None)["frac"],
+             "step_alg_gbs": round(r["mlups"] * 1e6 * step_bytes_per_node(prec) / 1e9, 1)}
+        if main_fields is not None and prec != "fp64" and main_prec == "fp64":
+            f["vs_fp64_after_steps"] = warmup + steps
+            f.update(form_errors(main_fields, fields, s))
+            f["mass_drift_vs_fp64"] = [round(a - b, 9) for a, b in zip(r["mass_change"], main_res["mass_change"])]
+        forms[prec] = f
+        del fields
+    for prec in forms:
+        forms[prec]["speedup_vs_fp64"] = round(forms[prec]["mlups"] / forms["fp64"]["mlups"], 3)
+    return forms
+
+
+def run_batch(steps, warmup, lone_steps):
+    """The 64-system interface ensemble (FP32 fluid, FP64 particles): `steps`
+    steps of every system in one HIP-graph launch after tuning, against the
+    same systems stepped one after another; fused-kernel roofline from the
+    tuner's timing."""
     import torch
 
     from paper_1109_3277_amd import workloads as W
@@ -137,18 +195,19 @@ def run_batch(steps, warmup):
     for k, s in enumerate(systems):
         b[k].init_fields(s.rho_a, s.rho_b)
         b[k].add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
-    bx = b.tune()
+    tune = b.tune_report()
     b.step(warmup)
+    b.step(steps)  # records the graph of `steps` steps (untimed first launch)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    b.step_async(steps)
+    b.step_async(steps)  # one graph launch: `steps` steps of all 64 systems
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    g_steps, g_nodes = b.last_graph()
     b.step(0)
     b.close()
     del b
     torch.cuda.empty_cache()
-    # one by one: every system on its own handle, all created first
     lone = []
     for s in systems:
         g = Lattice(s.dims, s.tau, s.g_br, s.psi_kind, "fp32", max_particles=s.n_particles, max_radius=s.max_radius)
@@ -159,60 +218,88 @@ def run_batch(steps, warmup):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for g in lone:
-        g.step_async(steps)
+        g.step_async(lone_steps)
     torch.cuda.synchronize()
     t_lone = time.perf_counter() - t0
     for g in lone:
         g.step(0)
+        g.close()
     del lone
     torch.cuda.empty_cache()
-    return {"systems": len(systems), "nodes": n_nodes, "steps": steps, "tile_width": bx,
-            "mlups_batched": round(n_nodes * steps / t_batch / 1e6, 1),
-            "mlups_one_by_one": round(n_nodes * steps / t_lone / 1e6, 1),
-            "speedup": round(t_lone / t_batch, 3), "precision": "fp32 fluid, fp64 particles"}
+    per = fused_bytes_per_node("fp32", True) * n_nodes
+    fused_ms = tune["best_ms"]
+    mlups_b = n_nodes * steps / t_batch / 1e6
+    mlups_l = n_nodes * lone_steps / t_lone / 1e6
+    assert g_steps == steps
+    return {"systems": len(systems), "nodes": n_nodes, "steps": steps, "graph_launches": 1,
+            "kernel_nodes_in_graph": g_nodes,
+            "tile": tune["tile"], "tuner_candidates_ms": tune["candidates"], "tuner_cached": tune["cached"],
+            "mlups_batched": round(mlups_b, 1), "mlups_one_by_one": round(mlups_l, 1),
+            "one_by_one_steps": lone_steps, "speedup": round(mlups_b / mlups_l, 3),
+            "precision": "fp32 fluid, fp64 particles",
+            "roofline": {"bound": "hbm", "kernel": "k_fused_batch (all systems, one launch)",
+                         "achieved": round(per / (fused_ms / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(per / (fused_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                         "algorithmic_bytes_per_launch": per, "avg_launch_ms": round(fused_ms, 5)}}
 
 
-def run_forms512(steps, warmup):
-    """The 512^3 domain with 41,802 ellipsoids in each precision form (ms per
-    step and MLUPS; errors against FP64 are checked by the test suite)."""
-    from paper_1109_3277_amd import workloads as W
+def host_info():
+    model, mem = "unknown", None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                mem = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    return model, mem
 
-    s = W.mixed_system()
-    out = {}
-    for prec in ("fp64", "fp32", "fp16_dev", "bf16_dev"):
-        log(f"timing 512^3 {prec}")
-        r = run_gpu(s, prec, steps, warmup, profile=False)
-        out[prec] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 3)}
-    for prec in out:
-        out[prec]["speedup_vs_fp64"] = round(out[prec]["mlups"] / out["fp64"]["mlups"], 3)
-    return {"dims": list(s.dims), "n_particles": s.n_particles, "steps": steps, "forms": out}
 
-
-def cpu_baseline(s, steps):
+def cpu_baseline(steps):
+    """The CPU FP64 oracle on a bounded sample of the headline recipe: the
+    512^3 recipe (same particle shapes, colours, density and volume fraction)
+    on a 256^3 box, timed with all host threads and with one."""
     import oracle
 
+    from paper_1109_3277_amd import workloads as W
+
+    s = W.mixed_system(n=256)
     o = oracle.Oracle(s.dims, s.tau, s.g_br, s.psi_kind)
     o.init_fields(s.rho_a, s.rho_b)
-    if s.n_particles:
-        o.add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
+    o.add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
+    threads = oracle.num_threads()
     t0 = time.perf_counter()
     o.step(steps)
-    sec = time.perf_counter() - t0
-    return {"value": round(s.N * steps / sec / 1e6, 3), "unit": "MLUPS", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"the same {s.dims[0]}x{s.dims[1]}x{s.dims[2]} system with its {s.n_particles} particles, "
-                      f"{steps} full time steps (FP64 oracle, OpenMP over z-slabs)"}
+    many = s.N * steps / (time.perf_counter() - t0) / 1e6
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    o.step(1)
+    one = s.N / (time.perf_counter() - t0) / 1e6
+    oracle.set_threads(threads)
+    model, mem = host_info()
+    return {"value": round(many, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "single_thread_mlups": round(one, 3), "cpu_model": model, "host_mem_gib": mem,
+            "host_logical_cpus": os.cpu_count(),
+            "sample": f"the 512^3 workload's recipe on a 256^3 box ({s.n_particles} ellipsoids, same shapes, colours, "
+                      f"density and volume fraction), {steps} full time steps with {threads} threads and 1 step with "
+                      f"1 thread (FP64 oracle, OpenMP over z-slabs)"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="bijel", choices=["bijel", "spinodal", "interface"])
+    ap.add_argument("--workload", default="mixed", choices=["mixed", "bijel", "spinodal", "interface"])
     ap.add_argument("--precision", default="fp64", choices=list(STORE))
-    ap.add_argument("--no-forms", action="store_true", help="skip the reduced-precision and pure-fluid runs")
+    ap.add_argument("--no-forms", action="store_true", help="skip the other precision forms and workloads")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched ensemble")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--cpu-steps", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -229,67 +316,59 @@ def main():
     s, desc = make_workload(args.workload)
     log(f"workload ready in {time.perf_counter() - t:.1f} s: {desc}")
 
-    log(f"timing {args.precision}: warmup {args.warmup}, steps {args.steps}")
-    main_res = run_gpu(s, args.precision, args.steps, args.warmup)
+    keep = not args.no_forms
+    log(f"timing {args.precision}: warmup {args.warmup}, steps {args.steps}, then {PROFILE_STEPS} event-timed steps")
+    main_res, main_fields = run_gpu(s, args.precision, args.steps, args.warmup, keep_fields=keep)
     log(f"  {main_res['mlups']:.1f} MLUPS, {main_res['ms_per_step']:.3f} ms/step, phases {main_res['prof']}")
     traffic = measured_traffic(args.workload, args.precision)
     roof = roofline_of(s, args.precision, main_res, traffic)
 
-    forms = {}
+    forms = other = None
     if not args.no_forms:
-        for prec in ("fp64", "fp32", "fp16_dev", "bf16_dev"):
-            if prec == args.precision:
-                r = main_res
-            else:
-                log(f"timing form {prec}")
-                r = run_gpu(s, prec, args.steps, args.warmup)
-            forms[prec] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
-                           "speedup_vs_fp64": None,
-                           "fused_roofline_frac": roofline_of(s, prec, r, None)["frac"],
-                           "step_alg_gbs": round(r["mlups"] * 1e6 * step_bytes_per_node(prec) / 1e9, 1)}
-        for prec in forms:
-            forms[prec]["speedup_vs_fp64"] = round(forms[prec]["mlups"] / forms["fp64"]["mlups"], 3)
-        if args.workload != "spinodal":
-            sp, _ = make_workload("spinodal")
-            for prec in ("fp64", "fp32"):
-                log(f"timing pure fluid 128^3 {prec}")
-                r = run_gpu(sp, prec, args.steps, args.warmup)
-                forms[f"spinodal128_{prec}"] = {"mlups": round(r["mlups"], 1),
-                                                "fused_roofline_frac": roofline_of(sp, prec, r, None)["frac"]}
+        forms = run_forms(s, args.workload, args.steps, args.warmup, args.precision, main_res, main_fields)
+        log(f"  forms {forms}")
+        del main_fields
+        other = {}
+        for wl, st in (("bijel", 200), ("spinodal", 200)):
+            if wl == args.workload:
+                continue
+            w, wdesc = make_workload(wl)
+            blk = {"workload": wdesc, "dims": list(w.dims), "n_particles": w.n_particles, "steps": st}
+            for prec in (("fp64", "fp32", "fp16_dev") if wl == "bijel" else ("fp64", "fp32")):
+                log(f"timing {wl} {prec}")
+                r, _ = run_gpu(w, prec, st, 10)
+                blk[prec] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                             "fused_roofline_frac": roofline_of(w, prec, r, None)["frac"],
+                             "traffic_per_fused_launch": measured_traffic(wl, prec),
+                             "phases_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in r["prof"].items()}}
+            other[wl] = blk
+            log(f"  {wl} {blk}")
 
-    batch = forms512 = None
-    if not args.no_forms:
-        forms512 = run_forms512(50, 5)
-        log(f"  512^3 forms {forms512}")
-        log("timing the 64-system batch")
-        batch = run_batch(args.steps, args.warmup)
+    batch = None
+    if not args.no_batch:
+        log(f"timing the 64-system batch ({args.batch_steps} steps in one graph launch)")
+        batch = run_batch(args.batch_steps, args.warmup, 200)
         log(f"  batch {batch}")
 
     cpu = None
     if not args.no_cpu:
-        log(f"timing the CPU oracle ({args.cpu_steps} steps)")
-        cpu = cpu_baseline(s, args.cpu_steps)
+        log("timing the CPU oracle")
+        cpu = cpu_baseline(args.cpu_steps)
         log(f"  oracle {cpu}")
 
     value = main_res["mlups"]
     rec = {
         "metric": METRIC, "value": round(value, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(main_res["ms_per_step"], 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "fp16_dev": "f16-storage/f32", "bf16_dev": "bf16-storage/f32"}[
-            args.precision],
-        "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.precision], "data": "synthetic",
         "config": {"workload": desc, "dims": list(s.dims), "n_nodes": s.N, "n_particles": s.n_particles,
                    "precision": args.precision, "parallelism": "1 GPU, whole box"},
         "roofline": roof,
         "step_hbm_frac_alg": round(value * 1e6 * step_bytes_per_node(args.precision) / 1e9 / HBM_PEAK_GBS, 4),
         "phases_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in main_res["prof"].items()},
-        "host_readout_ms": round(main_res.get("readout_ms", 0.0), 1),
-        "mlups_with_one_readout": round(s.N * args.steps / (1e-3 * (main_res["ms_per_step"] * args.steps +
-                                                                     main_res.get("readout_ms", 0.0))) / 1e6, 1),
         "cpu_baseline": cpu,
         "forms": forms,
-        "forms_512": forms512,
+        "other_workloads": other,
         "batch": batch,
     }
     print(json.dumps(rec), flush=True)

@@ -113,11 +113,21 @@ int lb_step(lb_handle* h, int32_t nsteps);
  * running (for timing and graph capture by the caller). */
 int lb_step_async(lb_handle* h, int32_t nsteps);
 
-/* Read densities rho_a, rho_b (N each), barycentric velocity u = (j^A+j^B) /
- * (rho^A+rho^B) (3N) and the owner map (N int32: -1 fluid, -2 wall, p >= 0
- * particle index). Solid nodes read 0 density and velocity. Any output may be
- * NULL. Synchronises the stream. */
+/* Macroscopic fields (Sec. 2, the moments defined after Eq. (2): rho^c =
+ * sum_i f_i^c and rho^c u^c = sum_i f_i^c c_i): densities rho_a, rho_b (N
+ * each), barycentric velocity u = (j^A+j^B) / (rho^A+rho^B) (3N, x y z per
+ * node, without a half-force correction) and the owner map (N int32: -1
+ * fluid, -2 wall, p >= 0 particle index; particles are discretised on the
+ * lattice, Sec. 2). Solid nodes read 0 density and velocity. Any output may
+ * be NULL. Host buffers are the caller's. Synchronises the stream. */
 int lb_read_fields(lb_handle* h, double* rho_a, double* rho_b, double* u, int32_t* owner);
+
+/* The same fields as lb_read_fields, written to the caller's device memory
+ * (dev_rho_a, dev_rho_b: N doubles; dev_u: 3N doubles; dev_owner: N int32;
+ * any may be NULL), ordered on the handle's stream without waiting: for
+ * analysis on the GPU without a host round trip. The buffers must not
+ * overlap the workspace. */
+int lb_read_fields_dev(lb_handle* h, double* dev_rho_a, double* dev_rho_b, double* dev_u, int32_t* dev_owner);
 
 /* Number of particles on the handle (or a negative error code). */
 int lb_num_particles(const lb_handle* h);
@@ -128,15 +138,34 @@ int lb_num_particles(const lb_handle* h);
 int lb_read_particles(lb_handle* h, double* pos, double* quat, double* vel, double* omega, double* force,
                       double* torque);
 
-/* Diagnostics, FP64, deterministic order: out[0..7] = {mass A, mass B,
- * momentum x, y, z over fluid nodes, mass removed by particles (killed minus
- * filled, cumulative), number of fluid nodes, health (1 = NaN or negative
- * density present)}. Synchronises the stream. */
+/* Diagnostics of the conserved quantities of Sec. 2 (per-component mass
+ * sum_n rho^c, which the BGK step (2) and streaming (1) conserve, and the
+ * total fluid momentum, which the Shan-Chen force (3) leaves unchanged since
+ * its pair forces cancel), FP64, deterministic order: out[0..7] = {mass A,
+ * mass B, momentum x, y, z over fluid nodes, mass removed by particles
+ * (removed at placement plus killed minus filled as they move, cumulative),
+ * number of fluid nodes, health (1 = NaN or negative density present)}.
+ * out is the caller's host array of 8 doubles. Synchronises the stream. */
 int lb_stats(lb_handle* h, double out[8]);
 
 /* Uniform body acceleration a (3 doubles) added to every fluid node's force
  * (test and channel-flow use; default 0). */
 int lb_set_body_accel(lb_handle* h, const double a[3]);
+
+/* Particle-particle interactions (Sec. 2, Eqs. (6)-(9)), off by default:
+ * Hertz repulsion K_H (2R - r)^{5/2} of equal spheres (Eq. (6)) extended to
+ * ellipsoids with the Berne-Pechukas strength and range of Eqs. (7)-(8)
+ * (sigma_bar = 2 R_o, eps_bar = K_H sigma_bar^{5/2}; for two particles of
+ * different shape R_p and R_o are the means of the pair's), and the
+ * lubrication correction of Eq. (9) with the ellipsoid gap |r| - sigma and
+ * R = sigma / 2, opposing the normal relative velocity, for gaps below
+ * delta_c (taken no smaller than delta_c / 4), viscosity from the initial
+ * mean densities. The paper uses K_H = 100 and delta_c = 2/3. The forces and
+ * torques join the bounce-back sums at each rigid-body update; pairs are
+ * found with a device cell list and summed in a fixed order. on = 0 turns
+ * them off. LB_EINVAL for K_H < 0 or delta_c <= 0; LB_ESTATE on a batch or
+ * system handle, or when max_particles < 2. */
+int lb_set_pair_interactions(lb_handle* h, int on, double K_H, double delta_c);
 
 /* Static solid (wall) nodes, for channel tests (Couette / Poiseuille):
  * mask[n] != 0 (N bytes, x fastest) marks node n as a wall; wall_u (3
@@ -170,32 +199,41 @@ int lb_load_state(lb_handle* h, const void* host_buf, size_t bytes);
 int lb_profile_enable(lb_handle* h, int on);
 int lb_profile_read(lb_handle* h, double* ms, int64_t* launches);
 
-/* Calibration helper for hardware traffic counters: copies `bytes` bytes
- * (a multiple of 16) from dev_src to dev_dst on hip_stream with a plain
- * streaming kernel, so that a profiler's fetch / write byte counters can be
- * scaled against a transfer of known size. Not part of the method. */
-int lb_probe_copy(void* dev_dst, const void* dev_src, size_t bytes, void* hip_stream);
-
 /* ---- Batches: many independent periodic systems advanced together.
  * The method per system is unchanged (same equations, same arithmetic: a
  * system stepped in a batch ends bit for bit where a lone handle with the
  * same parameters and inputs ends; the one exception is a particle-free box
  * in 4- or 2-byte storage whose width is 64, 128, 256 or 512, which a lone
- * handle runs with its row kernel and a batch with tiles, equal to rounding). Each kernel phase is one launch over all
- * systems, and the step sequence runs as a HIP graph of two steps on the
- * batch's own stream (ordered after and before the creation stream with
- * events), so many small systems fill the GPU and launch cost is paid once
- * per graph. All systems share one precision; dims, tau, g_br, psi_kind and
- * particle capacity may differ per system. */
+ * handle runs with its row kernel and a batch with tiles, equal to
+ * rounding). Each kernel phase is one launch over all systems, and n steps
+ * run as one captured HIP graph, launched on the stream given at creation
+ * (the graph is recorded on a private capture stream and runs nowhere else),
+ * so many small systems fill the GPU and launch cost is paid once per call.
+ * All systems share one precision; dims, tau, g_br, psi_kind and particle
+ * capacity may differ per system. */
 
 /* Workspace bytes for nsys systems with parameters per_sys[0..nsys-1] (0 if
  * any is invalid or the precisions differ). */
 size_t lb_batch_workspace_bytes(int32_t nsys, const lb_params* per_sys);
 
-/* Create a batch handle over one caller-owned workspace. The systems start
- * empty: initialise each through its system handle. *out is NULL on failure. */
-int lb_batch_create(int32_t nsys, const lb_params* per_sys, void* dev_ws, size_t ws_bytes, void* hip_stream,
+/* Create a batch handle over one caller-owned workspace and HIP stream (as
+ * lb_create). The systems start empty: initialise each with the *_sys calls
+ * below (or through its system handle). *out is NULL on failure. */
+int lb_create_batch(int32_t nsys, const lb_params* per_sys, void* dev_ws, size_t ws_bytes, void* hip_stream,
                     lb_handle** out);
+
+/* Per-system calls on a batch handle: the same arguments, layouts, errors
+ * and ownership as lb_init_fields, lb_add_ellipsoids, lb_read_fields,
+ * lb_read_particles and lb_stats, for system `sys` (0 <= sys < nsys, else
+ * LB_EINVAL). lb_step / lb_step_async on the batch handle advance every
+ * system; each must have fields first (LB_ESTATE otherwise). */
+int lb_init_fields_sys(lb_handle* batch, int32_t sys, const double* rho_a, const double* rho_b, const double* u);
+int lb_add_ellipsoids_sys(lb_handle* batch, int32_t sys, int32_t n, const double* radii, const double* pos,
+                          const double* quat, const double* delta_rho, const double* density);
+int lb_read_fields_sys(lb_handle* batch, int32_t sys, double* rho_a, double* rho_b, double* u, int32_t* owner);
+int lb_read_particles_sys(lb_handle* batch, int32_t sys, double* pos, double* quat, double* vel, double* omega,
+                          double* force, double* torque);
+int lb_stats_sys(lb_handle* batch, int32_t sys, double out[8]);
 
 /* Number of systems of a batch handle (or a negative error code). */
 int lb_batch_size(const lb_handle* batch);
@@ -203,21 +241,37 @@ int lb_batch_size(const lb_handle* batch);
 /* The handle of system `sys`, owned by the batch (valid until the batch is
  * destroyed; lb_destroy on it is a no-op). It takes every per-system call:
  * lb_init_fields, lb_add_ellipsoids, lb_read_fields, lb_read_particles,
- * lb_stats, lb_set_body_accel, lb_save_state / lb_load_state. lb_step on it
- * returns LB_ESTATE: systems advance only with lb_step / lb_step_async on the
- * batch handle, which every system must have fields for. Per-system calls on
- * the batch handle itself return LB_ESTATE. */
+ * lb_stats, lb_set_body_accel, lb_set_static_solid, lb_save_state /
+ * lb_load_state. lb_step on it returns LB_ESTATE: systems advance only with
+ * lb_step / lb_step_async on the batch handle. Per-system calls on the batch
+ * handle itself return LB_ESTATE. */
 int lb_batch_system(lb_handle* batch, int32_t sys, lb_handle** out);
 
-/* Autotune the fused kernel's tile shape (64 x 4 or 32 x 8 nodes per block)
- * for this batch by timing both on the current state (the timed launches only
- * write the scratch population copy; the state does not change). Writes the
- * chosen tile width (64 or 32) to *tile_width if not NULL. Results do not
- * depend on the choice. Requires fields on every system. */
-int lb_batch_tune(lb_handle* batch, int32_t* tile_width);
+/* Autotune the fused kernel's tile shape for this batch: each candidate
+ * (BX x 256/BX nodes of one xy-plane per 256-thread block, BX in
+ * tile_widths) is timed on the current state over all systems (the timed
+ * launches only write the scratch population copy; the state does not
+ * change) and the fastest is kept. The choice is cached for the life of the
+ * process per precision and system shapes (box, solids or not); a batch of
+ * the same shapes takes it without timing. Results do not depend on the
+ * choice. Requires fields on every system. out (may be NULL) receives the
+ * chosen width, whether it came from the cache, and each candidate's time
+ * per fused launch over all systems in ms. */
+#define LB_TUNE_CANDIDATES 3
+typedef struct {
+    int32_t tile_width;
+    int32_t cached;
+    int32_t tile_widths[LB_TUNE_CANDIDATES];
+    double ms[LB_TUNE_CANDIDATES];
+} lb_tune_result;
+int lb_batch_tune(lb_handle* batch, lb_tune_result* out);
+
+/* The graph of the last lb_step / lb_step_async call on a batch: its number
+ * of steps (all run by that one graph launch) and of kernel nodes. */
+int lb_batch_last_graph(const lb_handle* batch, int32_t* steps, int64_t* kernel_nodes);
 
 /* Message of the last failed call on h (or of the last failed lb_create or
- * lb_batch_create when h is NULL); valid until the next call on the same
+ * lb_create_batch when h is NULL); valid until the next call on the same
  * handle. */
 const char* lb_last_error(const lb_handle* h);
 

@@ -87,6 +87,12 @@ def lib(plant: int = 0):
         L.orc_read_owner.argtypes = [P, ip]
         L.orc_num_threads.restype = C.c_int
         L.orc_num_threads.argtypes = []
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_pairs.argtypes = [P, C.c_int, C.c_double, C.c_double]
+        L.orc_pair_hertz.restype = C.c_double
+        L.orc_pair_hertz.argtypes = [P, C.c_int, C.c_int, dp, dp, dp]
+        L.orc_pair_lub.argtypes = [P, C.c_int, C.c_int, dp]
+        L.orc_set_particle_pose.argtypes = [P, C.c_int, dp, dp]
         _libs[plant] = L
     return L
 
@@ -108,6 +114,11 @@ def _f64(a, n=None):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the checker's node loops (timing only; results do not depend on it)."""
+    lib().orc_set_threads(int(n))
 
 
 def lattice():
@@ -218,6 +229,24 @@ class Oracle:
 
     def set_particle_motion(self, k, V=None, L=None, W=None):
         self._L.orc_set_particle_motion(self._h, int(k), _d(_f64(V, 3)), _d(_f64(L, 3)), _d(_f64(W, 3)))
+
+    def set_pairs(self, on=True, K_H=100.0, delta_c=2.0 / 3.0):
+        """Particle-particle interactions (Hertz / Berne-Pechukas and lubrication)."""
+        self._L.orc_set_pairs(self._h, 1 if on else 0, float(K_H), float(delta_c))
+
+    def pair_hertz(self, i, j):
+        """(energy, force on i, torque on i, torque on j) of the Hertz pair term."""
+        F, Ti, Tj = np.zeros(3), np.zeros(3), np.zeros(3)
+        e = self._L.orc_pair_hertz(self._h, int(i), int(j), _d(F), _d(Ti), _d(Tj))
+        return e, F, Ti, Tj
+
+    def pair_lub(self, i, j):
+        F = np.zeros(3)
+        self._L.orc_pair_lub(self._h, int(i), int(j), _d(F))
+        return F
+
+    def set_particle_pose(self, k, X=None, q=None):
+        self._L.orc_set_particle_pose(self._h, int(k), _d(_f64(X, 3)), _d(_f64(q, 4)))
 
     def set_particle_accum(self, k, F, T):
         self._L.orc_set_particle_accum(self._h, int(k), _d(_f64(F, 3)), _d(_f64(T, 3)))

@@ -102,6 +102,7 @@ typedef struct {
     double F[3], T[3];          /* link force / torque of the current step */
     double J[3], H[3];          /* pending kill/fill impulses */
     double lastF[3], lastT[3];  /* totals applied in the last body update */
+    double PF[3], PT[3];        /* particle-particle force / torque of the last body update */
 } particle;
 
 typedef struct {
@@ -126,6 +127,8 @@ typedef struct {
     double kill_mass, fill_mass; /* last step */
     int inited;
     int any_wall;          /* a static wall node exists */
+    int pairs;             /* particle-particle interactions on (Eqs. (6)-(9)) */
+    double K_H, delta_c;   /* Hertz constant, lubrication cut-off */
 } orc_t;
 
 /* ---------------------------------------------------------------- helpers */
@@ -644,20 +647,177 @@ void orc_stage_stream(orc_t *s) {
     }
 }
 
+/* ---------------------------------------------------------------- pairs */
+/* Particle-particle interactions (Sec. 2, Eqs. (6)-(9)); off unless
+ * orc_set_pairs turns them on.
+ *
+ * Direct repulsion: the Hertz potential of two equal spheres,
+ * K_H (2R - r)^{5/2} for r <= 2R (Eq. (6)), written as eps phi~(r / sigma) with
+ * sigma = 2R, eps = K_H sigma^{5/2}, phi~(x) = (1 - x)^{5/2} for x <= 1 and 0
+ * beyond, and extended to ellipsoids after Berne and Pechukas (Eqs. (7)-(8)):
+ *   eps(o_i, o_j)      = eps_bar / sqrt(1 - chi^2 (o_i.o_j)^2)
+ *   sigma(o_i, o_j, r) = sigma_bar / sqrt(1 - chi/2 [(r.o_i + r.o_j)^2 / (1 + chi o_i.o_j)
+ *                                                   + (r.o_i - r.o_j)^2 / (1 - chi o_i.o_j)])
+ * with sigma_bar = 2 R_o, eps_bar = K_H sigma_bar^{5/2}, chi = (R_p^2 - R_o^2) /
+ * (R_p^2 + R_o^2), o the body axis and r the unit centre-to-centre vector
+ * (reading R36: for two particles of different shape, R_p and R_o are the
+ * means of the pair's). Force F_i = -d phi / d X_i, torque T_i = -o_i x
+ * d phi / d o_i.
+ *
+ * Lubrication (Eq. (9)): for a gap h = r - sigma(o_i, o_j, r) below Delta_c,
+ * F_i = -(3 pi mu R^2 / 2) r (r.(V_i - V_j)) (1/h - 1/Delta_c) on i and -F_i on
+ * j, with R = sigma / 2 and mu = (rho_A + rho_B) (tau - 1/2) / 3 from the
+ * initial mean densities; the force opposes the normal relative motion
+ * (reading R37) and the gap is taken no smaller than Delta_c / 4 (reading R38). */
+static void body_axis(const particle *p, double o[3]) {
+    double R[3][3];
+    qrot(p->q, R);
+    for (int d = 0; d < 3; d++) o[d] = R[d][2];
+}
+
+/* Potential, force on i and torques on i and j of pair (i, j), r = X_i - X_j
+ * (minimum image). Returns the Hertz energy. */
+static double pair_hertz(const orc_t *s, const particle *pi, const particle *pj, const double r[3],
+                         double Fi[3], double Ti[3], double Tj[3]) {
+    for (int d = 0; d < 3; d++) Fi[d] = Ti[d] = Tj[d] = 0.0;
+    double rp = 0.5 * (pi->Rpar + pj->Rpar), ro = 0.5 * (pi->Rperp + pj->Rperp);
+    double chi = (rp * rp - ro * ro) / (rp * rp + ro * ro);
+    double sbar = 2.0 * ro, ebar = s->K_H * pow(sbar, 2.5);
+    double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    double u[3] = {r[0] / rn, r[1] / rn, r[2] / rn};
+    double oi[3], oj[3];
+    body_axis(pi, oi);
+    body_axis(pj, oj);
+    double a = u[0] * oi[0] + u[1] * oi[1] + u[2] * oi[2];
+    double b = u[0] * oj[0] + u[1] * oj[1] + u[2] * oj[2];
+    double c = oi[0] * oj[0] + oi[1] * oj[1] + oi[2] * oj[2];
+    double G = (a + b) * (a + b) / (1.0 + chi * c) + (a - b) * (a - b) / (1.0 - chi * c);
+    double sig = sbar / sqrt(1.0 - 0.5 * chi * G);
+    double eps = ebar / sqrt(1.0 - chi * chi * c * c);
+    double x = rn / sig;
+    if (x >= 1.0) return 0.0;
+    double ph = pow(1.0 - x, 2.5);            /* phi~ */
+    double dph = -2.5 * eps * pow(1.0 - x, 1.5); /* d phi / d x */
+    double sG = 0.25 * chi * sig * sig * sig / (sbar * sbar); /* d sigma / d G */
+    double Ga = 2.0 * (a + b) / (1.0 + chi * c) + 2.0 * (a - b) / (1.0 - chi * c);
+    double Gb = 2.0 * (a + b) / (1.0 + chi * c) - 2.0 * (a - b) / (1.0 - chi * c);
+    double Gc = -chi * (a + b) * (a + b) / ((1.0 + chi * c) * (1.0 + chi * c)) +
+                chi * (a - b) * (a - b) / ((1.0 - chi * c) * (1.0 - chi * c));
+    double ec = ebar * chi * chi * c / pow(1.0 - chi * chi * c * c, 1.5); /* d eps / d c */
+    /* d phi / d r_vec: x = rn / sigma(a, b), a = u.o_i, da/dr = (o_i - a u) / rn */
+    double gr[3];
+    for (int d = 0; d < 3; d++)
+        gr[d] = dph * (u[d] / sig - (sG / (sig * sig)) * (Ga * (oi[d] - a * u[d]) + Gb * (oj[d] - b * u[d])));
+    for (int d = 0; d < 3; d++) Fi[d] = -gr[d];
+    /* d phi / d o_i and d phi / d o_j */
+    double k = dph * (-rn / (sig * sig)) * sG; /* d phi / d G */
+    double go_i[3], go_j[3];
+    for (int d = 0; d < 3; d++) {
+        go_i[d] = (ec * ph + k * Gc) * oj[d] + k * Ga * u[d];
+        go_j[d] = (ec * ph + k * Gc) * oi[d] + k * Gb * u[d];
+    }
+    Ti[0] = -(oi[1] * go_i[2] - oi[2] * go_i[1]);
+    Ti[1] = -(oi[2] * go_i[0] - oi[0] * go_i[2]);
+    Ti[2] = -(oi[0] * go_i[1] - oi[1] * go_i[0]);
+    Tj[0] = -(oj[1] * go_j[2] - oj[2] * go_j[1]);
+    Tj[1] = -(oj[2] * go_j[0] - oj[0] * go_j[2]);
+    Tj[2] = -(oj[0] * go_j[1] - oj[1] * go_j[0]);
+    return eps * ph;
+}
+
+/* Lubrication force on i of pair (i, j), r = X_i - X_j (minimum image). */
+static void pair_lub(const orc_t *s, const particle *pi, const particle *pj, const double r[3], double Fi[3]) {
+    for (int d = 0; d < 3; d++) Fi[d] = 0.0;
+    double rp = 0.5 * (pi->Rpar + pj->Rpar), ro = 0.5 * (pi->Rperp + pj->Rperp);
+    double chi = (rp * rp - ro * ro) / (rp * rp + ro * ro);
+    double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    double u[3] = {r[0] / rn, r[1] / rn, r[2] / rn};
+    double oi[3], oj[3];
+    body_axis(pi, oi);
+    body_axis(pj, oj);
+    double a = u[0] * oi[0] + u[1] * oi[1] + u[2] * oi[2];
+    double b = u[0] * oj[0] + u[1] * oj[1] + u[2] * oj[2];
+    double c = oi[0] * oj[0] + oi[1] * oj[1] + oi[2] * oj[2];
+    double G = (a + b) * (a + b) / (1.0 + chi * c) + (a - b) * (a - b) / (1.0 - chi * c);
+    double sig = 2.0 * ro / sqrt(1.0 - 0.5 * chi * G);
+    double h = rn - sig;
+    if (!(h < s->delta_c)) return;
+    if (h < 0.25 * s->delta_c) h = 0.25 * s->delta_c;
+    double mu = (s->rho_mean0[0] + s->rho_mean0[1]) * (s->tau - 0.5) / 3.0;
+    double R = 0.5 * sig;
+    double un = u[0] * (pi->V[0] - pj->V[0]) + u[1] * (pi->V[1] - pj->V[1]) + u[2] * (pi->V[2] - pj->V[2]);
+    double mag = -1.5 * M_PI * mu * R * R * un * (1.0 / h - 1.0 / s->delta_c);
+    for (int d = 0; d < 3; d++) Fi[d] = mag * u[d];
+}
+
+/* Particle-particle forces and torques of every particle from the current
+ * state, all pairs i < j in index order (serial, fixed order). */
+static void stage_pairs(orc_t *s) {
+    for (int k = 0; k < s->np; k++)
+        for (int d = 0; d < 3; d++) s->P[k].PF[d] = s->P[k].PT[d] = 0.0;
+    if (!s->pairs) return;
+    for (int i = 0; i < s->np; i++)
+        for (int j = i + 1; j < s->np; j++) {
+            particle *pi = &s->P[i], *pj = &s->P[j];
+            double r[3] = {minimg(pi->X[0] - pj->X[0], s->nx), minimg(pi->X[1] - pj->X[1], s->ny),
+                           minimg(pi->X[2] - pj->X[2], s->nz)};
+            double Fi[3], Ti[3], Tj[3], Fl[3];
+            pair_hertz(s, pi, pj, r, Fi, Ti, Tj);
+            pair_lub(s, pi, pj, r, Fl);
+            for (int d = 0; d < 3; d++) {
+                pi->PF[d] += Fi[d] + Fl[d];
+                pj->PF[d] -= Fi[d] + Fl[d];
+                pi->PT[d] += Ti[d];
+                pj->PT[d] += Tj[d];
+            }
+        }
+}
+
+void orc_set_pairs(orc_t *s, int on, double K_H, double delta_c) {
+    s->pairs = on;
+    s->K_H = K_H;
+    s->delta_c = delta_c;
+}
+
+/* Test hooks: Hertz energy, force on i and torques of pair (i, j); the
+ * lubrication force on i. */
+double orc_pair_hertz(const orc_t *s, int i, int j, double Fi[3], double Ti[3], double Tj[3]) {
+    const particle *pi = &s->P[i], *pj = &s->P[j];
+    double r[3] = {minimg(pi->X[0] - pj->X[0], s->nx), minimg(pi->X[1] - pj->X[1], s->ny),
+                   minimg(pi->X[2] - pj->X[2], s->nz)};
+    return pair_hertz(s, pi, pj, r, Fi, Ti, Tj);
+}
+void orc_pair_lub(const orc_t *s, int i, int j, double Fi[3]) {
+    const particle *pi = &s->P[i], *pj = &s->P[j];
+    double r[3] = {minimg(pi->X[0] - pj->X[0], s->nx), minimg(pi->X[1] - pj->X[1], s->ny),
+                   minimg(pi->X[2] - pj->X[2], s->nz)};
+    pair_lub(s, pi, pj, r, Fi);
+}
+/* Set a particle's centre and orientation (test use; no raster change). */
+void orc_set_particle_pose(orc_t *s, int k, const double X[3], const double q[4]) {
+    particle *p = &s->P[k];
+    for (int d = 0; d < 3; d++) if (X) p->X[d] = X[d];
+    if (q) {
+        for (int d = 0; d < 4; d++) p->q[d] = q[d];
+        qnormalize(p->q);
+    }
+}
+
 /* ---------------------------------------------------------------- S7 */
 /* Newton-Euler update with dt = 1 (Sec. 2: the particles obey Newton's
  * equations, integrated as in molecular dynamics; integrator R18):
- *   F = F_links + J, T = T_links + H, J = H = 0
+ *   F = F_links + J + F_pairs, T = T_links + H + T_pairs, J = H = 0
  *   V += F / M, X = wrap(X + V), L += T
  *   W = R(q) I_b^-1 R(q)^T L  (old q)
  *   q = normalize([cos(|W|/2), sin(|W|/2) W/|W|] (x) q)                     */
 void orc_stage_bodies(orc_t *s) {
+    stage_pairs(s);
     for (int k = 0; k < s->np; k++) {
         particle *p = &s->P[k];
         double F[3], T[3];
         for (int d = 0; d < 3; d++) {
-            F[d] = p->F[d] + p->J[d];
-            T[d] = p->T[d] + p->H[d];
+            F[d] = p->F[d] + p->J[d] + p->PF[d];
+            T[d] = p->T[d] + p->H[d] + p->PT[d];
             p->J[d] = p->H[d] = 0.0;
             p->lastF[d] = F[d];
             p->lastT[d] = T[d];
@@ -963,6 +1123,16 @@ void orc_feq(double rho, const double u[3], double out[NQ]) { feq(rho, u, out); 
 
 /* Owner map of a set of particles alone (test use: raster checks). */
 void orc_read_owner(const orc_t *s, int *owner) { memcpy(owner, s->owner, sizeof(int) * (size_t)s->N); }
+
+/* Threads the node loops use from now on (timing of the checker only; the
+ * results do not depend on it). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
 
 /* Threads the node loops use (1 without OpenMP). */
 int orc_num_threads(void) {

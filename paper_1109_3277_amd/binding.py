@@ -18,10 +18,11 @@ LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_EUNSTABLE, LB_ESTATE, LB_EGEOM = 0, -1,
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp16_dev": 2, "bf16_dev": 3}
 EXPORTED = [
     "lb_workspace_bytes", "lb_create", "lb_destroy", "lb_init_fields", "lb_add_ellipsoids", "lb_step",
-    "lb_step_async", "lb_read_fields", "lb_num_particles", "lb_read_particles", "lb_stats",
-    "lb_set_body_accel", "lb_set_static_solid", "lb_state_bytes", "lb_save_state", "lb_load_state", "lb_last_error",
-    "lb_profile_enable", "lb_profile_read", "lb_probe_copy", "lb_batch_workspace_bytes", "lb_batch_create",
-    "lb_batch_size", "lb_batch_system", "lb_batch_tune",
+    "lb_step_async", "lb_read_fields", "lb_read_fields_dev", "lb_num_particles", "lb_read_particles", "lb_stats",
+    "lb_set_body_accel", "lb_set_static_solid", "lb_set_pair_interactions", "lb_state_bytes", "lb_save_state", "lb_load_state", "lb_last_error",
+    "lb_profile_enable", "lb_profile_read", "lb_batch_workspace_bytes", "lb_create_batch", "lb_init_fields_sys",
+    "lb_add_ellipsoids_sys", "lb_read_fields_sys", "lb_read_particles_sys", "lb_stats_sys", "lb_batch_size",
+    "lb_batch_system", "lb_batch_tune", "lb_batch_last_graph",
 ]
 PHASES = ["density", "shell", "fused", "forces", "bodies", "raster", "killfill"]
 
@@ -36,6 +37,14 @@ class lb_params(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("tau", C.c_double),
                 ("g_br", C.c_double), ("psi_kind", C.c_int32), ("precision", C.c_int32),
                 ("max_particles", C.c_int32), ("max_radius", C.c_double)]
+
+
+TUNE_CANDIDATES = 3
+
+
+class lb_tune_result(C.Structure):
+    _fields_ = [("tile_width", C.c_int32), ("cached", C.c_int32), ("tile_widths", C.c_int32 * TUNE_CANDIDATES),
+                ("ms", C.c_double * TUNE_CANDIDATES)]
 
 
 _lib = None
@@ -61,11 +70,13 @@ def load_library():
     L.lb_step.argtypes = [vp, C.c_int32]
     L.lb_step_async.argtypes = [vp, C.c_int32]
     L.lb_read_fields.argtypes = [vp, dp, dp, dp, ip]
+    L.lb_read_fields_dev.argtypes = [vp, vp, vp, vp, vp]
     L.lb_num_particles.argtypes = [vp]
     L.lb_read_particles.argtypes = [vp, dp, dp, dp, dp, dp, dp]
     L.lb_stats.argtypes = [vp, dp]
     L.lb_set_body_accel.argtypes = [vp, dp]
     L.lb_set_static_solid.argtypes = [vp, C.POINTER(C.c_uint8), dp]
+    L.lb_set_pair_interactions.argtypes = [vp, C.c_int, C.c_double, C.c_double]
     L.lb_state_bytes.restype = C.c_size_t
     L.lb_state_bytes.argtypes = [vp]
     L.lb_save_state.argtypes = [vp, vp, C.c_size_t]
@@ -74,13 +85,18 @@ def load_library():
     L.lb_last_error.argtypes = [vp]
     L.lb_profile_enable.argtypes = [vp, C.c_int]
     L.lb_profile_read.argtypes = [vp, dp, C.POINTER(C.c_int64)]
-    L.lb_probe_copy.argtypes = [vp, vp, C.c_size_t, vp]
     L.lb_batch_workspace_bytes.restype = C.c_size_t
     L.lb_batch_workspace_bytes.argtypes = [C.c_int32, pp]
-    L.lb_batch_create.argtypes = [C.c_int32, pp, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.lb_create_batch.argtypes = [C.c_int32, pp, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.lb_init_fields_sys.argtypes = [vp, C.c_int32, dp, dp, dp]
+    L.lb_add_ellipsoids_sys.argtypes = [vp, C.c_int32, C.c_int32, dp, dp, dp, dp, dp]
+    L.lb_read_fields_sys.argtypes = [vp, C.c_int32, dp, dp, dp, ip]
+    L.lb_read_particles_sys.argtypes = [vp, C.c_int32, dp, dp, dp, dp, dp, dp]
+    L.lb_stats_sys.argtypes = [vp, C.c_int32, dp]
     L.lb_batch_size.argtypes = [vp]
     L.lb_batch_system.argtypes = [vp, C.c_int32, C.POINTER(vp)]
-    L.lb_batch_tune.argtypes = [vp, ip]
+    L.lb_batch_tune.argtypes = [vp, C.POINTER(lb_tune_result)]
+    L.lb_batch_last_graph.argtypes = [vp, ip, C.POINTER(C.c_int64)]
     _lib = L
     return L
 
@@ -147,9 +163,12 @@ class Lattice:
             raise LBError(rc, load_library().lb_last_error(self._h).decode())
 
     def close(self):
+        """Destroy the handle and drop the workspace tensor (the memory goes
+        back to torch's allocator)."""
         if getattr(self, "_h", None) and not getattr(self, "_borrowed", False):
             load_library().lb_destroy(self._h)
         self._h = None
+        self._ws = None
 
     def __del__(self):
         try:
@@ -185,6 +204,10 @@ class Lattice:
         aa = _f64(a, 3)
         self._check(load_library().lb_set_body_accel(self._h, _dp(aa)))
 
+    def set_pair_interactions(self, on=True, K_H=100.0, delta_c=2.0 / 3.0):
+        """Hertz / Berne-Pechukas repulsion and lubrication between particles."""
+        self._check(load_library().lb_set_pair_interactions(self._h, 1 if on else 0, float(K_H), float(delta_c)))
+
     def set_static_solid(self, mask, wall_u=None):
         """Wall nodes (mask, N entries, x fastest) with one velocity wall_u
         (3 values, None for resting walls); before init_fields."""
@@ -201,6 +224,20 @@ class Lattice:
         self._check(load_library().lb_read_fields(self._h, _dp(ra), _dp(rb), _dp(u),
                                                   own.ctypes.data_as(C.POINTER(C.c_int32))))
         return ra, rb, u.reshape(-1, 3), own
+
+    def read_fields_dev(self, rho_a=None, rho_b=None, u=None, owner=None):
+        """Fields into torch device tensors (float64 N, N, N x 3; int32 N; any
+        may be None), ordered on the handle's stream."""
+        def ptr(t, dtype, n):
+            if t is None:
+                return None
+            import torch
+            assert t.is_cuda and t.dtype == dtype and t.numel() == n and t.is_contiguous()
+            return C.c_void_p(t.data_ptr())
+        import torch
+        self._check(load_library().lb_read_fields_dev(
+            self._h, ptr(rho_a, torch.float64, self.N), ptr(rho_b, torch.float64, self.N),
+            ptr(u, torch.float64, 3 * self.N), ptr(owner, torch.int32, self.N)))
 
     def num_particles(self) -> int:
         return int(load_library().lb_num_particles(self._h))
@@ -260,7 +297,7 @@ class Batch:
         self._ws_ptr = (self._ws.data_ptr() + 255) // 256 * 256
         self.stream = torch.cuda.current_stream(self._ws.device)
         h = C.c_void_p()
-        rc = L.lb_batch_create(len(plist), arr, C.c_void_p(self._ws_ptr), nbytes, C.c_void_p(self.stream.cuda_stream),
+        rc = L.lb_create_batch(len(plist), arr, C.c_void_p(self._ws_ptr), nbytes, C.c_void_p(self.stream.cuda_stream),
                                C.byref(h))
         if rc != 0:
             raise LBError(rc, L.lb_last_error(None).decode())
@@ -288,9 +325,21 @@ class Batch:
         self._check(load_library().lb_step_async(self._h, int(n)))
 
     def tune(self) -> int:
-        bx = C.c_int32(0)
-        self._check(load_library().lb_batch_tune(self._h, C.byref(bx)))
-        return int(bx.value)
+        """Autotune the fused tile shape; returns the chosen tile width."""
+        return self.tune_report()["tile_width"]
+
+    def tune_report(self) -> dict:
+        r = lb_tune_result()
+        self._check(load_library().lb_batch_tune(self._h, C.byref(r)))
+        cand = {f"{w}x{256 // w}": round(float(m), 5) for w, m in zip(r.tile_widths, r.ms)}
+        return {"tile_width": int(r.tile_width), "tile": f"{r.tile_width}x{256 // r.tile_width}",
+                "cached": bool(r.cached), "candidates": cand, "best_ms": float(min(r.ms))}
+
+    def last_graph(self):
+        """(steps, kernel nodes) of the graph the last step call launched."""
+        st, nodes = C.c_int32(0), C.c_int64(0)
+        self._check(load_library().lb_batch_last_graph(self._h, C.byref(st), C.byref(nodes)))
+        return int(st.value), int(nodes.value)
 
     def close(self):
         for s in getattr(self, "systems", []):
@@ -298,22 +347,10 @@ class Batch:
         if getattr(self, "_h", None):
             load_library().lb_destroy(self._h)
             self._h = None
+        self._ws = None
 
     def __del__(self):
         try:
             self.close()
         except Exception:
             pass
-
-
-def probe_copy(dst, src, stream=None):
-    """Copy torch tensor src into dst (same byte size, multiple of 16) with the
-    library's plain streaming kernel (traffic-counter calibration)."""
-    import torch
-
-    nbytes = src.numel() * src.element_size()
-    assert dst.numel() * dst.element_size() == nbytes and nbytes % 16 == 0
-    st = (stream or torch.cuda.current_stream()).cuda_stream
-    rc = load_library().lb_probe_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes, C.c_void_p(st))
-    if rc != 0:
-        raise LBError(rc, load_library().lb_last_error(None).decode())

@@ -3,7 +3,9 @@
     python -m paper_1109_3277_amd.build
 
 Every source under csrc/ is compiled for gfx950 only; the shared library is
-written next to this file so that it travels with the source tree.
+written next to this file so that it travels with the source tree. The
+counter-calibration copy (csrc/probe/) becomes a separate liblbe_probe.so,
+loaded only by the profiling driver.
 """
 from __future__ import annotations
 
@@ -16,7 +18,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbe.so")
-SOURCES = ["lbe_fluid.hip", "lbe_particles.hip", "lbe_runtime.hip", "lbe_batch.hip"]
+PROBE_LIB = os.path.join(HERE, "liblbe_probe.so")
+PROBE_SRC = os.path.join(CSRC, "probe", "lbe_probe.hip")
+SOURCES = ["lbe_fluid.hip", "lbe_particles.hip", "lbe_pairs.hip", "lbe_runtime.hip", "lbe_batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -29,7 +33,7 @@ FLAGS = [
 
 
 def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    obj = os.path.join(BUILD, os.path.splitext(os.path.basename(src))[0] + ".o")
     cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -37,18 +41,23 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+def _link(objs, out: str):
+    tmp = out + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=min(5, len(SOURCES) + 1)) as ex:
+        objs = list(ex.map(_compile, SOURCES + [os.path.join("probe", "lbe_probe.hip")]))
+    _link(objs[:-1], LIB)
+    _link(objs[-1:], PROBE_LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", PROBE_LIB)
     return LIB
 
 

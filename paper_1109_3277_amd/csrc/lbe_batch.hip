@@ -1,18 +1,25 @@
 // Batches of independent periodic systems advanced together: one launch per
 // phase covers every system (work items name the system and its local block),
-// and the step sequence runs as a captured HIP graph on the batch's own
-// stream. Each system keeps its own buffers, parameters and particles, and
+// and a call's whole step sequence runs as one captured HIP graph, launched on
+// the caller's stream. Each system keeps its own buffers, parameters and particles, and
 // its arithmetic is exactly that of a single-system run: a batch changes the
 // launch shape, never the result.
 #include <math.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "lbe_internal.h"
 
 namespace lbe {
+
+// Fused-kernel tile shapes the batch tuner tries: BX x (256 / BX) nodes of one
+// xy-plane per 256-thread block (wide tiles coalesce better, square ones
+// stage a smaller halo).
+constexpr int kTileWidths[LB_TUNE_CANDIDATES] = {64, 32, 16};
 
 struct BatchState {
     std::vector<lb_handle*> subs;
@@ -28,10 +35,13 @@ struct BatchState {
     int parity = 0;   // index of the current population and owner copies, shared by all systems
     bool dens_ready = false;  // every system's Psi / rho match its current populations
     bool walls = false;       // some system has wall nodes
-    hipStream_t own = nullptr;
-    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipStream_t cap = nullptr;  // records graphs only; nothing is launched on it
+    // the graph of the last step count, per starting parity
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
+    int graph_steps[2] = {0, 0};
+    int last_steps = 0;          // steps of the graph launched last
+    int64_t last_nodes = 0;      // its kernel nodes
 };
 
 namespace {
@@ -47,7 +57,7 @@ void item_capacity(const lb_params& p, size_t cap[BI_COUNT]) {
     const size_t N = (size_t)p.nx * p.ny * p.nz;
     int tx, ty;
     size_t tiles = 0;
-    for (int bx : {64, 32}) {
+    for (int bx : kTileWidths) {
         tiles_for(p, bx, tx, ty);
         tiles = std::max(tiles, (size_t)tx * ty * p.nz);
     }
@@ -104,14 +114,42 @@ bool batch_layout(int nsys, const lb_params* prm, BatchLayout& L, std::string* w
     return true;
 }
 
-void drop_graphs(BatchState* B) {
-    for (int k = 0; k < 2; k++) {
-        if (B->exec[k]) (void)hipGraphExecDestroy(B->exec[k]);
-        if (B->graph[k]) (void)hipGraphDestroy(B->graph[k]);
-        B->exec[k] = nullptr;
-        B->graph[k] = nullptr;
-    }
+void drop_graph(BatchState* B, int k) {
+    if (B->exec[k]) (void)hipGraphExecDestroy(B->exec[k]);
+    if (B->graph[k]) (void)hipGraphDestroy(B->graph[k]);
+    B->exec[k] = nullptr;
+    B->graph[k] = nullptr;
+    B->graph_steps[k] = 0;
 }
+void drop_graphs(BatchState* B) {
+    for (int k = 0; k < 2; k++) drop_graph(B, k);
+}
+
+}  // namespace
+
+SysDev sys_dev(const lb_handle* q) {
+    SysDev d{};
+    d.box = q->box;
+    d.f[0] = q->b.f[0];
+    d.f[1] = q->b.f[1];
+    d.psi = q->b.psi;
+    d.rho = q->b.rho;
+    d.owner[0] = q->b.owner[0];
+    d.owner[1] = q->b.owner[1];
+    d.part = q->b.part;
+    d.bmask[0] = q->b.bmask[0];
+    d.bmask[1] = q->b.bmask[1];
+    d.rec = q->b.rec;
+    d.pfast = q->b.pfast;
+    d.kpart = q->b.kpart;
+    d.health = q->b.health;
+    d.counters = q->b.counters;
+    d.cap = q->cap;
+    d.np = q->np;
+    return d;
+}
+
+namespace {
 
 // Rebuild the device descriptors and work lists from the systems' state.
 int refresh(lb_handle* h) {
@@ -123,23 +161,8 @@ int refresh(lb_handle* h) {
     for (int s = 0; s < nsys; s++) {
         lb_handle* q = B->subs[s];
         SysDev& d = B->h_sys[s];
-        d.box = q->box;
+        d = sys_dev(q);
         B->walls = B->walls || q->box.walls != 0;
-        d.f[0] = q->b.f[0];
-        d.f[1] = q->b.f[1];
-        d.psi = q->b.psi;
-        d.rho = q->b.rho;
-        d.owner[0] = q->b.owner[0];
-        d.owner[1] = q->b.owner[1];
-        d.part = q->b.part;
-        d.bmask[0] = q->b.bmask[0];
-        d.bmask[1] = q->b.bmask[1];
-        d.rec = q->b.rec;
-        d.pfast = q->b.pfast;
-        d.kpart = q->b.kpart;
-        d.health = q->b.health;
-        d.cap = q->cap;
-        d.np = q->np;
         tiles_for(q->prm, B->bx, d.tiles_x, d.tiles_y);
         d.kext = kill_ext(q);
         const int nnode = (int)((q->box.N + 255) / 256);
@@ -185,14 +208,16 @@ hipError_t enqueue_batch_step(BatchState* B, hipStream_t st, int c) {
     return launch_batch_killfill(bl, prec, st, c, 1 - c);
 }
 
-// Graph of two steps starting at parity c (it ends at parity c again).
-int capture(lb_handle* h, int c) {
+// Graph of n steps starting at parity c (it ends at parity c when n is even),
+// recorded on the capture stream.
+int capture(lb_handle* h, int c, int n) {
     BatchState* B = h->batch;
-    LBE_HIP_OR_FAIL(h, hipStreamBeginCapture(B->own, hipStreamCaptureModeThreadLocal));
-    hipError_t e = enqueue_batch_step(B, B->own, c);
-    if (e == hipSuccess) e = enqueue_batch_step(B, B->own, 1 - c);
+    drop_graph(B, c);
+    LBE_HIP_OR_FAIL(h, hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < n && e == hipSuccess; k++) e = enqueue_batch_step(B, B->cap, (c + k) & 1);
     hipGraph_t g = nullptr;
-    const hipError_t e2 = hipStreamEndCapture(B->own, &g);
+    const hipError_t e2 = hipStreamEndCapture(B->cap, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
         return fail(h, LB_EHIP, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
@@ -205,6 +230,7 @@ int capture(lb_handle* h, int c) {
     }
     B->graph[c] = g;
     B->exec[c] = x;
+    B->graph_steps[c] = n;
     return LB_OK;
 }
 
@@ -219,35 +245,43 @@ int check_ready(lb_handle* h) {
 
 }  // namespace
 
+// n steps of every system as one graph launch on the caller's stream. The
+// graph of the last step count is kept per starting parity and replayed
+// while the count and the systems stay the same.
+int batch_sys(lb_handle* h, const SysDev** d_sys, int* nsys, int* parity) {
+    BatchState* B = h->batch;
+    const int rc = check_ready(h);
+    if (rc != LB_OK) return rc;
+    *d_sys = B->d_sys;
+    *nsys = (int)B->subs.size();
+    *parity = B->parity;
+    return LB_OK;
+}
+
 int batch_step_async(lb_handle* h, int nsteps) {
     BatchState* B = h->batch;
     int rc = check_ready(h);
     if (rc != LB_OK) return rc;
     if (nsteps == 0) return LB_OK;
-    LBE_HIP_OR_FAIL(h, hipEventRecord(B->ev_in, h->stream));
-    LBE_HIP_OR_FAIL(h, hipStreamWaitEvent(B->own, B->ev_in, 0));
     if (!B->dens_ready) {
-        LBE_HIP_OR_FAIL(h, launch_batch_density(B->bl, B->precision, B->own, B->parity, B->parity, -1));
+        LBE_HIP_OR_FAIL(h, launch_batch_density(B->bl, B->precision, h->stream, B->parity, B->parity, -1));
         B->dens_ready = true;
     }
-    const int pairs = nsteps / 2;
-    if (pairs > 0) {
-        if (!B->exec[B->parity]) {
-            rc = capture(h, B->parity);
-            if (rc != LB_OK) return rc;
-        }
-        for (int k = 0; k < pairs; k++) LBE_HIP_OR_FAIL(h, hipGraphLaunch(B->exec[B->parity], B->own));
+    const int c = B->parity;
+    if (!B->exec[c] || B->graph_steps[c] != nsteps) {
+        rc = capture(h, c, nsteps);
+        if (rc != LB_OK) return rc;
     }
-    if (nsteps & 1) {
-        LBE_HIP_OR_FAIL(h, enqueue_batch_step(B, B->own, B->parity));
-        B->parity = 1 - B->parity;
-    }
+    LBE_HIP_OR_FAIL(h, hipGraphLaunch(B->exec[c], h->stream));
+    size_t nodes = 0;
+    LBE_HIP_OR_FAIL(h, hipGraphGetNodes(B->graph[c], nullptr, &nodes));
+    B->last_steps = nsteps;
+    B->last_nodes = (int64_t)nodes;
+    B->parity = (c + nsteps) & 1;
     for (lb_handle* q : B->subs) {
         q->cur = q->ocur = B->parity;
         q->dens_ready = true;
     }
-    LBE_HIP_OR_FAIL(h, hipEventRecord(B->ev_out, B->own));
-    LBE_HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, B->ev_out, 0));
     return LB_OK;
 }
 
@@ -270,11 +304,9 @@ int batch_health(lb_handle* h) {
 void batch_destroy(lb_handle* h) {
     BatchState* B = h->batch;
     if (!B) return;
-    if (B->own) (void)hipStreamSynchronize(B->own);
+    (void)hipStreamSynchronize(h->stream);
     drop_graphs(B);
-    if (B->ev_in) (void)hipEventDestroy(B->ev_in);
-    if (B->ev_out) (void)hipEventDestroy(B->ev_out);
-    if (B->own) (void)hipStreamDestroy(B->own);
+    if (B->cap) (void)hipStreamDestroy(B->cap);
     for (lb_handle* q : B->subs) {
         for (hipEvent_t e : q->ev_pool) (void)hipEventDestroy(e);
         delete q;
@@ -303,7 +335,7 @@ size_t lb_batch_workspace_bytes(int32_t nsys, const lb_params* per_sys) {
     return L.total;
 }
 
-int lb_batch_create(int32_t nsys, const lb_params* per_sys, void* dev_ws, size_t ws_bytes, void* hip_stream,
+int lb_create_batch(int32_t nsys, const lb_params* per_sys, void* dev_ws, size_t ws_bytes, void* hip_stream,
                     lb_handle** out) {
     if (!out) return fail(nullptr, LB_EINVAL, "out is NULL");
     *out = nullptr;
@@ -346,11 +378,10 @@ int lb_batch_create(int32_t nsys, const lb_params* per_sys, void* dev_ws, size_t
         }
         B->subs.push_back(q);
     }
-    if (rc == LB_OK && hipStreamCreateWithFlags(&B->own, hipStreamNonBlocking) != hipSuccess)
-        rc = fail(nullptr, LB_EHIP, "stream creation failed");
-    if (rc == LB_OK && (hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming) != hipSuccess ||
-                        hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming) != hipSuccess))
-        rc = fail(nullptr, LB_EHIP, "event creation failed");
+    // a stream to record graphs on (the caller's may be the null stream,
+    // which cannot be captured); default priority
+    if (rc == LB_OK && hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess)
+        rc = fail(nullptr, LB_EHIP, "capture stream creation failed");
     if (rc != LB_OK) {
         batch_destroy(h);
         delete h;
@@ -375,52 +406,153 @@ int lb_batch_system(lb_handle* h, int32_t sys, lb_handle** out) {
     return LB_OK;
 }
 
-int lb_batch_tune(lb_handle* h, int32_t* tile_width) {
+static lb_handle* sys_of(lb_handle* h, int32_t sys) {
+    if (!h || !h->batch || sys < 0 || sys >= (int32_t)h->batch->subs.size()) return nullptr;
+    return h->batch->subs[sys];
+}
+
+#define LBE_SYS_OR_FAIL(h, sys, q)                                                                  \
+    lb_handle* q = sys_of(h, sys);                                                                  \
+    if (!q) {                                                                                       \
+        if (h) (void)fail(h, LB_EINVAL, h->batch ? "system index out of range" : "not a batch handle"); \
+        return LB_EINVAL;                                                                           \
+    }
+
+int lb_init_fields_sys(lb_handle* h, int32_t sys, const double* rho_a, const double* rho_b, const double* u) {
+    LBE_SYS_OR_FAIL(h, sys, q);
+    return lb_init_fields(q, rho_a, rho_b, u);
+}
+
+int lb_add_ellipsoids_sys(lb_handle* h, int32_t sys, int32_t n, const double* radii, const double* pos,
+                          const double* quat, const double* delta_rho, const double* density) {
+    LBE_SYS_OR_FAIL(h, sys, q);
+    return lb_add_ellipsoids(q, n, radii, pos, quat, delta_rho, density);
+}
+
+int lb_read_fields_sys(lb_handle* h, int32_t sys, double* rho_a, double* rho_b, double* u, int32_t* owner) {
+    LBE_SYS_OR_FAIL(h, sys, q);
+    return lb_read_fields(q, rho_a, rho_b, u, owner);
+}
+
+int lb_read_particles_sys(lb_handle* h, int32_t sys, double* pos, double* quat, double* vel, double* omega,
+                          double* force, double* torque) {
+    LBE_SYS_OR_FAIL(h, sys, q);
+    return lb_read_particles(q, pos, quat, vel, omega, force, torque);
+}
+
+int lb_stats_sys(lb_handle* h, int32_t sys, double out[8]) {
+    LBE_SYS_OR_FAIL(h, sys, q);
+    return lb_stats(q, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Tuning results kept for the life of the process, keyed by the precision and
+// the shape of every system (box and whether it holds solids): a batch of the
+// same systems is not timed again.
+struct TuneEntry {
+    int bx;
+    double ms[LB_TUNE_CANDIDATES];
+};
+std::map<std::string, TuneEntry>& tune_cache() {
+    static std::map<std::string, TuneEntry> c;
+    return c;
+}
+std::mutex& tune_mutex() {
+    static std::mutex m;
+    return m;
+}
+std::string tune_key(const BatchState* B) {
+    std::string k = std::to_string(B->precision);
+    for (const lb_handle* q : B->subs)
+        k += ";" + std::to_string(q->box.nx) + "x" + std::to_string(q->box.ny) + "x" + std::to_string(q->box.nz) +
+             (q->has_solid ? "s" : "f");
+    return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lb_batch_last_graph(const lb_handle* h, int32_t* steps, int64_t* kernel_nodes) {
+    if (!h || !h->batch) return LB_EINVAL;
+    if (steps) *steps = h->batch->last_steps;
+    if (kernel_nodes) *kernel_nodes = h->batch->last_nodes;
+    return LB_OK;
+}
+
+int lb_batch_tune(lb_handle* h, lb_tune_result* out) {
     if (!h) return LB_EINVAL;
     if (!h->batch) return fail(h, LB_EINVAL, "not a batch handle");
     BatchState* B = h->batch;
     int rc = check_ready(h);
     if (rc != LB_OK) return rc;
-    // the fused launch only writes the next population copy and its masks,
-    // which the next step rewrites whole, and link records (cleared below):
-    // timing it leaves the state untouched
-    const int c = B->parity;
-    hipEvent_t e0, e1;
-    LBE_HIP_OR_FAIL(h, hipEventCreate(&e0));
-    LBE_HIP_OR_FAIL(h, hipEventCreate(&e1));
-    float best = 0.0f;
-    int best_bx = B->bx;
-    for (int bx : {64, 32}) {
-        B->bx = bx;
-        rc = refresh(h);
-        if (rc != LB_OK) break;
-        LBE_HIP_OR_FAIL(h, launch_batch_density(B->bl, B->precision, h->stream, c, c, -1));
-        LBE_HIP_OR_FAIL(h, launch_batch_shell(B->bl, B->precision, h->stream, c));
-        LBE_HIP_OR_FAIL(h, launch_batch_fused(B->bl, B->precision, h->stream, c, c));
-        LBE_HIP_OR_FAIL(h, hipEventRecord(e0, h->stream));
-        for (int k = 0; k < 3; k++) LBE_HIP_OR_FAIL(h, launch_batch_fused(B->bl, B->precision, h->stream, c, c));
-        LBE_HIP_OR_FAIL(h, hipEventRecord(e1, h->stream));
-        LBE_HIP_OR_FAIL(h, hipEventSynchronize(e1));
-        float ms = 0.0f;
-        LBE_HIP_OR_FAIL(h, hipEventElapsedTime(&ms, e0, e1));
-        if (best == 0.0f || ms < best) {
-            best = ms;
-            best_bx = bx;
+    const std::string key = tune_key(B);
+    TuneEntry te{};
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> lk(tune_mutex());
+        auto it = tune_cache().find(key);
+        if (it != tune_cache().end()) {
+            te = it->second;
+            cached = true;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (rc != LB_OK) return rc;
-    // the timed launches also wrote link records, which the force pass would
-    // otherwise have read and cleared: clear them
-    for (lb_handle* q : B->subs) {
-        const size_t rb = layout_of(&q->prm).rec;
-        if (rb) LBE_HIP_OR_FAIL(h, launch_fill_f64(h, q->b.rec, 0.0, (int64_t)(rb / sizeof(double))));
+    if (!cached) {
+        // the fused launch only writes the next population copy and its masks,
+        // which the next step rewrites whole, and link records (cleared
+        // below): timing it leaves the state untouched
+        const int c = B->parity;
+        hipEvent_t e0, e1;
+        LBE_HIP_OR_FAIL(h, hipEventCreate(&e0));
+        LBE_HIP_OR_FAIL(h, hipEventCreate(&e1));
+        float best = 0.0f;
+        te.bx = B->bx;
+        for (int k = 0; k < LB_TUNE_CANDIDATES && rc == LB_OK; k++) {
+            B->bx = kTileWidths[k];
+            rc = refresh(h);
+            if (rc != LB_OK) break;
+            LBE_HIP_OR_FAIL(h, launch_batch_density(B->bl, B->precision, h->stream, c, c, -1));
+            LBE_HIP_OR_FAIL(h, launch_batch_shell(B->bl, B->precision, h->stream, c));
+            LBE_HIP_OR_FAIL(h, launch_batch_fused(B->bl, B->precision, h->stream, c, c));
+            LBE_HIP_OR_FAIL(h, hipEventRecord(e0, h->stream));
+            constexpr int reps = 3;
+            for (int r = 0; r < reps; r++) LBE_HIP_OR_FAIL(h, launch_batch_fused(B->bl, B->precision, h->stream, c, c));
+            LBE_HIP_OR_FAIL(h, hipEventRecord(e1, h->stream));
+            LBE_HIP_OR_FAIL(h, hipEventSynchronize(e1));
+            float ms = 0.0f;
+            LBE_HIP_OR_FAIL(h, hipEventElapsedTime(&ms, e0, e1));
+            te.ms[k] = (double)ms / reps;
+            if (best == 0.0f || ms < best) {
+                best = ms;
+                te.bx = kTileWidths[k];
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc != LB_OK) return rc;
+        // the timed launches also wrote link records, which the force pass
+        // would otherwise have read and cleared: clear them
+        for (lb_handle* q : B->subs) {
+            const size_t rb = layout_of(&q->prm).rec;
+            if (rb) LBE_HIP_OR_FAIL(h, launch_fill_f64(h, q->b.rec, 0.0, (int64_t)(rb / sizeof(double))));
+        }
+        std::lock_guard<std::mutex> lk(tune_mutex());
+        tune_cache()[key] = te;
     }
-    B->bx = best_bx;
+    B->bx = te.bx;
     rc = refresh(h);
     if (rc != LB_OK) return rc;
-    if (tile_width) *tile_width = best_bx;
+    if (out) {
+        out->tile_width = te.bx;
+        out->cached = cached ? 1 : 0;
+        for (int k = 0; k < LB_TUNE_CANDIDATES; k++) {
+            out->tile_widths[k] = kTileWidths[k];
+            out->ms[k] = te.ms[k];
+        }
+    }
     return LB_OK;
 }
 

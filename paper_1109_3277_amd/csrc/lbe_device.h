@@ -48,48 +48,62 @@ enum PField : int {
     LFX, LFY, LFZ, LTX, LTY, LTZ,  // totals applied in the last body update
     OX, OY, OZ,                // centre before the last body update
     KMASS, FMASS,              // fluid mass killed / filled by this particle (cumulative)
+    PFX, PFY, PFZ, PTX, PTY, PTZ,  // particle-particle force / torque of the current step
     NPFIELD
 };
 
 // Population storage policies. S is the stored type, R the arithmetic type.
-// Deviation forms store f_i - w_i rho_ref^c. enc / dec convert one value
-// (dec(enc(v)) is what a later load of the stored value returns).
+// FP64 stores the population f_i itself. The other forms store the deviation
+// h_i = f_i - w_i rho_ref^c from the rest state of the component's initial
+// mean density, and the collision works on the h_i directly (the moments
+// follow from rho^c = rho_ref^c + sum_i h_i and j^c = sum_i h_i c_i, since the
+// w_i sum to one and sum_i w_i c_i = 0), so storage and arithmetic rounding
+// scale with the deviations, not with the populations.
+// raw(s) is the stored number as an R; mk(v) stores an R number.
 struct PolF64 {
     using S = double;
     using R = double;
     static constexpr bool dev = false;
-    __device__ static S enc(R v, R) { return v; }
-    __device__ static R dec(S s, R) { return s; }
-    __device__ static R ld(const S* p, R w) { return dec(*p, w); }
-    __device__ static void st(S* p, R v, R w) { *p = enc(v, w); }
+    __device__ static R raw(S s) { return s; }
+    __device__ static S mk(R v) { return v; }
 };
 struct PolF32 {
     using S = float;
     using R = float;
-    static constexpr bool dev = false;
-    __device__ static S enc(R v, R) { return v; }
-    __device__ static R dec(S s, R) { return s; }
-    __device__ static R ld(const S* p, R w) { return dec(*p, w); }
-    __device__ static void st(S* p, R v, R w) { *p = enc(v, w); }
+    static constexpr bool dev = true;
+    __device__ static R raw(S s) { return s; }
+    __device__ static S mk(R v) { return v; }
 };
 struct PolF16 {
     using S = __half;
     using R = float;
     static constexpr bool dev = true;
-    __device__ static S enc(R v, R wref) { return __float2half_rn(v - wref); }
-    __device__ static R dec(S s, R wref) { return __half2float(s) + wref; }
-    __device__ static R ld(const S* p, R w) { return dec(*p, w); }
-    __device__ static void st(S* p, R v, R w) { *p = enc(v, w); }
+    __device__ static R raw(S s) { return __half2float(s); }
+    __device__ static S mk(R v) { return __float2half_rn(v); }
 };
 struct PolBF16 {
     using S = __hip_bfloat16;
     using R = float;
     static constexpr bool dev = true;
-    __device__ static S enc(R v, R wref) { return __float2bfloat16(v - wref); }
-    __device__ static R dec(S s, R wref) { return __bfloat162float(s) + wref; }
-    __device__ static R ld(const S* p, R w) { return dec(*p, w); }
-    __device__ static void st(S* p, R v, R w) { *p = enc(v, w); }
+    __device__ static R raw(S s) { return __bfloat162float(s); }
+    __device__ static S mk(R v) { return __float2bfloat16(v); }
 };
+// Population f_i in double from a stored number (wref = w_i rho_ref^c).
+template <class P>
+__device__ inline double pop64(typename P::S s, double wref) {
+    return P::dev ? (double)P::raw(s) + wref : (double)P::raw(s);
+}
+// Stored number of population f_i given in double (the deviation is formed in
+// double, then rounded once).
+template <class P>
+__device__ inline typename P::S enc64(double f, double wref) {
+    return P::mk(typename P::R(P::dev ? f - wref : f));
+}
+// Stored number of an empty slot (f_i = 0), in the arithmetic type.
+template <class P>
+__device__ inline typename P::R empty_raw(typename P::R wref) {
+    return P::dev ? -wref : typename P::R(0);
+}
 
 // Everything a kernel needs to know about one periodic box.
 struct Box {
@@ -101,9 +115,13 @@ struct Box {
     int psi_kind;    // 0: Psi = rho, 1: Psi = 1 - exp(-rho)
     double ax, ay, az;  // body acceleration
     double rref[2];  // deviation reference density per component
+    double eref[2];  // exp(-rref): Psi(rref) = 1 - eref for the exponential form
     double rmean0[2];  // initial global mean density per component
     double uw[3];    // velocity of the static-solid (wall) nodes
     int walls;       // 0: no wall nodes, 1: resting walls, 2: moving walls
+    int pairs;       // particle-particle interactions on (Eqs. (6)-(9))
+    double K_H;      // Hertz constant
+    double delta_c;  // lubrication cut-off
 };
 
 // Element at a 32-bit byte offset from a uniform base (lets the compiler use a
@@ -157,6 +175,35 @@ __device__ inline R psi_ratio(R r, int kind) {
     if (kind == 0) return R(1);
     if (r == R(0)) return R(1);
     return -expm1(-r) / r;
+}
+
+// Densities rho^c and effective masses Psi^c of Eq. (3) kept per node (the
+// density pass, the shell fills and kill / fill write them; the force stencil
+// and the shell fills read them). FP64 keeps the values themselves. The float
+// forms keep their deviations from the reference state, rho - rho_ref^c and
+// Psi(rho) - Psi(rho_ref^c): the force needs only differences of Psi between
+// neighbours (sum_i c_i = 0), which then carry no rounding of the large common
+// part. A kept density d is the deviation in the float forms; eref =
+// exp(-rho_ref^c).
+template <class R>
+__device__ inline constexpr bool kept_dev() {
+    return sizeof(R) != sizeof(double);
+}
+template <class R>
+__device__ inline R psi_kept(R d, int kind, R eref) {
+    if (!kept_dev<R>()) return psi_of(d, kind);
+    return kind == 0 ? d : -eref * expm1(-d);  // e^-ref - e^-(ref + d)
+}
+// Kept density from a kept Psi value (the inverse of psi_kept).
+template <class R>
+__device__ inline R rho_kept_of_psi(R p, int kind, R eref) {
+    if (!kept_dev<R>()) return rho_of_psi(p, kind);
+    return kind == 0 ? p : -log1p(-p / eref);
+}
+// The density itself from a kept density.
+template <class R>
+__device__ inline double rho_full(R d, double ref) {
+    return kept_dev<R>() ? (double)d + ref : (double)d;
 }
 
 // Bounding box of a particle with centre X and bounding radius rb: first
@@ -293,6 +340,7 @@ struct SysDev {
     double* pfast;
     double* kpart;
     int* health;
+    double* counters;  // [0] fluid mass removed at particle placement
     int cap, np;
     int tiles_x, tiles_y;
     int kext;  // largest kill/fill box edge of a normal step

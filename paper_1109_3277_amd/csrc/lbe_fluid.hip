@@ -49,7 +49,8 @@ __device__ inline void node_xyz(const Box& bx, uint32_t n, int& x, int& y, int& 
 }
 
 // ---------------------------------------------------------------- S1
-// rho^c(n) = sum_i f_i^c(n) on fluid nodes, stored as the effective mass
+// rho^c(n) = sum_i f_i^c(n) on fluid nodes (rho_ref^c + sum_i h_i^c in the
+// deviation forms), stored as the effective mass
 // Psi^c(n) of Eq. (3) (what the force stencil reads) and, when the shell fill
 // needs it, as rho^c(n); health flag on NaN / rho < 0.
 // With owner_old given (the pass that follows the re-rasterisation), nodes that
@@ -77,8 +78,8 @@ __device__ inline void density_body(const Box& bx, const typename P::S* __restri
         if (live) {
 #pragma unroll
             for (int i = 0; i < Q; i++) {
-                r0 += P::ld(at(f + (size_t)i * N, nb), R(wq(i)) * ref0);
-                r1 += P::ld(at(f + (size_t)(Q + i) * N, nb), R(wq(i)) * ref1);
+                r0 += P::raw(*at(f + (size_t)i * N, nb));
+                r1 += P::raw(*at(f + (size_t)(Q + i) * N, nb));
             }
         }
     } else if (live) {
@@ -111,8 +112,8 @@ __device__ inline void density_body(const Box& bx, const typename P::S* __restri
         for (int i = 0; i < Q; i++) {
             const bool u = (bm >> i) & 1u;
             const uint32_t ob = up[i] * (uint32_t)sizeof(typename P::S);
-            v0[i] = P::ld(at(u ? f + (size_t)opp(i) * N : f + (size_t)i * N, ob), R(wq(i)) * ref0);
-            v1[i] = P::ld(at(u ? f + (size_t)(Q + opp(i)) * N : f + (size_t)(Q + i) * N, ob), R(wq(i)) * ref1);
+            v0[i] = P::raw(*at(u ? f + (size_t)opp(i) * N : f + (size_t)i * N, ob));
+            v1[i] = P::raw(*at(u ? f + (size_t)(Q + opp(i)) * N : f + (size_t)(Q + i) * N, ob));
         }
 #pragma unroll
         for (int i = 0; i < Q; i++) {
@@ -120,11 +121,17 @@ __device__ inline void density_body(const Box& bx, const typename P::S* __restri
             r1 += v1[i];
         }
     }
-    psi[n] = live ? psi_of(r0, bx.psi_kind) : R(0);
-    psi[N + n] = live ? psi_of(r1, bx.psi_kind) : R(0);
-    if (rho) {  // densities themselves, for the shell fill (exponential Psi only)
+    // r0, r1 are the kept densities (deviations rho - rho_ref in the float
+    // forms, where the population sums are sums of deviations)
+    psi[n] = live ? psi_kept<R>(r0, bx.psi_kind, R(bx.eref[0])) : R(0);
+    psi[N + n] = live ? psi_kept<R>(r1, bx.psi_kind, R(bx.eref[1])) : R(0);
+    if (rho) {  // densities, for the shell fill (exponential Psi only)
         rho[n] = r0;
         rho[N + n] = r1;
+    }
+    if (P::dev) {  // rho^c = rho_ref^c + sum of the deviations
+        r0 += ref0;
+        r1 += ref1;
     }
     if (live && (!(r0 >= R(0)) || !(r1 >= R(0)))) atomicOr(health, 1);
 }
@@ -136,15 +143,22 @@ __global__ __launch_bounds__(256) void k_density(Box bx, const typename P::S* __
                                                  const uint32_t* __restrict__ bmask, int* __restrict__ health) {
     density_body<P, SOLID>(bx, f, psi, rho, owner, owner_old, bmask, health, blockIdx.x);
 }
+// The densities rho^c of a batched system are kept (written by the density
+// pass, read by the shell fills) exactly when a lone handle keeps them: the
+// system has solid nodes (particles or walls), Psi is not rho itself, and the
+// workspace holds the buffer.
+__device__ inline void* sys_rho(const SysDev& d) {
+    return (d.rho && (d.np > 0 || d.box.walls != 0) && d.box.psi_kind != 0) ? d.rho : nullptr;
+}
 // Batched: item = (system, block of 256 nodes); populations copy `c`, owner
 // copy `o` (and, if oo >= 0, old owner copy `oo`); rho is written where the
-// system keeps it (particles present).
+// system keeps it (sys_rho).
 template <class P>
 __global__ __launch_bounds__(256) void k_density_batch(const SysDev* __restrict__ sd,
                                                        const WorkItem* __restrict__ items, int c, int o, int oo) {
     const WorkItem w = items[blockIdx.x];
     const SysDev& d = sd[w.sys];
-    typename P::R* rho = (d.np > 0 && d.box.psi_kind != 0) ? (typename P::R*)d.rho : nullptr;
+    typename P::R* rho = (typename P::R*)sys_rho(d);
     density_body<P, true>(d.box, (const typename P::S*)d.f[c], (typename P::R*)d.psi, rho, d.owner[o],
                           oo >= 0 ? d.owner[oo] : nullptr, d.bmask[c], d.health, w.local);
 }
@@ -185,19 +199,22 @@ __device__ inline void psi_sums(F0 ps0, F1 ps1, R (&s0)[3], R (&s1)[3]) {
 }
 
 // Moments, Shan-Chen velocity shift and BGK relaxation of one node, in place
-// on f0 / f1 (component A / B). S0, S1: the neighbour sums of Psi^A, Psi^B.
+// on f0 / f1 (component A / B): the populations themselves (FP64) or their
+// deviations h_i = f_i - w_i rho_ref^c (the other forms; then
+// f^eq_i - w_i rho_ref = w_i [(rho - rho_ref) + rho (3 c.u + 4.5 (c.u)^2 -
+// 1.5 u.u)] and rho - rho_ref = sum_i h_i). S0, S1: the neighbour sums of
+// Psi^A, Psi^B. r0, r1 return the densities.
 template <class P>
 __device__ inline void collide_node(const Box& bx, typename P::R (&f0)[Q], typename P::R (&f1)[Q],
                                     const typename P::R (&S0)[3], const typename P::R (&S1)[3],
                                     typename P::R& r0, typename P::R& r1) {
     using R = typename P::R;
     R jx = R(0), jy = R(0), jz = R(0);
-    r0 = R(0);
-    r1 = R(0);
+    R d0 = R(0), d1 = R(0);  // sums of the stored numbers
 #pragma unroll
     for (int i = 0; i < Q; i++) {
-        r0 += f0[i];
-        r1 += f1[i];
+        d0 += f0[i];
+        d1 += f1[i];
         const R s = f0[i] + f1[i];
         if (cx(i) > 0) jx += s;
         if (cx(i) < 0) jx -= s;
@@ -206,6 +223,8 @@ __device__ inline void collide_node(const Box& bx, typename P::R (&f0)[Q], typen
         if (cz(i) > 0) jz += s;
         if (cz(i) < 0) jz -= s;
     }
+    r0 = P::dev ? R(bx.rref[0]) + d0 : d0;
+    r1 = P::dev ? R(bx.rref[1]) + d1 : d1;
     const R s0x = S0[0], s0y = S0[1], s0z = S0[2], s1x = S1[0], s1y = S1[1], s1z = S1[2];
     const int kind = bx.psi_kind;
     const R tau = R(bx.tau);
@@ -221,8 +240,18 @@ __device__ inline void collide_node(const Box& bx, typename P::R (&f0)[Q], typen
     const R om = R(bx.omega);
 #pragma unroll
     for (int i = 0; i < Q; i++) {
-        f0[i] = f0[i] - om * (f0[i] - feq_i(i, r0, u0x, u0y, u0z, uu0));
-        f1[i] = f1[i] - om * (f1[i] - feq_i(i, r1, u1x, u1y, u1z, uu1));
+        R e0, e1;
+        if (P::dev) {
+            const R c0 = R(cx(i)) * u0x + R(cy(i)) * u0y + R(cz(i)) * u0z;
+            const R c1 = R(cx(i)) * u1x + R(cy(i)) * u1y + R(cz(i)) * u1z;
+            e0 = R(wq(i)) * (d0 + r0 * (R(3) * c0 + R(4.5) * c0 * c0 - R(1.5) * uu0));
+            e1 = R(wq(i)) * (d1 + r1 * (R(3) * c1 + R(4.5) * c1 * c1 - R(1.5) * uu1));
+        } else {
+            e0 = feq_i(i, r0, u0x, u0y, u0z, uu0);
+            e1 = feq_i(i, r1, u1x, u1y, u1z, uu1);
+        }
+        f0[i] = f0[i] - om * (f0[i] - e0);
+        f1[i] = f1[i] - om * (f1[i] - e1);
     }
 }
 
@@ -291,8 +320,8 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
             const bool up = SOLID && ((bm >> i) & 1u);
             const int pi = up ? opp(i) : i;
             const uint32_t ob = up ? LBE_NB(opp(i)) * (uint32_t)sizeof(S) : nb;
-            f0[i] = P::ld(at(fs + (size_t)pi * N, ob), R(wq(i)) * ref0);
-            f1[i] = P::ld(at(fs + (size_t)(Q + pi) * N, ob), R(wq(i)) * ref1);
+            f0[i] = P::raw(*at(fs + (size_t)pi * N, ob));
+            f1[i] = P::raw(*at(fs + (size_t)(Q + pi) * N, ob));
         }
     } else {
 #pragma unroll
@@ -340,14 +369,14 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
     psi_sums<R>([&](int i) { return s_psi[0][LBE_LS(i)]; }, [&](int i) { return s_psi[1][LBE_LS(i)]; }, S0, S1);
     R r0 = R(0), r1 = R(0);
     if (fluid) collide_node<P>(bx, f0, f1, S0, S1, r0, r1);
-    P::st(atw(fd, nb), fluid ? f0[0] : R(0), R(wq(0)) * ref0);
-    P::st(atw(fd + (size_t)Q * N, nb), fluid ? f1[0] : R(0), R(wq(0)) * ref1);
+    *atw(fd, nb) = P::mk(fluid ? f0[0] : empty_raw<P>(R(wq(0)) * ref0));
+    *atw(fd + (size_t)Q * N, nb) = P::mk(fluid ? f1[0] : empty_raw<P>(R(wq(0)) * ref1));
     if constexpr (!SOLID) {
 #pragma unroll
         for (int i = 1; i < Q; i++) {
             const uint32_t mb = LBE_NB(i) * (uint32_t)sizeof(S);
-            P::st(atw(fd + (size_t)i * N, mb), f0[i], R(wq(i)) * ref0);
-            P::st(atw(fd + (size_t)(Q + i) * N, mb), f1[i], R(wq(i)) * ref1);
+            *atw(fd + (size_t)i * N, mb) = P::mk(f0[i]);
+            *atw(fd + (size_t)(Q + i) * N, mb) = P::mk(f1[i]);
         }
     } else {
         // U_n of the first two particles each fluid lane links to: the wave
@@ -439,7 +468,9 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
                 const double cu = Ux * cx(i) + Uy * cy(i) + Uz * cz(i);
                 C0 = R(-6.0 * wq(i) * cu) * r0;
                 C1 = R(-6.0 * wq(i) * cu) * r1;
-                const double mag = 2.0 * ((double)f0[i] + (double)f1[i]) + ((double)C0 + (double)C1);
+                // (2 f*_i + C) over both components, in double (f = h + w rho_ref in the deviation forms)
+                const double fsum = (double)f0[i] + (double)f1[i] + (P::dev ? wq(i) * (bx.rref[0] + bx.rref[1]) : 0.0);
+                const double mag = 2.0 * fsum + ((double)C0 + (double)C1);
                 if (o == p1) {
                     F1[0] += mag * cx(i);
                     F1[1] += mag * cy(i);
@@ -461,8 +492,8 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
                 C1 = R(-6.0 * wq(i) * cu) * r1;
             }
             const uint32_t mb = LBE_NB(i) * (uint32_t)sizeof(S);
-            P::st(atw(fd + (size_t)i * N, mb), fluid ? f0[i] + C0 : R(0), R(wq(i)) * ref0);
-            P::st(atw(fd + (size_t)(Q + i) * N, mb), fluid ? f1[i] + C1 : R(0), R(wq(i)) * ref1);
+            *atw(fd + (size_t)i * N, mb) = P::mk(fluid ? f0[i] + C0 : empty_raw<P>(R(wq(i)) * ref0));
+            *atw(fd + (size_t)(Q + i) * N, mb) = P::mk(fluid ? f1[i] + C1 : empty_raw<P>(R(wq(i)) * ref1));
         }
         if (fluid && p1 < OWN_WALL && cb1 >= 0) {
             double* r = rec + ((size_t)p1 * rstride + cb1) * kRec;
@@ -535,13 +566,12 @@ __global__ __launch_bounds__(NXT * ROWS, NXT * ROWS == 256 ? (sizeof(typename P:
     const int y = y0 + r;
     const uint32_t n = (uint32_t)(x + nx * (y + ny * z));
     const uint32_t nb = n * (uint32_t)sizeof(S);
-    const R ref0 = R(bx.rref[0]), ref1 = R(bx.rref[1]);
 
     R f0[Q], f1[Q];
 #pragma unroll
     for (int i = 0; i < Q; i++) {
-        f0[i] = P::ld(at(fs + (size_t)i * N, nb), R(wq(i)) * ref0);
-        f1[i] = P::ld(at(fs + (size_t)(Q + i) * N, nb), R(wq(i)) * ref1);
+        f0[i] = P::raw(*at(fs + (size_t)i * N, nb));
+        f1[i] = P::raw(*at(fs + (size_t)(Q + i) * N, nb));
     }
     // halo rows: every load of this thread issued before any is waited for
     constexpr int NE = (LR * NXT + NT - 1) / NT;
@@ -596,8 +626,8 @@ __global__ __launch_bounds__(NXT * ROWS, NXT * ROWS == 256 ? (sizeof(typename P:
     const int wnext = r * WPR + (wr == WPR - 1 ? 0 : wr + 1);  // wave holding x0 + 64
 
     // rest population
-    P::st(atw(fd, nb), f0[0], R(wq(0)) * ref0);
-    P::st(atw(fd + (size_t)Q * N, nb), f1[0], R(wq(0)) * ref1);
+    *atw(fd, nb) = P::mk(f0[0]);
+    *atw(fd + (size_t)Q * N, nb) = P::mk(f1[0]);
     // aligned row stores: plane i, destination row (y + c_iy, z + c_iz), this x
     const uint32_t pl = (uint32_t)(nx * ny);
     const uint32_t yrow[3] = {(uint32_t)(y * nx), (uint32_t)((y + 1 == ny ? 0 : y + 1) * nx),
@@ -622,8 +652,8 @@ __global__ __launch_bounds__(NXT * ROWS, NXT * ROWS == 256 ? (sizeof(typename P:
         const uint32_t mb =
             ((uint32_t)x + yrow[cy(i) == 0 ? 0 : (cy(i) > 0 ? 1 : 2)] + zpl[cz(i) == 0 ? 0 : (cz(i) > 0 ? 1 : 2)]) *
             (uint32_t)sizeof(S);
-        P::st(atw(fd + (size_t)i * N, mb), v0, R(wq(i)) * ref0);
-        P::st(atw(fd + (size_t)(Q + i) * N, mb), v1, R(wq(i)) * ref1);
+        *atw(fd + (size_t)i * N, mb) = P::mk(v0);
+        *atw(fd + (size_t)(Q + i) * N, mb) = P::mk(v1);
     }
 }
 
@@ -632,7 +662,6 @@ template <class P>
 __global__ __launch_bounds__(256) void k_init(Box bx, typename P::S* __restrict__ f, const double* __restrict__ ra,
                                               const double* __restrict__ rb, const double* __restrict__ u,
                                               const uint32_t* __restrict__ owner) {
-    using R = typename P::R;
     const int64_t N = bx.N;
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
@@ -642,11 +671,10 @@ __global__ __launch_bounds__(256) void k_init(Box bx, typename P::S* __restrict_
     const double rr[2] = {ra[n], rb[n]};
 #pragma unroll
     for (int c = 0; c < 2; c++) {
-        const R ref = R(bx.rref[c]);
 #pragma unroll
         for (int i = 0; i < Q; i++) {
             const double v = fluid ? feq_i<double>(i, rr[c], ux, uy, uz, uu) : 0.0;
-            P::st(f + (size_t)(c * Q + i) * N + n, R(v), R(wq(i)) * ref);
+            f[(size_t)(c * Q + i) * N + n] = enc64<P>(v, wq(i) * bx.rref[c]);
         }
     }
 }
@@ -668,13 +696,12 @@ __global__ __launch_bounds__(256) void k_fields(Box bx, const typename P::S* __r
         node_xyz(bx, (uint32_t)n, x, y, z);
 #pragma unroll
         for (int c = 0; c < 2; c++) {
-            const R ref = R(bx.rref[c]);
 #pragma unroll
             for (int i = 0; i < Q; i++) {
                 int pi;
                 uint32_t m;
                 pop_src(bx, (uint32_t)n, x, y, z, bm, i, pi, m);
-                const double v = (double)P::ld(f + (size_t)(c * Q + pi) * N + m, R(wq(i)) * ref);
+                const double v = pop64<P>(f[(size_t)(c * Q + pi) * N + m], wq(i) * bx.rref[c]);
                 r[c] += v;
                 j[0] += v * cx(i);
                 j[1] += v * cy(i);
@@ -687,6 +714,19 @@ __global__ __launch_bounds__(256) void k_fields(Box bx, const typename P::S* __r
     const double rt = r[0] + r[1];
 #pragma unroll
     for (int k = 0; k < 3; k++) out[2 * N + 3 * n + k] = (fluid && rt != 0.0) ? j[k] / rt : 0.0;
+}
+
+// Owner codes as the ABI reports them: -1 fluid, -2 wall, else the particle index.
+__global__ void k_owner_codes(const uint32_t* __restrict__ owner, int32_t* __restrict__ out, int64_t n) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t o = owner[k];
+        out[k] = o == OWN_FLUID ? -1 : (o == OWN_WALL ? -2 : (int32_t)o);
+    }
+}
+hipError_t launch_owner_codes(lb_handle* h, int32_t* dev_out) {
+    unsigned g = (unsigned)std::min<int64_t>((h->box.N + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_owner_codes, dim3(g), dim3(256), 0, h->stream, h->b.owner[h->ocur], dev_out, h->box.N);
+    return hipGetLastError();
 }
 
 // Deterministic reduction: fixed grid, per-block LDS tree, then one ordered pass.
@@ -705,14 +745,13 @@ __global__ __launch_bounds__(256) void k_stats_partial(Box bx, const typename P:
         node_xyz(bx, (uint32_t)n, x, y, z);
 #pragma unroll
         for (int c = 0; c < 2; c++) {
-            const R ref = R(bx.rref[c]);
             double r = 0.0;
 #pragma unroll
             for (int i = 0; i < Q; i++) {
                 int pi;
                 uint32_t m;
                 pop_src(bx, (uint32_t)n, x, y, z, bm, i, pi, m);
-                const double v = (double)P::ld(f + (size_t)(c * Q + pi) * N + m, R(wq(i)) * ref);
+                const double v = pop64<P>(f[(size_t)(c * Q + pi) * N + m], wq(i) * bx.rref[c]);
                 r += v;
                 acc[2] += v * cx(i);
                 acc[3] += v * cy(i);
@@ -752,15 +791,13 @@ __global__ void k_stats_final(double* __restrict__ red, int nblocks) {
 template <class P>
 __global__ __launch_bounds__(256) void k_remove_covered(Box bx, typename P::S* __restrict__ f,
                                                         const uint32_t* __restrict__ owner) {
-    using R = typename P::R;
     const int64_t N = bx.N;
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N || owner[n] == OWN_FLUID) return;
 #pragma unroll
     for (int c = 0; c < 2; c++) {
-        const R ref = R(bx.rref[c]);
 #pragma unroll
-        for (int i = 0; i < Q; i++) P::st(f + (size_t)(c * Q + i) * N + n, R(0), R(wq(i)) * ref);
+        for (int i = 0; i < Q; i++) f[(size_t)(c * Q + i) * N + n] = enc64<P>(0.0, wq(i) * bx.rref[c]);
     }
 }
 
@@ -786,8 +823,7 @@ __global__ __launch_bounds__(256) void k_canonical(Box bx, const typename P::S* 
             int pi;
             uint32_t m;
             pop_src(bx, (uint32_t)n, x, y, z, bm, i, pi, m);
-            const S v = fluid ? fs[(size_t)(c * Q + pi) * N + m]
-                              : P::enc(typename P::R(0), typename P::R(wq(i)) * typename P::R(bx.rref[c]));
+            const S v = fluid ? fs[(size_t)(c * Q + pi) * N + m] : enc64<P>(0.0, wq(i) * bx.rref[c]);
             fd[(size_t)(c * Q + i) * N + n] = v;
         }
     }
@@ -822,7 +858,7 @@ __global__ __launch_bounds__(256) void k_clear_owner_batch(const SysDev* __restr
 // Eq. (10) for wall nodes (colour 0): a wall node with fluid neighbours
 // (over the 18 links) takes their mean density, stored as Psi; 0 without
 // fluid neighbours. Densities of fluid nodes: the stored rho where kept, else
-// Psi itself (Psi = rho) or recovered from it.
+// Psi itself (Psi = rho) or recovered from it (all as kept values).
 template <class R>
 __device__ inline void wall_shell_node(const Box& bx, R* __restrict__ psi, const R* __restrict__ rho,
                                        const uint32_t* __restrict__ owner, int64_t n) {
@@ -843,15 +879,15 @@ __device__ inline void wall_shell_node(const Box& bx, R* __restrict__ psi, const
             d0 = rho[m];
             d1 = rho[N + m];
         } else {
-            d0 = rho_of_psi(psi[m], 1);
-            d1 = rho_of_psi(psi[N + m], 1);
+            d0 = rho_kept_of_psi(psi[m], 1, R(bx.eref[0]));
+            d1 = rho_kept_of_psi(psi[N + m], 1, R(bx.eref[1]));
         }
         s0 += d0;
         s1 += d1;
         k++;
     }
-    psi[n] = k == 0 ? R(0) : psi_of(s0 / R(k), bx.psi_kind);
-    psi[N + n] = k == 0 ? R(0) : psi_of(s1 / R(k), bx.psi_kind);
+    psi[n] = k == 0 ? R(0) : psi_kept(s0 / R(k), bx.psi_kind, R(bx.eref[0]));
+    psi[N + n] = k == 0 ? R(0) : psi_kept(s1 / R(k), bx.psi_kind, R(bx.eref[1]));
 }
 template <class R>
 __global__ __launch_bounds__(256) void k_wall_shell(Box bx, R* __restrict__ psi, const R* __restrict__ rho,
@@ -866,7 +902,7 @@ __global__ __launch_bounds__(256) void k_wall_shell_batch(const SysDev* __restri
     const SysDev& d = sd[w.sys];
     if (d.box.walls == 0) return;
     const int64_t n = (int64_t)w.local * 256 + threadIdx.x;
-    if (n < d.box.N) wall_shell_node<R>(d.box, (R*)d.psi, (const R*)d.rho, d.owner[o], n);
+    if (n < d.box.N) wall_shell_node<R>(d.box, (R*)d.psi, (const R*)sys_rho(d), d.owner[o], n);
 }
 // Owner copy cleared for re-rasterisation, wall nodes kept (from the current copy).
 __global__ void k_clear_keep_walls(uint32_t* __restrict__ dst, const uint32_t* __restrict__ cur, int64_t n) {
@@ -1102,9 +1138,12 @@ static void launch_batch_fused_t(const BatchLaunch& bl, hipStream_t st, int c, i
     if (bl.bx == 64)
         hipLaunchKernelGGL((k_fused_batch<P, SOLID, 64, 4>), dim3(bl.n[k]), dim3(256), 0, st, bl.sys, bl.items[k], c,
                            o);
-    else
+    else if (bl.bx == 32)
         hipLaunchKernelGGL((k_fused_batch<P, SOLID, 32, 8>), dim3(bl.n[k]), dim3(256), 0, st, bl.sys, bl.items[k], c,
                            o);
+    else
+        hipLaunchKernelGGL((k_fused_batch<P, SOLID, 16, 16>), dim3(bl.n[k]), dim3(256), 0, st, bl.sys, bl.items[k],
+                           c, o);
 }
 
 hipError_t launch_batch_fused(const BatchLaunch& bl, int precision, hipStream_t st, int c, int o) {

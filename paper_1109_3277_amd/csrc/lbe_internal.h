@@ -26,7 +26,14 @@ struct Buffers {
     double* red = nullptr;             // reduction partials, kRedBlocks x 8, then totals
     double* counters = nullptr;        // [0] fluid mass removed at particle placement (cumulative)
     int* health = nullptr;             // nonzero once a NaN / negative density was seen
+    int* cells = nullptr;              // pair cell list: counts, starts, cell of each particle, list
 };
+
+// Cell grid of the particle-particle cell list (cells per axis).
+struct CellGrid {
+    int nc[3];
+};
+constexpr int kMaxCellsPerAxis = 64;
 
 constexpr int kRedBlocks = 1024;       // fixed grid of the deterministic reductions
 
@@ -49,6 +56,7 @@ struct lb_handle {
     lb_params prm;
     lbe::Box box;
     hipStream_t stream = nullptr;
+    int device = 0;      // the GPU current at creation
     char* ws = nullptr;
     size_t ws_bytes = 0;
     lbe::Buffers b;
@@ -86,13 +94,18 @@ namespace lbe {
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
-    size_t f, psi, rho, owner, bmask, part, pfast, rec, kpart, red, counters, health, total;
+    size_t f, psi, rho, owner, bmask, part, pfast, rec, kpart, red, counters, health, cells, total;
 };
 bool params_ok(const lb_params* p, std::string* why);
 Layout layout_of(const lb_params* p);
 int fail(lb_handle* h, int code, const std::string& msg);
 // Carve one system's buffers from ws and clear them (synchronizes stream).
 int setup_handle(lb_handle* h, const lb_params* prm, char* ws, size_t ws_bytes, hipStream_t stream);
+
+// Descriptor of one system as the batched kernels see it (lbe_batch.hip).
+SysDev sys_dev(const lb_handle* q);
+// Device descriptors and systems of a batch (refreshed when stale).
+int batch_sys(lb_handle* h, const SysDev** d_sys, int* nsys, int* parity);
 
 // Batches (lbe_batch.hip).
 int batch_step_async(lb_handle* h, int nsteps);
@@ -123,6 +136,7 @@ hipError_t launch_fused(lb_handle* h);
 hipError_t launch_forces(lb_handle* h);
 Tiles fused_tiles(int nx, int ny, bool solids, int precision);
 hipError_t launch_fields(lb_handle* h, double* d_out);       // rho_a, rho_b, u (5 x N doubles)
+hipError_t launch_owner_codes(lb_handle* h, int32_t* dev_out);  // ABI owner codes, N int32
 hipError_t launch_stats(lb_handle* h);                       // totals into b.red[kRedBlocks*8 ...]
 hipError_t launch_remove_covered(lb_handle* h);
 // Populations into plain form (every value in its node's own slot, masks
@@ -136,6 +150,9 @@ hipError_t launch_clear_keep_walls(lb_handle* h, uint32_t* dst, const uint32_t* 
 hipError_t launch_wall_shell(lb_handle* h);  // Psi of wall nodes next to fluid
 hipError_t launch_killfill(lb_handle* h);
 hipError_t launch_fold_impulses(lb_handle* h);
+// Particle-particle forces and torques into the particle table (lbe_pairs.hip).
+hipError_t launch_pairs(lb_handle* h);
+CellGrid cell_grid(int nx, int ny, int nz, double range);
 int raster_extent(int nx, int ny, int nz, double rb);
 int killfill_extent(int nx, int ny, int nz, double rb);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);

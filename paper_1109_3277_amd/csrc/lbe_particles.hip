@@ -191,8 +191,8 @@ __device__ inline void shell_body(const Box& bx, R* __restrict__ psi, const R* _
                 R a = s0 / R(k), b = s1 / R(k);
                 if (dr > 0.0) a += R(dr);
                 else if (dr < 0.0) b += R(-dr);
-                psi[n] = psi_of(a, bx.psi_kind);
-                psi[N + n] = psi_of(b, bx.psi_kind);
+                psi[n] = psi_kept(a, bx.psi_kind, R(bx.eref[0]));
+                psi[N + n] = psi_kept(b, bx.psi_kind, R(bx.eref[1]));
             }
         }
         __syncthreads();  // the list is read before the next segment resets it
@@ -300,7 +300,9 @@ __global__ __launch_bounds__(kPB) void k_linkforce_batch(const SysDev* __restric
 }
 
 // ---------------------------------------------------------------- S7
-// Newton-Euler update, dt = 1: F = F_links + J, T = T_links + H; V += F/M,
+// Newton-Euler update, dt = 1: F = F_links + J + F_pairs, T = T_links + H +
+// T_pairs (the pair terms are zero unless particle-particle interactions are
+// on); V += F/M,
 // X = wrap(X + V); L += T; W = R I^-1 R^T L with the old orientation;
 // q <- normalise(exp(W/2) (x) q). F_links / T_links come from k_linkforce;
 // J / H are the stored impulses plus the kill/fill slots. One wave per
@@ -325,8 +327,8 @@ __device__ inline void bodies_body(const Box& bx, double* __restrict__ part, int
     const double H[3] = {F_(HX) + Jk[3], F_(HY) + Jk[4], F_(HZ) + Jk[5]};
     double F[3], T[3];
     for (int d = 0; d < 3; d++) {
-        F[d] = Fl[d] + J[d];
-        T[d] = Fl[3 + d] + H[d];
+        F[d] = Fl[d] + J[d] + F_(PFX + d);
+        T[d] = Fl[3 + d] + H[d] + F_(PTX + d);
     }
     F_(FX) = Fl[0];
     F_(FY) = Fl[1];
@@ -471,16 +473,16 @@ __device__ inline void killfill_node(const Box& bx, typename P::S* __restrict__ 
         double j[3] = {0.0, 0.0, 0.0}, m = 0.0;
 #pragma unroll
         for (int cc = 0; cc < 2; cc++) {
-            R v[Q];  // a component's loads all issued before its in-order sums
+            typename P::S v[Q];  // a component's loads all issued before its in-order sums
 #pragma unroll
             for (int i = 0; i < Q; i++) {
                 const bool u = (bm >> i) & 1u;
                 const int64_t src = u ? (int64_t)upstream(Ls[0], Ls[1], Ls[2], x, y, z, i) : n;
-                v[i] = P::ld(f + (size_t)(cc * Q + (u ? opp(i) : i)) * N + src, R(wq(i)) * R(bx.rref[cc]));
+                v[i] = f[(size_t)(cc * Q + (u ? opp(i) : i)) * N + src];
             }
 #pragma unroll
             for (int i = 0; i < Q; i++) {
-                const double w = (double)v[i];
+                const double w = pop64<P>(v[i], wq(i) * bx.rref[cc]);
                 m += w;
                 j[0] += w * cx(i);
                 j[1] += w * cy(i);
@@ -522,7 +524,8 @@ __device__ inline void killfill_node(const Box& bx, typename P::S* __restrict__ 
             cnt++;
         }
 #pragma unroll
-        for (int cc = 0; cc < 2; cc++) rn[cc] = cnt > 0 ? rn[cc] / (double)cnt : bx.rmean0[cc];
+        for (int cc = 0; cc < 2; cc++)
+            rn[cc] = cnt > 0 ? rho_full<R>(R(0), bx.rref[cc]) + rn[cc] / (double)cnt : bx.rmean0[cc];
         const double ub[3] = {V[0] + (W[1] * r[2] - W[2] * r[1]), V[1] + (W[2] * r[0] - W[0] * r[2]),
                               V[2] + (W[0] * r[1] - W[1] * r[0])};
         // Population i of the node goes to its own slot (i, n), unless the
@@ -538,23 +541,22 @@ __device__ inline void killfill_node(const Box& bx, typename P::S* __restrict__ 
         R rs[2];
 #pragma unroll
         for (int cc = 0; cc < 2; cc++) {
-            const R ref = R(bx.rref[cc]);
             R r = R(0);
 #pragma unroll
             for (int i = 0; i < Q; i++) {
                 const bool u = (bm >> i) & 1u;
                 typename P::S* dst = f + (size_t)(cc * Q + (u ? opp(i) : i)) * N + (u ? (int64_t)up[i] : n);
-                const typename P::S e = P::enc(R(feq_p<double>(i, rn[cc], ub[0], ub[1], ub[2])), R(wq(i)) * ref);
+                const typename P::S e = enc64<P>(feq_p<double>(i, rn[cc], ub[0], ub[1], ub[2]), wq(i) * bx.rref[cc]);
                 *dst = e;
                 // the node's density as the density pass forms it from the stored values
-                r += P::dec(e, R(wq(i)) * ref);
+                r += P::raw(e);
             }
             for (int d = 0; d < 3; d++) jm[d] += rn[cc] * ub[d];
-            rs[cc] = r;
+            rs[cc] = r;  // the kept density (the deviation in the float forms)
         }
         bmask[n] = bm;
-        psi[n] = psi_of(rs[0], bx.psi_kind);
-        psi[N + n] = psi_of(rs[1], bx.psi_kind);
+        psi[n] = psi_kept(rs[0], bx.psi_kind, R(bx.eref[0]));
+        psi[N + n] = psi_kept(rs[1], bx.psi_kind, R(bx.eref[1]));
         if (bx.psi_kind != 0) {
             rho[n] = rs[0];
             rho[N + n] = rs[1];

@@ -65,8 +65,13 @@ Layout layout_of(const lb_params* p) {
     L.red = align_up((kRedBlocks + 1) * 8 * sizeof(double));
     L.counters = align_up(8 * sizeof(double));
     L.health = align_up(sizeof(int));
+    // pair cell list: counts and starts of at most kMaxCellsPerAxis^3 cells
+    // (one cell per node at most), the cell of each particle and the list
+    size_t ncell = 1;
+    for (int d : {p->nx, p->ny, p->nz}) ncell *= (size_t)std::min(d, kMaxCellsPerAxis);
+    L.cells = p->max_particles > 1 ? align_up((2 * ncell + 1 + 2 * cap) * sizeof(int)) : 0;
     L.total = 2 * L.f + L.psi + L.rho + 2 * L.owner + 2 * L.bmask + L.part + L.pfast + L.rec + L.kpart + L.red +
-              L.counters + L.health;
+              L.counters + L.health + L.cells;
     return L;
 }
 
@@ -74,6 +79,7 @@ int setup_handle(lb_handle* h, const lb_params* prm, char* ws, size_t ws_bytes, 
     const Layout L = layout_of(prm);
     h->prm = *prm;
     h->stream = stream;
+    (void)hipGetDevice(&h->device);
     h->ws = ws;
     h->ws_bytes = ws_bytes;
     h->cap = std::max(prm->max_particles, 1);
@@ -88,9 +94,13 @@ int setup_handle(lb_handle* h, const lb_params* prm, char* ws, size_t ws_bytes, 
     b.psi_kind = prm->psi_kind;
     b.ax = b.ay = b.az = 0.0;
     b.rref[0] = b.rref[1] = 0.0;
+    b.eref[0] = b.eref[1] = 1.0;
     b.rmean0[0] = b.rmean0[1] = 0.0;
     b.uw[0] = b.uw[1] = b.uw[2] = 0.0;
     b.walls = 0;
+    b.pairs = 0;
+    b.K_H = 100.0;
+    b.delta_c = 2.0 / 3.0;
     char* p = h->ws;
     h->b.f[0] = p; p += L.f;
     h->b.f[1] = p; p += L.f;
@@ -107,6 +117,7 @@ int setup_handle(lb_handle* h, const lb_params* prm, char* ws, size_t ws_bytes, 
     h->b.red = (double*)p; p += L.red;
     h->b.counters = (double*)p; p += L.counters;
     h->b.health = (int*)p; p += L.health;
+    h->b.cells = L.cells ? (int*)p : nullptr; p += L.cells;
     int rc = LB_OK;
     auto chk = [&](hipError_t e, const char* what) {
         if (e != hipSuccess && rc == LB_OK) rc = fail(nullptr, LB_EHIP, std::string(what) + ": " + hipGetErrorString(e));
@@ -173,6 +184,7 @@ int enqueue_step(lb_handle* h) {
     LBE_PHASE(h, 2, launch_fused(h));
     if (h->np > 0) {
         LBE_PHASE(h, 3, launch_forces(h));
+        if (h->box.pairs) LBE_PHASE(h, 3, launch_pairs(h));
         LBE_PHASE(h, 4, launch_bodies(h));
         uint32_t* on = h->b.owner[1 - h->ocur];
         LBE_HIP(h, mark(h, 5, true));
@@ -266,6 +278,7 @@ int lb_init_fields(lb_handle* h, const double* rho_a, const double* rho_b, const
     for (int c = 0; c < 2; c++) {
         h->box.rmean0[c] = s[c] / (double)N;
         h->box.rref[c] = h->box.rmean0[c];
+        h->box.eref[c] = exp(-h->box.rref[c]);
     }
     double* st = (double*)staging(h);
     double* d_ra = st;
@@ -422,6 +435,25 @@ int lb_read_fields(lb_handle* h, double* rho_a, double* rho_b, double* u, int32_
     return LB_OK;
 }
 
+int lb_read_fields_dev(lb_handle* h, double* dev_rho_a, double* dev_rho_b, double* dev_u, int32_t* dev_owner) {
+    if (!h) return LB_EINVAL;
+    LBE_NOT_BATCH(h);
+    if (!h->inited) return fail(h, LB_ESTATE, "fields not initialised");
+    const int64_t N = h->box.N;
+    double* st = (double*)staging(h);
+    if (dev_rho_a || dev_rho_b || dev_u) {
+        LBE_HIP(h, launch_fields(h, st));
+        if (dev_rho_a)
+            LBE_HIP(h, hipMemcpyAsync(dev_rho_a, st, N * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+        if (dev_rho_b)
+            LBE_HIP(h, hipMemcpyAsync(dev_rho_b, st + N, N * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+        if (dev_u)
+            LBE_HIP(h, hipMemcpyAsync(dev_u, st + 2 * N, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    }
+    if (dev_owner) LBE_HIP(h, launch_owner_codes(h, dev_owner));
+    return LB_OK;
+}
+
 int lb_num_particles(const lb_handle* h) { return h ? h->np : LB_EINVAL; }
 
 int lb_read_particles(lb_handle* h, double* pos, double* quat, double* vel, double* omega, double* force,
@@ -490,6 +522,24 @@ int lb_set_body_accel(lb_handle* h, const double a[3]) {
     h->box.ay = a[1];
     h->box.az = a[2];
     batch_touch(h);
+    return LB_OK;
+}
+
+int lb_set_pair_interactions(lb_handle* h, int on, double K_H, double delta_c) {
+    if (!h) return LB_EINVAL;
+    LBE_NOT_BATCH(h);
+    if (h->parent) return fail(h, LB_ESTATE, "particle-particle interactions are not available on batch systems");
+    if (on) {
+        if (!(K_H >= 0.0) || !isfinite(K_H)) return fail(h, LB_EINVAL, "K_H must be finite and >= 0");
+        if (!(delta_c > 0.0) || !isfinite(delta_c)) return fail(h, LB_EINVAL, "delta_c must be finite and > 0");
+        if (h->prm.max_particles < 2) return fail(h, LB_ESTATE, "the workspace holds fewer than two particles");
+        h->box.K_H = K_H;
+        h->box.delta_c = delta_c;
+    } else {
+        // clear the pair terms the next body update would otherwise add
+        LBE_HIP(h, launch_fill_f64(h, h->b.part + (size_t)PFX * h->cap, 0.0, (int64_t)6 * h->cap));
+    }
+    h->box.pairs = on ? 1 : 0;
     return LB_OK;
 }
 
@@ -595,6 +645,8 @@ int lb_load_state(lb_handle* h, const void* host_buf, size_t bytes) {
     h->box.rmean0[1] = hdr[2];
     h->box.rref[0] = hdr[3];
     h->box.rref[1] = hdr[4];
+    h->box.eref[0] = exp(-hdr[3]);
+    h->box.eref[1] = exp(-hdr[4]);
     h->rmax = hdr[5];
     // wall nodes come with the owner map; their velocity is the handle's own
     const bool moving = h->box.uw[0] != 0.0 || h->box.uw[1] != 0.0 || h->box.uw[2] != 0.0;
@@ -604,13 +656,6 @@ int lb_load_state(lb_handle* h, const void* host_buf, size_t bytes) {
     h->inited = true;
     h->dens_ready = false;
     batch_touch(h);
-    return LB_OK;
-}
-
-int lb_probe_copy(void* dev_dst, const void* dev_src, size_t bytes, void* hip_stream) {
-    if (!dev_dst || !dev_src || bytes % 16 != 0) return fail(nullptr, LB_EINVAL, "probe copy needs 16-byte multiples");
-    hipError_t e = launch_copy(dev_dst, dev_src, bytes, (hipStream_t)hip_stream);
-    if (e != hipSuccess) return fail(nullptr, LB_EHIP, hipGetErrorString(e));
     return LB_OK;
 }
 

@@ -4,13 +4,14 @@
 
 Builds the named synthetic workload, runs `--warmup` untimed and `--steps`
 further time steps through the HIP library, then copies `--copy-mib` MiB with
-the library's plain streaming kernel (k_copy16). The copy gives the
-calibration point for hardware byte counters: its algorithmic traffic is
+the plain streaming kernel of liblbe_probe.so (k_probe_copy16). The copy gives
+the calibration point for hardware byte counters: its algorithmic traffic is
 exactly that many bytes read and written.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes as C
 import os
 import sys
 
@@ -21,7 +22,7 @@ if ROOT not in sys.path:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="bijel", choices=["bijel", "spinodal", "interface"])
+    ap.add_argument("--workload", default="bijel", choices=["bijel", "spinodal", "interface", "mixed"])
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
@@ -30,9 +31,10 @@ def main():
     import torch
 
     from paper_1109_3277_amd import workloads as W
-    from paper_1109_3277_amd.binding import Lattice, probe_copy
+    from paper_1109_3277_amd.binding import Lattice
 
-    s = {"bijel": W.bijel_system, "spinodal": W.spinodal_system, "interface": W.interface_system}[a.workload]()
+    s = {"bijel": W.bijel_system, "spinodal": W.spinodal_system, "interface": W.interface_system,
+         "mixed": W.mixed_system}[a.workload]()
     g = Lattice(s.dims, s.tau, s.g_br, s.psi_kind, a.precision, max_particles=s.n_particles, max_radius=s.max_radius)
     g.init_fields(s.rho_a, s.rho_b)
     if s.n_particles:
@@ -44,9 +46,12 @@ def main():
         n = a.copy_mib << 20
         src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        probe_copy(dst, src)
+        probe = C.CDLL(os.path.join(ROOT, "paper_1109_3277_amd", "liblbe_probe.so"))
+        probe.lbe_probe_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+        rc = probe.lbe_probe_copy(dst.data_ptr(), src.data_ptr(), n, torch.cuda.current_stream().cuda_stream)
+        assert rc == 0, rc
         torch.cuda.synchronize()
-        print(f"copied {a.copy_mib} MiB with k_copy16", flush=True)
+        print(f"copied {a.copy_mib} MiB with k_probe_copy16", flush=True)
 
 
 if __name__ == "__main__":

@@ -26,6 +26,13 @@ single-particle adsorption of Sec. 4):
   ensemble    64 flat-interface systems of uneven sizes, one ellipsoid each
               (Rperp ~ U[3, 6], m log-uniform in [1/4, 4], tilt ~ U[0, 90 deg],
               azimuth ~ U[0, 360 deg), colour ~ U[-0.5, 0.5]). seed 5.
+  adsorption  the single-ellipsoid adsorption of Sec. 4: 64^3, walls on the
+              two z faces, two lamellae of 31 nodes (red below), g_br = 0.1,
+              one ellipsoid R_p = 12, R_o = 6, colour 0 (contact angle 90 deg),
+              its axis tilted 0.0057 deg from the interface normal, centred
+              in x, y and below the interface. seed 6.
+  contact     a sphere of radius R at a flat interface between walls, colour
+              dr (the contact-angle calibration of Eq. (11)).
 """
 from __future__ import annotations
 
@@ -265,3 +272,39 @@ def ensemble_systems(n_sys: int = 64, seed: int = 5, g_br: float = 0.08, tau: fl
         out.append(System(f"ensemble{s}", dims, tau, g_br, ra, rb, np.array([[rpar, rperp]]), pos, q,
                           np.array([dr]), np.array([float(density)]), seed=seed * 1000 + s))
     return out
+
+
+def wall_mask(dims) -> np.ndarray:
+    """Static solid nodes on the two z faces (z = 0 and z = nz - 1)."""
+    z = _zcoord(dims)
+    return (z == 0) | (z == dims[2] - 1)
+
+
+def adsorption_system(seed: int = 6, phi0_deg: float = 0.0057, z0: float = 16.5, rpar: float = 12.0,
+                      rperp: float = 6.0, g_br: float = 0.1, hi: float = 1.4, lo: float = 0.05,
+                      density: float = 1.0) -> System:
+    """Sec. 4 single-particle adsorption: 64^3, walls at z = 0 and 63 (the
+    paper's z = 1 and 64), fluid z = 1..62 in two lamellae of 31 nodes, red
+    (A) below z = 32, g_br = 0.1; lamella densities near the coexisting pair
+    at this g (hi / lo, +-0.001 noise); one ellipsoid R_p = 12, R_o = 6,
+    colour 0, its axis tilted phi0 from the interface normal (about x), centre
+    (32, 32, z0) in the red lamella below the interface at z = 31.5."""
+    dims = (64, 64, 64)
+    ra, rb = layered_fields(dims, seed, hi=hi, lo=lo, amp=0.001, z_split=32)
+    th = math.radians(phi0_deg)
+    q = np.array([[math.cos(0.5 * th), math.sin(0.5 * th), 0.0, 0.0]])
+    return System("adsorption", dims, 1.0, g_br, ra, rb, np.array([[rpar, rperp]]), np.array([[32.0, 32.0, z0]]), q,
+                  np.array([0.0]), np.array([float(density)]), seed=seed)
+
+
+def contact_system(delta_rho: float, radius: float = 8.0, n: int = 48, seed: int = 7, g_br: float = 0.1,
+                   hi: float = 1.4, lo: float = 0.05, density: float = 1.0) -> System:
+    """A sphere of radius R with colour delta_rho at a flat interface between
+    walls on the z faces (lamellae as in adsorption_system), its centre on the
+    interface: the equilibrium height it settles at gives the contact angle."""
+    dims = (n, n, n)
+    zs = n // 2
+    ra, rb = layered_fields(dims, seed, hi=hi, lo=lo, amp=0.001, z_split=zs)
+    return System(f"contact{delta_rho:+.2f}", dims, 1.0, g_br, ra, rb, np.array([[radius, radius]]),
+                  np.array([[n / 2 + 0.1, n / 2 - 0.2, zs - 0.5]]), np.array([[1.0, 0.0, 0.0, 0.0]]),
+                  np.array([float(delta_rho)]), np.array([float(density)]), seed=seed)

@@ -95,11 +95,40 @@ def test_batch_workspace_and_create_validate(lib):
     bad = (B.lb_params * 2)(a, B.make_params((32, 32, 2), 1.0, 0.08, precision="fp32"))
     assert lib.lb_batch_workspace_bytes(2, bad) == 0
     h = C.c_void_p()
-    assert lib.lb_batch_create(2, arr, None, n, None, C.byref(h)) == B.LB_EINVAL
-    assert lib.lb_batch_create(2, arr, C.c_void_p(256), n - 1, None, C.byref(h)) == B.LB_ENOMEM
-    assert lib.lb_batch_create(2, arr, C.c_void_p(256 + 8), n, None, C.byref(h)) == B.LB_EINVAL
-    assert lib.lb_batch_create(2, mixed, C.c_void_p(256), n, None, C.byref(h)) == B.LB_EINVAL
+    assert lib.lb_create_batch(2, arr, None, n, None, C.byref(h)) == B.LB_EINVAL
+    assert lib.lb_create_batch(2, arr, C.c_void_p(256), n - 1, None, C.byref(h)) == B.LB_ENOMEM
+    assert lib.lb_create_batch(2, arr, C.c_void_p(256 + 8), n, None, C.byref(h)) == B.LB_EINVAL
+    assert lib.lb_create_batch(2, mixed, C.c_void_p(256), n, None, C.byref(h)) == B.LB_EINVAL
     assert b"precision" in lib.lb_last_error(None)
     assert lib.lb_batch_size(None) == B.LB_EINVAL
     assert lib.lb_batch_system(None, 0, C.byref(h)) == B.LB_EINVAL
     assert lib.lb_batch_tune(None, None) == B.LB_EINVAL
+
+
+def test_per_system_calls_reject_bad_handles(lib):
+    from paper_1109_3277_amd import binding as B
+    assert lib.lb_init_fields_sys(None, 0, None, None, None) == B.LB_EINVAL
+    assert lib.lb_add_ellipsoids_sys(None, 0, 0, None, None, None, None, None) == B.LB_EINVAL
+    assert lib.lb_read_fields_sys(None, 0, None, None, None, None) == B.LB_EINVAL
+    assert lib.lb_read_particles_sys(None, 0, None, None, None, None, None, None) == B.LB_EINVAL
+    assert lib.lb_stats_sys(None, 0, None) == B.LB_EINVAL
+
+
+def test_probe_copy_lives_outside_the_method_library(lib):
+    """The counter-calibration copy is a separate library, not part of the ABI."""
+    assert not hasattr(lib, "lb_probe_copy")
+    from paper_1109_3277_amd import build
+    if not os.path.exists(build.PROBE_LIB):
+        build.build()
+    probe = C.CDLL(build.PROBE_LIB)
+    assert hasattr(probe, "lbe_probe_copy")
+
+
+def test_pair_interactions_reject_bad_handles(lib):
+    from paper_1109_3277_amd import binding as B
+    assert lib.lb_set_pair_interactions(None, 1, 100.0, 2.0 / 3.0) == B.LB_EINVAL
+
+
+def test_device_readout_rejects_bad_handles(lib):
+    from paper_1109_3277_amd import binding as B
+    assert lib.lb_read_fields_dev(None, None, None, None, None) == B.LB_EINVAL

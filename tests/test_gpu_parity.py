@@ -1,15 +1,16 @@
 """GPU (HIP, through the C ABI) against the CPU FP64 oracle on the same seeded
 inputs. Gates: FP64 <= 1e-12 relative after 100 steps (densities L-inf over
-max |rho|; velocity L-inf over max(|u|_max, 1e-3), see parity_util), owner
-map identical; FP32 <= 1e-5; reduced storage <= 1e-3 with the mass drift
-reported."""
+max |rho|; velocity L-inf over max(|u|_max, 1e-3) and raw L2; total momentum
+and removed mass; see parity_util), owner map identical; FP32 <= 1e-5 on the
+same quantities and on the particles; reduced storage <= 1e-3 with the mass
+drift reported."""
 import math
 
 import numpy as np
 import pytest
 
 from paper_1109_3277_amd import workloads as W
-from tests.parity_util import compare, log, run_gpu, run_oracle
+from tests.parity_util import check, compare, log, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -17,22 +18,19 @@ FP64_GATE = 1e-12
 
 
 def _check_fp64(res, particles=True):
-    log(f"  parity {res}")
-    assert res["e_rho"] <= FP64_GATE, res
-    assert res["e_u"] <= FP64_GATE, res
-    assert res["owner_equal"], res
-    assert res["n_fluid_equal"], res
-    assert res["e_mass"] <= 1e-13, res
-    if particles and "e_pos" in res:
-        assert res["e_pos"] <= 1e-12 and res["e_quat"] <= 1e-12, res
-        assert res["e_vel"] <= 1e-10 and res["e_omega"] <= 1e-10, res
+    check(res, FP64_GATE, vel_gate=1e-10, particles=particles)
+    assert res["e_mass"] <= FP64_GATE, res
+
+
+FP32_GATE = 1e-5
+RED_GATE = 1e-3
 
 
 def _run(sysm, steps, precision="fp64"):
     log(f"case {sysm.name} dims={sysm.dims} np={sysm.n_particles} steps={steps} precision={precision}")
     o = run_oracle(sysm, steps)
     g = run_gpu(sysm, steps, precision)
-    return o, g, compare(o, g, sysm.dims)
+    return o, g, compare(o, g, sysm.dims, sysm.radii)
 
 
 def test_fluid_ragged_tiles_fp64():
@@ -54,8 +52,7 @@ def test_tile_z_runs_ragged_fp64():
 def test_tile_z_runs_fp32():
     s = W.bijel_system(dims=(70, 516, 12), seed=22, phi=0.1, rpar=4.5, rperp=2.5)
     _, _, res = _run(s, 30, "fp32")
-    log(f"  fp32 {res}")
-    assert res["owner_equal"] and res["e_rho"] <= 1e-5, res
+    check(res, FP32_GATE)
 
 
 def test_zero_steps_and_minimum_box():
@@ -64,7 +61,7 @@ def test_zero_steps_and_minimum_box():
     assert res["e_rho"] <= 1e-15
     o.step(20)
     g.step(20)
-    _check_fp64(compare(o, g, s.dims))
+    _check_fp64(compare(o, g, s.dims, s.radii))
 
 
 def test_interface_full_size_fp64():
@@ -121,7 +118,7 @@ def test_moving_particles_cross_nodes_fp64():
     own0 = o.owner().copy()
     o.step(100)
     g.step(100)
-    res = compare(o, g, s.dims)
+    res = compare(o, g, s.dims, s.radii)
     assert (o.owner() != own0).sum() > 0
     _check_fp64(res)
 
@@ -141,15 +138,13 @@ def test_large_particle_near_half_box_fp64():
 def test_spinodal_fp32():
     s = W.spinodal_system(dims=(64, 48, 40), seed=18)
     _, _, res = _run(s, 100, "fp32")
-    log(f"  fp32 {res}")
-    assert res["e_rho"] <= 1e-5 and res["e_u"] <= 1e-4, res
+    check(res, FP32_GATE)
 
 
 def test_interface_fp32():
     s = W.interface_system()
     _, _, res = _run(s, 100, "fp32")
-    log(f"  fp32 {res}")
-    assert res["e_rho"] <= 1e-5, res
+    check(res, FP32_GATE)
 
 
 @pytest.mark.parametrize("prec", ["fp16_dev", "bf16_dev"])
@@ -157,8 +152,7 @@ def test_spinodal_reduced_storage(prec):
     s = W.spinodal_system(dims=(64, 48, 40), seed=19)
     o, g, res = _run(s, 100, prec)
     log(f"  {prec} {res}")
-    gate = 1e-3 if prec == "fp16_dev" else 2e-2
-    assert res["e_rho"] <= gate, res
+    assert res["e_rho"] <= RED_GATE, res
 
 
 @pytest.mark.parametrize("prec", ["fp16_dev", "bf16_dev"])
@@ -177,8 +171,7 @@ def test_bijel_reduced_storage(prec):
     both = (own == -1) & (gown == -1)
     e_rho = max(np.abs(ga - ra)[both].max() / np.abs(ra).max(), np.abs(gb - rb)[both].max() / np.abs(rb).max())
     log(f"  e_rho on nodes fluid in both: {e_rho:.3e}")
-    gate = 1e-3 if prec == "fp16_dev" else 2e-2
-    assert e_rho <= gate, res
+    assert e_rho <= RED_GATE, res
     assert res["owner_diff"] <= 10, res
     assert res["e_pos"] <= 1e-4, res
 
@@ -270,7 +263,7 @@ def test_particles_added_mid_run_fp64():
         x.step(30)
         x.add_ellipsoids(s.radii[h:], s.pos[h:], s.quat[h:], s.delta_rho[h:], s.density[h:])
         x.step(30)
-    _check_fp64(compare(o, g, s.dims))
+    _check_fp64(compare(o, g, s.dims, s.radii))
 
 
 def test_node_touching_three_particles_fp64():
@@ -343,15 +336,35 @@ def test_row_kernel_widths(nx, prec, particles):
     if prec == "fp64":
         _check_fp64(res)
     elif prec == "fp32":
-        log(f"  fp32 {res}")
-        assert res["e_rho"] <= 1e-5 and res["owner_equal"], res
+        check(res, FP32_GATE)
     else:
         log(f"  {prec} {res}")
-        assert res["e_rho"] <= 1e-3 and res["owner_equal"], res
+        assert res["e_rho"] <= RED_GATE and res["owner_equal"], res
 
 
+@pytest.mark.timeout(900)
 def test_bijel_full_size_fp64():
-    """The full 256^3 bijel workload with its 4694 ellipsoids, a few steps."""
+    """The full 256^3 bijel workload with its 4694 ellipsoids, 100 steps
+    against the oracle (stepped in chunks with a progress line each); the
+    particles move far enough for nodes to change owner."""
+    import oracle
+    from paper_1109_3277_amd.binding import Lattice
+
     s = W.bijel_system()
-    _, _, res = _run(s, 3)
+    log(f"case bijel 256^3 np={s.n_particles} steps=100 (oracle in chunks of 10)")
+    o = oracle.Oracle(s.dims, s.tau, s.g_br, s.psi_kind)
+    o.init_fields(s.rho_a, s.rho_b)
+    o.add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
+    own0 = o.owner().copy()
+    for k in range(10):
+        o.step(10)
+        log(f"  oracle step {10 * (k + 1)}")
+    g = Lattice(s.dims, s.tau, s.g_br, s.psi_kind, "fp64", max_particles=s.n_particles, max_radius=s.max_radius)
+    g.init_fields(s.rho_a, s.rho_b)
+    g.add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
+    g.step(100)
+    res = compare(o, g, s.dims, s.radii)
+    flips = int((o.owner() != own0).sum())
+    log(f"  owner changes over 100 steps: {flips}")
+    assert flips > 0
     _check_fp64(res)

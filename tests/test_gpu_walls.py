@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from paper_1109_3277_amd import workloads as W
-from tests.parity_util import compare, log
+from tests.parity_util import check, compare, log
 
 pytestmark = pytest.mark.gpu
 
@@ -40,9 +40,7 @@ def _pair(dims, tau, g, ra, rb, mask, wall_u=None, accel=None, precision="fp64",
 
 
 def _check(res, gate):
-    log(f"  parity {res}")
-    assert res["owner_equal"] and res["n_fluid_equal"], res
-    assert res["e_rho"] <= gate and res["e_u"] <= gate, res
+    check(res, gate, vel_gate=1e-10 if gate < 1e-10 else gate)
 
 
 def test_poiseuille_resting_walls_fp64():
@@ -81,7 +79,7 @@ def test_walls_with_particle_fp64():
     o, g = _pair(dims, 1.0, 0.08, ra, rb, _walls(dims), accel=[2e-5, 1e-5, 0.0], particles=parts, max_radius=6.0)
     o.step(120)
     g.step(120)
-    res = compare(o, g, dims)
+    res = compare(o, g, dims, parts["radii"])
     _check(res, 1e-12)
     assert res["e_pos"] <= 1e-12 and res["e_vel"] <= 1e-10, res
     assert np.abs(g.read_particles()["pos"] - parts["pos"]).max() > 0
