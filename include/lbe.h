@@ -270,6 +270,23 @@ int lb_batch_tune(lb_handle* batch, lb_tune_result* out);
  * of steps (all run by that one graph launch) and of kernel nodes. */
 int lb_batch_last_graph(const lb_handle* batch, int32_t* steps, int64_t* kernel_nodes);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the diagnostics of
+ * lb_stats, computed on the GPU into the caller's DEVICE memory dev_out and
+ * enqueued on the handle's stream without waiting. A lone handle writes its 8
+ * values (the order of lb_stats); a batch handle writes nsys x 8, system by
+ * system. Nothing is allocated on the host or the device: the per-block
+ * partial sums live in a static device array of the library, 256 blocks x 8
+ * doubles for each of up to LB_NOALLOC_MAX_SYSTEMS systems (4 MiB), which
+ * every GPU the library runs on holds until the process ends. A batch of more
+ * systems is rejected (LB_EINVAL). Each call rewrites every partial before it
+ * reads it; calls that overlap on one GPU race on that array. Values equal
+ * lb_stats's to rounding (the partial sums are grouped differently); the
+ * fluid count, health flag and removed mass match exactly. LB_ESTATE on a
+ * system handle of a batch (call it on the batch) or before lb_init_fields. */
+#define LB_NOALLOC_MAX_SYSTEMS 256
+int lb_stats_noalloc(lb_handle* h, double* dev_out);
+
 /* Message of the last failed call on h (or of the last failed lb_create or
  * lb_create_batch when h is NULL); valid until the next call on the same
  * handle. */

@@ -22,7 +22,7 @@ EXPORTED = [
     "lb_set_body_accel", "lb_set_static_solid", "lb_set_pair_interactions", "lb_state_bytes", "lb_save_state", "lb_load_state", "lb_last_error",
     "lb_profile_enable", "lb_profile_read", "lb_batch_workspace_bytes", "lb_create_batch", "lb_init_fields_sys",
     "lb_add_ellipsoids_sys", "lb_read_fields_sys", "lb_read_particles_sys", "lb_stats_sys", "lb_batch_size",
-    "lb_batch_system", "lb_batch_tune", "lb_batch_last_graph",
+    "lb_batch_system", "lb_batch_tune", "lb_batch_last_graph", "lb_stats_noalloc",
 ]
 PHASES = ["density", "shell", "fused", "forces", "bodies", "raster", "killfill"]
 
@@ -97,6 +97,7 @@ def load_library():
     L.lb_batch_system.argtypes = [vp, C.c_int32, C.POINTER(vp)]
     L.lb_batch_tune.argtypes = [vp, C.POINTER(lb_tune_result)]
     L.lb_batch_last_graph.argtypes = [vp, ip, C.POINTER(C.c_int64)]
+    L.lb_stats_noalloc.argtypes = [vp, vp]
     _lib = L
     return L
 
