@@ -85,10 +85,32 @@ def _lattice(s, prec):
     return g
 
 
-def run_gpu(s, prec, steps, warmup, profile_steps=PROFILE_STEPS, keep_fields=False):
+def domain_size_bytes_per_node(prec: str) -> int:
+    """Algorithmic bytes of one lb_domain_size call per node: the order
+    parameter pass reads 2 x 19 populations, the owner code and the bounce mask
+    and writes phi (8 B); each of the three line passes reads phi once."""
+    return 2 * 19 * STORE[prec] + 4 + 4 + 8 + 3 * 8
+
+
+def run_domain_size(g, s, prec, calls=5):
+    """Eq. (12) on the lattice's current state: `calls` timed lb_domain_size
+    calls (each ends with its own synchronisation)."""
+    g.domain_size()  # warm-up
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        out = g.domain_size()
+    ms = 1e3 * (time.perf_counter() - t0) / calls
+    per = domain_size_bytes_per_node(prec) * s.N
+    return {"L": [round(float(v), 4) for v in out[:4]], "ms_per_call": round(ms, 3), "calls": calls,
+            "algorithmic_bytes_per_call": per, "alg_gbs": round(per / (ms / 1e3) / 1e9, 1),
+            "hbm_frac_alg": round(per / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def run_gpu(s, prec, steps, warmup, profile_steps=PROFILE_STEPS, keep_fields=False, analysis=False):
     """Warm-up, then `steps` timed steps with per-kernel profiling off, then
     `profile_steps` steps with HIP events around every launch (per-kernel
-    average durations for the roofline)."""
+    average durations for the roofline); with `analysis`, the domain size of
+    Eq. (12) timed on the final state."""
     import torch
 
     g = _lattice(s, prec)
@@ -113,6 +135,8 @@ def run_gpu(s, prec, steps, warmup, profile_steps=PROFILE_STEPS, keep_fields=Fal
         out["prof"] = g.profile_read()
         g.profile(False)
         g.step(0)
+    if analysis:
+        out["domain_size"] = run_domain_size(g, s, prec)
     g.close()
     del g
     torch.cuda.empty_cache()
@@ -318,7 +342,7 @@ def main():
 
     keep = not args.no_forms
     log(f"timing {args.precision}: warmup {args.warmup}, steps {args.steps}, then {PROFILE_STEPS} event-timed steps")
-    main_res, main_fields = run_gpu(s, args.precision, args.steps, args.warmup, keep_fields=keep)
+    main_res, main_fields = run_gpu(s, args.precision, args.steps, args.warmup, keep_fields=keep, analysis=True)
     log(f"  {main_res['mlups']:.1f} MLUPS, {main_res['ms_per_step']:.3f} ms/step, phases {main_res['prof']}")
     traffic = measured_traffic(args.workload, args.precision)
     roof = roofline_of(s, args.precision, main_res, traffic)
@@ -366,6 +390,7 @@ def main():
         "roofline": roof,
         "step_hbm_frac_alg": round(value * 1e6 * step_bytes_per_node(args.precision) / 1e9 / HBM_PEAK_GBS, 4),
         "phases_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in main_res["prof"].items()},
+        "domain_size": main_res["domain_size"],
         "cpu_baseline": cpu,
         "forms": forms,
         "other_workloads": other,

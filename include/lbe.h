@@ -148,6 +148,21 @@ int lb_read_particles(lb_handle* h, double* pos, double* quat, double* vel, doub
  * out is the caller's host array of 8 doubles. Synchronises the stream. */
 int lb_stats(lb_handle* h, double out[8]);
 
+/* Lateral domain size of the order parameter phi~ = rho_A - rho_B (Sec. 4,
+ * Eq. (12)), FP64, deterministic order: out[0..7] = {L_x, L_y, L_z,
+ * L = (L_x + L_y + L_z) / 3, <k_x^2>, <k_y^2>, <k_z^2>, sum_k S(k)}, with
+ * S(k) = |phi'_k|^2 / N the structure function of the fluctuation phi' =
+ * phi~ - <phi~> (the squared modulus), k_i = 2 pi n_i / L_i in the symmetric
+ * range, <k_i^2> = sum_k k_i^2 S(k) / sum_k S(k), L_i = 2 pi / sqrt(<k_i^2>).
+ * Particle and wall nodes hold no fluid and count as phi~ = 0. A component
+ * with no variation along its axis gives L_i = +inf; a uniform field gives
+ * NaN. out is the caller's host array of 8 doubles. Uses the idle population
+ * copy as staging (the state is unchanged). Synchronises the stream.
+ * LB_EINVAL if a box side exceeds LB_DOMAIN_MAX_LINE; LB_ESTATE on a batch
+ * handle (call it on a system) or before lb_init_fields. */
+#define LB_DOMAIN_MAX_LINE 2048
+int lb_domain_size(lb_handle* h, double out[8]);
+
 /* Uniform body acceleration a (3 doubles) added to every fluid node's force
  * (test and channel-flow use; default 0). */
 int lb_set_body_accel(lb_handle* h, const double a[3]);

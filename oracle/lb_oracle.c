@@ -28,24 +28,24 @@
  *                     (Sec. 2, Eq. (10) and the text after it).
  *   S3-S4 SC force    F^c = -g_br Psi^c(x) sum_{i=1..18} Psi^cbar(x+c_i) c_i
  *                     (Sec. 2, Eq. (3); only the cross coupling g_AB = g_br,
- *                     unweighted sum over the 18 neighbours, R4/R5/R7).
+ *                     unweighted sum over the 18 neighbours).
  *   S5 collision      BGK, Eq. (2), with the Shan-Chen common velocity
  *                     u' = (j^A+j^B)/(rho^A+rho^B) shifted per component by
- *                     tau F^c / rho^c (R8); f^eq standard 2nd order (R1).
+ *                     tau F^c / rho^c; f^eq standard 2nd order.
  *   S6 stream / BB    Eq. (1) to fluid targets; moving bounce-back Eq. (4)
  *                     with C = 6 w_i rho^c(x) (u_b . c_ibar) at solid targets,
  *                     and the momentum-exchange force of Eq. (5) built from
- *                     the post-collision population (R11), surface velocity
- *                     at the link midpoint (R12).
+ *                     the post-collision population, surface velocity
+ *                     at the link midpoint.
  *   S7 rigid bodies   Newton-Euler with dt = 1, symplectic Euler for the
  *                     centre, space-frame angular momentum and a quaternion
- *                     exponential map for the orientation (Sec. 2, R18).
+ *                     exponential map for the orientation (Sec. 2).
  *   S8 raster + kill/fill   new owner map from the moved ellipsoids (closed
  *                     test Q <= 1, smallest index wins); fluid that ends up
  *                     inside a particle is removed and its momentum handed to
  *                     the particle; uncovered nodes are refilled with f^eq of
  *                     the neighbour-mean density and the surface velocity, the
- *                     momentum taken from the particle (R17).
+ *                     momentum taken from the particle.
  */
 #include <math.h>
 #include <stdint.h>
@@ -79,7 +79,7 @@ static const int CX[NQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 
 static const int CY[NQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 static const int CZ[NQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
 
-/* Lattice weights (the alpha_{c_i} of Eq. (4)) and c_s^2 = 1/3 (R2). */
+/* Lattice weights (the alpha_{c_i} of Eq. (4)) and c_s^2 = 1/3. */
 static double wgt(int i) {
     if (i == 0) return 1.0 / 3.0;
     if (i <= 6) return 1.0 / 18.0;
@@ -171,7 +171,7 @@ static double minimg(double d, int Lx) {
     return d;
 }
 
-/* Standard second-order D3Q19 equilibrium (R1): its zeroth, first and second
+/* Standard second-order D3Q19 equilibrium: its zeroth, first and second
  * moments are rho, rho u and rho c_s^2 I + rho u u. */
 static void feq(double rho, const double u[3], double out[NQ]) {
     double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
@@ -181,7 +181,7 @@ static void feq(double rho, const double u[3], double out[NQ]) {
     }
 }
 
-/* Effective mass Psi of Eq. (3) (R4): kind 0 Psi = rho, kind 1 Psi = 1-exp(-rho). */
+/* Effective mass Psi of Eq. (3): kind 0 Psi = rho, kind 1 Psi = 1-exp(-rho). */
 static double psi(const orc_t *s, double r) {
     if (s->psi_kind == 0) return r;
     return -expm1(-r);
@@ -221,10 +221,10 @@ static void qnormalize(double q[4]) {
     q[3] = q[3] / n;
 }
 
-/* Closed inside test of an ellipsoid (R20): with d = minimum-image offset of
+/* Closed inside test of an ellipsoid: with d = minimum-image offset of
  * the node from the centre and d_b = R(q)^T d its body-frame coordinates,
  * the node is inside when (d_bx^2 + d_by^2)/Rperp^2 + d_bz^2/Rpar^2 <= 1.
- * The body z axis is the symmetry axis (R22). Evaluated in this fixed order
+ * The body z axis is the symmetry axis. Evaluated in this fixed order
  * without contraction so the owner map is a function of the inputs. */
 static int inside(const orc_t *s, const particle *p, const double R[3][3], int x, int y, int z) {
     double dx = minimg((double)x - p->X[0], s->nx);
@@ -289,7 +289,7 @@ void orc_destroy(orc_t *s) {
     free(s);
 }
 
-/* Initial populations f = f^eq(rho, u) on fluid nodes (R32). u may be NULL. */
+/* Initial populations f = f^eq(rho, u) on fluid nodes. u may be NULL. */
 void orc_init_fields(orc_t *s, const double *rho_a, const double *rho_b, const double *u) {
     const double *rr[2] = {rho_a, rho_b};
     for (int c = 0; c < 2; c++) {
@@ -335,7 +335,7 @@ void orc_set_accel(orc_t *s, const double a[3]) {
 }
 
 static void particle_derived(particle *p) {
-    /* Continuous ellipsoid of density dens (R19): M = dens * 4/3 pi Rpar Rperp^2,
+    /* Continuous ellipsoid of density dens: M = dens * 4/3 pi Rpar Rperp^2,
      * principal moments about the body axes. */
     p->M = p->dens * (4.0 / 3.0) * M_PI * p->Rpar * p->Rperp * p->Rperp;
     p->Iperp = p->M * (p->Rperp * p->Rperp + p->Rpar * p->Rpar) / 5.0;
@@ -350,7 +350,7 @@ static void axis_range(double c, double rb, int *lo, int *hi) {
 }
 
 /* Rasterise particle k into owner map o (only onto fluid nodes or nodes of a
- * larger index: smallest index wins, R20). */
+ * larger index: smallest index wins). */
 static void raster_one(const orc_t *s, int k, int *o) {
     const particle *p = &s->P[k];
     double R[3][3];
@@ -372,7 +372,7 @@ static void raster_one(const orc_t *s, int k, int *o) {
 }
 
 /* Add n ellipsoids (radii n x 2: Rpar, Rperp; pos n x 3; quat n x 4 (w,x,y,z);
- * drho n; dens n or NULL -> 1). Covered fluid is removed (R16). Returns 0, or
+ * drho n; dens n or NULL -> 1). Covered fluid is removed. Returns 0, or
  * -6 when a bounding radius is not below half the shortest box side, a radius
  * is not positive or a value is not finite. */
 int orc_add_ellipsoids(orc_t *s, int n, const double *radii, const double *pos, const double *quat,
@@ -555,7 +555,7 @@ void orc_stage_collide(orc_t *s) {
 
 /* Bounce-back term C of Eq. (4) for the link from fluid node n along c_i into
  * solid node m (component c): C = 2 w_i / c_s^2 rho^c(n) u_b . c_ibar, with
- * u_b the surface velocity at the link midpoint (R12, R13). Also returns the
+ * u_b the surface velocity at the link midpoint. Also returns the
  * lever arm r of the midpoint (particles only). */
 static double link_C(const orc_t *s, long n, int i, int c, long m, double r[3]) {
     double ub[3] = {0.0, 0.0, 0.0};
@@ -587,7 +587,7 @@ static double link_C(const orc_t *s, long n, int i, int c, long m, double r[3]) 
  *   m fluid: fn_i(m)    = f*_i(n)
  *   m solid: fn_ibar(n) = f*_i(n) + C
  * The particle owning m receives (2 f*_i(n) + C) c_i and the torque r x that,
- * Eq. (5), written with the reflected population of Eq. (4) as f*_i (R11). */
+ * Eq. (5), written with the reflected population of Eq. (4) as f*_i. */
 void orc_stage_stream(orc_t *s) {
     long N = s->N;
     /* Every population of a fluid node is written below (by a push from its
@@ -660,15 +660,17 @@ void orc_stage_stream(orc_t *s) {
  *                                                   + (r.o_i - r.o_j)^2 / (1 - chi o_i.o_j)])
  * with sigma_bar = 2 R_o, eps_bar = K_H sigma_bar^{5/2}, chi = (R_p^2 - R_o^2) /
  * (R_p^2 + R_o^2), o the body axis and r the unit centre-to-centre vector
- * (reading R36: for two particles of different shape, R_p and R_o are the
- * means of the pair's). Force F_i = -d phi / d X_i, torque T_i = -o_i x
- * d phi / d o_i.
+ * (the paper treats equal particles; for two particles of different shape,
+ * R_p and R_o are read as the means of the pair's). Force F_i = -d phi /
+ * d X_i, torque T_i = -o_i x d phi / d o_i.
  *
  * Lubrication (Eq. (9)): for a gap h = r - sigma(o_i, o_j, r) below Delta_c,
  * F_i = -(3 pi mu R^2 / 2) r (r.(V_i - V_j)) (1/h - 1/Delta_c) on i and -F_i on
  * j, with R = sigma / 2 and mu = (rho_A + rho_B) (tau - 1/2) / 3 from the
- * initial mean densities; the force opposes the normal relative motion
- * (reading R37) and the gap is taken no smaller than Delta_c / 4 (reading R38). */
+ * initial mean densities; the force opposes the normal relative motion (a
+ * sign the printed equation leaves implicit), and the gap is taken no smaller
+ * than Delta_c / 4 (not in the paper: it keeps the force finite when two
+ * particles overlap). */
 static void body_axis(const particle *p, double o[3]) {
     double R[3][3];
     qrot(p->q, R);
@@ -805,7 +807,7 @@ void orc_set_particle_pose(orc_t *s, int k, const double X[3], const double q[4]
 
 /* ---------------------------------------------------------------- S7 */
 /* Newton-Euler update with dt = 1 (Sec. 2: the particles obey Newton's
- * equations, integrated as in molecular dynamics; integrator R18):
+ * equations, integrated as in molecular dynamics):
  *   F = F_links + J + F_pairs, T = T_links + H + T_pairs, J = H = 0
  *   V += F / M, X = wrap(X + V), L += T
  *   W = R(q) I_b^-1 R(q)^T L  (old q)
@@ -862,7 +864,7 @@ void orc_stage_bodies(orc_t *s) {
 }
 
 /* ---------------------------------------------------------------- S8 */
-/* New owner map from the moved particles, then kill / fill (R17):
+/* New owner map from the moved particles, then kill / fill:
  *  kill (fluid -> particle p): J_p += sum_c j^c(n), H_p += r x that, the
  *       populations at n are removed;
  *  fill (particle p -> fluid): rho_new^c = mean of rho^c over the neighbours
@@ -977,7 +979,7 @@ void orc_stream_only(orc_t *s) {
 /* ---------------------------------------------------------------- readout */
 
 /* Densities and barycentric velocity (j^A + j^B)/(rho^A + rho^B) of the
- * current populations (R9); solid nodes read 0. Any pointer may be NULL. */
+ * current populations; solid nodes read 0. Any pointer may be NULL. */
 void orc_read_fields(const orc_t *s, double *rho_a, double *rho_b, double *u, int *owner) {
     long N = s->N;
     for (long n = 0; n < N; n++) {

@@ -22,7 +22,7 @@ EXPORTED = [
     "lb_set_body_accel", "lb_set_static_solid", "lb_set_pair_interactions", "lb_state_bytes", "lb_save_state", "lb_load_state", "lb_last_error",
     "lb_profile_enable", "lb_profile_read", "lb_batch_workspace_bytes", "lb_create_batch", "lb_init_fields_sys",
     "lb_add_ellipsoids_sys", "lb_read_fields_sys", "lb_read_particles_sys", "lb_stats_sys", "lb_batch_size",
-    "lb_batch_system", "lb_batch_tune", "lb_batch_last_graph", "lb_stats_noalloc",
+    "lb_batch_system", "lb_batch_tune", "lb_batch_last_graph", "lb_stats_noalloc", "lb_domain_size",
 ]
 PHASES = ["density", "shell", "fused", "forces", "bodies", "raster", "killfill"]
 
@@ -98,6 +98,7 @@ def load_library():
     L.lb_batch_tune.argtypes = [vp, C.POINTER(lb_tune_result)]
     L.lb_batch_last_graph.argtypes = [vp, ip, C.POINTER(C.c_int64)]
     L.lb_stats_noalloc.argtypes = [vp, vp]
+    L.lb_domain_size.argtypes = [vp, dp]
     _lib = L
     return L
 
@@ -254,6 +255,12 @@ class Lattice:
     def stats(self):
         o = np.zeros(8)
         self._check(load_library().lb_stats(self._h, _dp(o)))
+        return o
+
+    def domain_size(self):
+        """Eq. (12): [L_x, L_y, L_z, L, <k_x^2>, <k_y^2>, <k_z^2>, sum_k S(k)]."""
+        o = np.zeros(8)
+        self._check(load_library().lb_domain_size(self._h, _dp(o)))
         return o
 
     def profile(self, on: bool):

@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "liblbe.so")
 PROBE_LIB = os.path.join(HERE, "liblbe_probe.so")
 PROBE_SRC = os.path.join(CSRC, "probe", "lbe_probe.hip")
 SOURCES = ["lbe_fluid.hip", "lbe_particles.hip", "lbe_pairs.hip", "lbe_runtime.hip", "lbe_batch.hip",
-           "lbe_noalloc.hip"]
+           "lbe_noalloc.hip", "lbe_analysis.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -145,6 +145,25 @@ __device__ inline int wrapc(int a, int n) { return a < 0 ? a + n : (a >= n ? a -
 __device__ inline uint32_t upstream(int nx, int ny, int nz, int x, int y, int z, int i) {
     return (uint32_t)(wrapc(x - cx(i), nx) + nx * (wrapc(y - cy(i), ny) + ny * wrapc(z - cz(i), nz)));
 }
+// Plane and node holding population i of fluid node n (coordinates x, y, z)
+// after streaming, given its bounce mask bm.
+__device__ inline void pop_src(const Box& bx, uint32_t n, int x, int y, int z, uint32_t bm, int i, int& plane,
+                               uint32_t& node) {
+    if ((bm >> i) & 1u) {
+        plane = opp(i);
+        node = upstream(bx.nx, bx.ny, bx.nz, x, y, z, i);
+    } else {
+        plane = i;
+        node = n;
+    }
+}
+__device__ inline void node_xyz(const Box& bx, uint32_t n, int& x, int& y, int& z) {
+    const uint32_t pl = (uint32_t)bx.nx * (uint32_t)bx.ny;
+    z = (int)(n / pl);
+    const uint32_t r = n - (uint32_t)z * pl;
+    y = (int)(r / (uint32_t)bx.nx);
+    x = (int)(r - (uint32_t)y * (uint32_t)bx.nx);
+}
 // periodic wrap of any integer coordinate
 __device__ inline int wrapc_any(int a, int n) {
     a %= n;

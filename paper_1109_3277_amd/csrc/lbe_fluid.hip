@@ -28,26 +28,6 @@ __device__ inline R feq_i(int i, R rho, R ux, R uy, R uz, R uu) {
     return R(wq(i)) * rho * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
 }
 
-// Plane and node holding population i of fluid node n (coordinates x, y, z)
-// after streaming, given its bounce mask bm.
-__device__ inline void pop_src(const Box& bx, uint32_t n, int x, int y, int z, uint32_t bm, int i, int& plane,
-                               uint32_t& node) {
-    if ((bm >> i) & 1u) {
-        plane = opp(i);
-        node = upstream(bx.nx, bx.ny, bx.nz, x, y, z, i);
-    } else {
-        plane = i;
-        node = n;
-    }
-}
-__device__ inline void node_xyz(const Box& bx, uint32_t n, int& x, int& y, int& z) {
-    const uint32_t pl = (uint32_t)bx.nx * (uint32_t)bx.ny;
-    z = (int)(n / pl);
-    const uint32_t r = n - (uint32_t)z * pl;
-    y = (int)(r / (uint32_t)bx.nx);
-    x = (int)(r - (uint32_t)y * (uint32_t)bx.nx);
-}
-
 // ---------------------------------------------------------------- S1
 // rho^c(n) = sum_i f_i^c(n) on fluid nodes (rho_ref^c + sum_i h_i^c in the
 // deviation forms), stored as the effective mass

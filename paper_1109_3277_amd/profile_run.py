@@ -27,6 +27,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--domain-size", type=int, default=0, help="calls of the Eq. (12) domain-size pass afterwards")
     a = ap.parse_args()
     import torch
 
@@ -42,6 +43,8 @@ def main():
     g.step(a.warmup)
     g.step(a.steps)
     print(f"ran {a.workload} {a.precision}: {a.warmup} + {a.steps} steps, N = {s.N}", flush=True)
+    for _ in range(a.domain_size):
+        print(f"domain size {g.domain_size()[:4].tolist()}", flush=True)
     if a.copy_mib:
         n = a.copy_mib << 20
         src = torch.ones(n // 4, dtype=torch.float32, device="cuda")

@@ -40,7 +40,7 @@ def _csvs(d, suffix):
 def _short(name: str) -> str:
     """Kernel name without the namespace and argument list, template arguments kept."""
     n = re.sub(r"^void\s+", "", name)
-    n = n.replace("lbe::", "")
+    n = n.replace("lbe::", "").replace("(anonymous namespace)::", "")
     depth, out = 0, []
     for ch in n:  # drop the parameter list after the template arguments
         if ch == "<":

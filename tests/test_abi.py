@@ -132,3 +132,12 @@ def test_pair_interactions_reject_bad_handles(lib):
 def test_device_readout_rejects_bad_handles(lib):
     from paper_1109_3277_amd import binding as B
     assert lib.lb_read_fields_dev(None, None, None, None, None) == B.LB_EINVAL
+
+
+def test_domain_size_and_noalloc_stats_reject_bad_handles(lib):
+    """Eq. (12) observable and the allocation-free diagnostics: no handle or
+    no output is rejected before any GPU work."""
+    from paper_1109_3277_amd import binding as B
+    out = (C.c_double * 8)()
+    assert lib.lb_domain_size(None, out) == B.LB_EINVAL
+    assert lib.lb_stats_noalloc(None, None) == B.LB_EINVAL
