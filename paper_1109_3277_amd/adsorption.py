@@ -1,15 +1,25 @@
 """Observables of a single particle at a fluid-fluid interface (Sec. 4):
 the adsorption trajectory z(t), phi(t) of an ellipsoid, and the equilibrium
-height of a coloured sphere, from which the contact angle follows (Eq. (11)).
+height of a coloured sphere, from which the contact angle follows (Sec. 2,
+the calibration of Eq. (11)).
 
 Every step runs in the HIP library; this module only reads the particle
 state and the density field between steps.
 
 z is the distance of the particle centre from the interface, positive on the
-blue side; the interface level is where rho_A = rho_B, found by linear
-interpolation along z in the columns of the box's x-y corner region (farthest
-from the particle) and averaged. phi is the angle between the particle's
-symmetry axis and the interface normal z, in [0, 90] degrees.
+blue side (component B, above the red lamella in these boxes); the interface
+level is where rho_A = rho_B, found by linear interpolation along z in the
+columns of the box's x-y corner region (farthest from the particle) and
+averaged. phi is the angle between the particle's symmetry axis and the
+interface normal z, in [0, 90] degrees.
+
+Contact angle: a sphere of radius R whose centre rests at height h above a
+flat interface meets it at the angle Theta with cos(Theta) = -h / R, measured
+through the red phase: a sphere sitting mostly in the blue phase (h > 0) has
+Theta > 90 degrees. The colour Delta rho > 0 drives the sphere into the blue
+phase in this method (the shell's extra red density repels the blue fluid,
+and the particle feels the fluid only through Eq. (5)), so this convention
+gives Theta rising with Delta rho, the sign of the paper's linear fit.
 """
 from __future__ import annotations
 
@@ -59,3 +69,38 @@ def trajectory(lat, steps: int, every: int):
         lat.step(n)
         t += n
     return np.array(out)
+
+
+def sphere_height(lat) -> float:
+    """Height of particle 0's centre above the interface (blue side positive)."""
+    ra, rb, _, _ = lat.read_fields()
+    return float(lat.read_particles()["pos"][0, 2] - interface_level(ra, rb, lat.dims))
+
+
+def equilibrium_height(lat, steps: int, every: int, tail: int):
+    """Advance `steps` steps and return the mean and the standard deviation of
+    the sphere height over the last `tail` steps, sampled every `every`."""
+    hs = []
+    t = 0
+    while t < steps:
+        n = min(every, steps - t)
+        lat.step(n)
+        t += n
+        if t > steps - tail:
+            hs.append(sphere_height(lat))
+    hs = np.array(hs)
+    return float(hs.mean()), float(hs.std())
+
+
+def contact_angle_deg(h: float, radius: float) -> float:
+    """Theta of a sphere resting at height h (blue side positive) above the
+    interface, measured through the red phase: cos(Theta) = -h / R."""
+    return math.degrees(math.acos(max(-1.0, min(1.0, -h / radius))))
+
+
+def fit_line(x, y):
+    """Least-squares line y = a x + b: (a, b, largest |residual|)."""
+    x, y = np.asarray(x, float), np.asarray(y, float)
+    A = np.stack([x, np.ones_like(x)], 1)
+    (a, b), *_ = np.linalg.lstsq(A, y, rcond=None)
+    return float(a), float(b), float(np.abs(A @ np.array([a, b]) - y).max())

@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 output for the profiles/ folder.
 
-    python paper_1109_3277_amd/profile_summary.py trace  <trace_dir> --title T --cmd C > out.md
+    python paper_1109_3277_amd/profile_summary.py trace  <trace_dir> --title T --cmd C [--by-grid] > out.md
     python paper_1109_3277_amd/profile_summary.py traffic <fetch_dir> <write_dir> --kernel K \
         --workload W --precision P --nodes N --bytes-per-node B --cmds C1 C2 > out.md  (+ --json out.json)
 
@@ -53,7 +53,30 @@ def _short(name: str) -> str:
     return "".join(out).strip()
 
 
+def trace_by_grid(args):
+    """Per (kernel, grid) statistics from the per-dispatch trace, so that one
+    kernel launched on boxes of different sizes is reported per box."""
+    groups = {}
+    for f in _csvs(args.dir, "kernel_trace.csv"):
+        for r in csv.DictReader(open(f)):
+            grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+            d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            groups.setdefault((_short(r["Kernel_Name"]), grid), []).append(d)
+    print(f"# {args.title}\n")
+    print("Command (from the repository root, on one MI355X):\n")
+    print(f"    {args.cmd}\n")
+    print("Per kernel and launch grid (work-items), from the per-dispatch trace.\n")
+    print("| kernel | grid | calls | average (us) | min (us) | max (us) | total (ms) |")
+    print("|---|---|---|---|---|---|---|")
+    for (k, g), v in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+        if sum(v) < args.min_total_us:
+            continue
+        print(f"| {k} | {g} | {len(v)} | {sum(v) / len(v):.1f} | {min(v):.1f} | {max(v):.1f} | {sum(v) / 1e3:.2f} |")
+
+
 def trace(args):
+    if args.by_grid:
+        return trace_by_grid(args)
     rows = []
     for f in _csvs(args.dir, "kernel_stats.csv"):
         for r in csv.DictReader(open(f)):
@@ -126,6 +149,8 @@ def main():
     t.add_argument("dir")
     t.add_argument("--title", required=True)
     t.add_argument("--cmd", required=True)
+    t.add_argument("--by-grid", action="store_true", help="group the per-dispatch trace by kernel and grid")
+    t.add_argument("--min-total-us", type=float, default=0.0, help="omit groups with less total time (by-grid)")
     p = sub.add_parser("traffic")
     p.add_argument("fetch_dir")
     p.add_argument("write_dir")
