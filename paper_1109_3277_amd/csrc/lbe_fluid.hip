@@ -8,6 +8,7 @@
 // of 64x4 (or 32x8) nodes of one xy-plane per 256-thread block, tiles of
 // neighbouring z on the same XCD.
 #include <algorithm>
+#include <type_traits>
 
 #include "lbe_internal.h"
 
@@ -361,29 +362,43 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
     } else {
         // U_n of the first two particles each fluid lane links to: the wave
         // visits the distinct particles among them one at a time, reading
-        // each one's centre and velocities with wave-uniform loads. Links to
-        // a third particle of the same node (rare) read it per lane. Walls do
-        // not move (C = 0).
-        uint32_t on[Q];
+        // each one's centre and velocities with wave-uniform loads. Walls do
+        // not move unless the box says so. Links to further particles of the
+        // same node (rare) read them per lane in the 4- and 8-byte forms. The
+        // 2-byte forms defer them until after the pushes (see below) and do
+        // the link arithmetic in float (their stored deviations carry 8 to 11
+        // bits): this keeps them within 128 VGPRs, four waves per SIMD.
+        constexpr bool kDefer = sizeof(S) == 2;
+        using L = typename std::conditional<kDefer, float, double>::type;
+        uint32_t on[Q];  // owner codes of the links, held in registers unless deferring
+        auto own = [&](int i) -> uint32_t {
+            if constexpr (kDefer)
+                return s_own[LBE_LS(i)];
+            else
+                return on[i];
+        };
         uint32_t p1 = OWN_FLUID;
         uint32_t mask = 0u;  // the node's bounce mask in the written copy
 #pragma unroll
         for (int i = 1; i < Q; i++) {
-            on[i] = s_own[LBE_LS(i)];
-            p1 = (fluid && p1 == OWN_FLUID && on[i] < OWN_WALL) ? on[i] : p1;
-            mask |= (on[i] != OWN_FLUID ? 1u : 0u) << opp(i);
+            const uint32_t o = s_own[LBE_LS(i)];
+            if constexpr (!kDefer) on[i] = o;
+            p1 = (fluid && p1 == OWN_FLUID && o < OWN_WALL) ? o : p1;
+            mask |= (o != OWN_FLUID ? 1u : 0u) << opp(i);
         }
         bm_out[n] = fluid ? mask : 0u;
         uint32_t p2 = OWN_FLUID;
 #pragma unroll
-        for (int i = 1; i < Q; i++)
-            p2 = (fluid && p2 == OWN_FLUID && on[i] < OWN_WALL && on[i] != p1) ? on[i] : p2;
+        for (int i = 1; i < Q; i++) {
+            const uint32_t o = own(i);
+            p2 = (fluid && p2 == OWN_FLUID && o < OWN_WALL && o != p1) ? o : p2;
+        }
         // per particle slot: surface velocity U_n at this node and the
         // node's cell in the particle's link records
-        double Ux2 = 0.0, Uy2 = 0.0, Uz2 = 0.0;
+        L Ux2 = L(0), Uy2 = L(0), Uz2 = L(0);
         int cb2 = -1;
         bool need2 = p2 < OWN_WALL;
-        double Ux1 = 0.0, Uy1 = 0.0, Uz1 = 0.0;
+        L Ux1 = L(0), Uy1 = L(0), Uz1 = L(0);
         int cb1 = -1;
         bool need = p1 < OWN_WALL;
         const int Ls[3] = {nx, ny, nz};
@@ -399,9 +414,9 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
             const double qWx = pq[PF_W], qWy = pq[PF_W + 1], qWz = pq[PF_W + 2];
             const double rx = minimg((double)x - qX[0], nx), ry = minimg((double)y - qX[1], ny),
                          rz = minimg((double)z - qX[2], nz);
-            const double ux = qVx + (qWy * rz - qWz * ry);
-            const double uy = qVy + (qWz * rx - qWx * rz);
-            const double uz = qVz + (qWx * ry - qWy * rx);
+            const L ux = L(qVx + (qWy * rz - qWz * ry));
+            const L uy = L(qVy + (qWz * rx - qWx * rz));
+            const L uz = L(qVz + (qWx * ry - qWy * rx));
             int lo[3], sz[3];
             const int cb = box_of(bx, qX, pq[PF_RB], lo, sz) ? rec_cell(xyz, lo, sz, Ls) : -1;
             if (need && p1 == q) {
@@ -423,47 +438,53 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
         // fluid target, the bounced f*_i + C for a solid one, zero from a
         // solid lane. A particle link adds its momentum exchange
         // (2 f*_i + C) c_i to the node's force on that particle: in registers
-        // for the first two particles, in the record itself for others.
-        double F1[3] = {0.0, 0.0, 0.0}, F2[3] = {0.0, 0.0, 0.0};
+        // for the first two particles, in the record itself for others (or,
+        // deferring, not yet: the link is stored without C and marked).
+        L F1[3] = {L(0), L(0), L(0)}, F2[3] = {L(0), L(0), L(0)};
+        uint32_t rare = 0u;  // deferred links
 #pragma unroll
         for (int i = 1; i < Q; i++) {
-            const uint32_t o = on[i];
+            const uint32_t o = own(i);
             R C0 = R(0), C1 = R(0);
             if (fluid && o < OWN_WALL) {
-                double Ux = o == p1 ? Ux1 : Ux2, Uy = o == p1 ? Uy1 : Uy2, Uz = o == p1 ? Uz1 : Uz2;
-                int cb = o == p1 ? cb1 : cb2;
-                if (o != p1 && o != p2) {
-                    const double* po = pfast + (size_t)o * kPF;
-                    const double X[3] = {po[PF_X], po[PF_X + 1], po[PF_X + 2]};
-                    const double rx = minimg((double)x - X[0], nx);
-                    const double ry = minimg((double)y - X[1], ny);
-                    const double rz = minimg((double)z - X[2], nz);
-                    const double wx = po[PF_W], wy = po[PF_W + 1], wz = po[PF_W + 2];
-                    Ux = po[PF_V] + (wy * rz - wz * ry);
-                    Uy = po[PF_V + 1] + (wz * rx - wx * rz);
-                    Uz = po[PF_V + 2] + (wx * ry - wy * rx);
-                    int lo[3], sz[3];
-                    cb = box_of(bx, X, po[PF_RB], lo, sz) ? rec_cell(xyz, lo, sz, Ls) : -1;
-                }
-                const double cu = Ux * cx(i) + Uy * cy(i) + Uz * cz(i);
-                C0 = R(-6.0 * wq(i) * cu) * r0;
-                C1 = R(-6.0 * wq(i) * cu) * r1;
-                // (2 f*_i + C) over both components, in double (f = h + w rho_ref in the deviation forms)
-                const double fsum = (double)f0[i] + (double)f1[i] + (P::dev ? wq(i) * (bx.rref[0] + bx.rref[1]) : 0.0);
-                const double mag = 2.0 * fsum + ((double)C0 + (double)C1);
-                if (o == p1) {
-                    F1[0] += mag * cx(i);
-                    F1[1] += mag * cy(i);
-                    F1[2] += mag * cz(i);
-                } else if (o == p2) {
-                    F2[0] += mag * cx(i);
-                    F2[1] += mag * cy(i);
-                    F2[2] += mag * cz(i);
-                } else if (cb >= 0) {  // a third particle (rare): this lane alone updates the record
-                    double* r = rec + ((size_t)o * rstride + cb) * kRec;
-                    r[0] += mag * cx(i);
-                    r[1] += mag * cy(i);
-                    r[2] += mag * cz(i);
+                if (kDefer && o != p1 && o != p2) {
+                    rare |= 1u << i;
+                } else {
+                    L Ux = o == p1 ? Ux1 : Ux2, Uy = o == p1 ? Uy1 : Uy2, Uz = o == p1 ? Uz1 : Uz2;
+                    int cb = o == p1 ? cb1 : cb2;
+                    if (!kDefer && o != p1 && o != p2) {
+                        const double* po = pfast + (size_t)o * kPF;
+                        const double X[3] = {po[PF_X], po[PF_X + 1], po[PF_X + 2]};
+                        const double rx = minimg((double)x - X[0], nx);
+                        const double ry = minimg((double)y - X[1], ny);
+                        const double rz = minimg((double)z - X[2], nz);
+                        const double wx = po[PF_W], wy = po[PF_W + 1], wz = po[PF_W + 2];
+                        Ux = L(po[PF_V] + (wy * rz - wz * ry));
+                        Uy = L(po[PF_V + 1] + (wz * rx - wx * rz));
+                        Uz = L(po[PF_V + 2] + (wx * ry - wy * rx));
+                        int lo[3], sz[3];
+                        cb = box_of(bx, X, po[PF_RB], lo, sz) ? rec_cell(xyz, lo, sz, Ls) : -1;
+                    }
+                    const L cu = Ux * L(cx(i)) + Uy * L(cy(i)) + Uz * L(cz(i));
+                    C0 = R(L(-6.0 * wq(i)) * cu) * r0;
+                    C1 = R(L(-6.0 * wq(i)) * cu) * r1;
+                    // (2 f*_i + C) over both components (f = h + w rho_ref in the deviation forms)
+                    const L fsum = L(f0[i]) + L(f1[i]) + L(P::dev ? wq(i) * (bx.rref[0] + bx.rref[1]) : 0.0);
+                    const L mag = L(2) * fsum + (L(C0) + L(C1));
+                    if (o == p1) {
+                        F1[0] += mag * L(cx(i));
+                        F1[1] += mag * L(cy(i));
+                        F1[2] += mag * L(cz(i));
+                    } else if (o == p2) {
+                        F2[0] += mag * L(cx(i));
+                        F2[1] += mag * L(cy(i));
+                        F2[2] += mag * L(cz(i));
+                    } else if (cb >= 0) {  // a third particle (rare): this lane alone updates the record
+                        double* r = rec + ((size_t)o * rstride + cb) * kRec;
+                        r[0] += (double)mag * cx(i);
+                        r[1] += (double)mag * cy(i);
+                        r[2] += (double)mag * cz(i);
+                    }
                 }
             } else if (bx.walls == 2 && fluid && o == OWN_WALL) {
                 // a moving wall: the same term with the wall velocity
@@ -487,13 +508,81 @@ __device__ inline void fused_body(const Box& bx, const typename P::S* __restrict
             r[1] = F2[1];
             r[2] = F2[2];
         }
+        if constexpr (kDefer) {
+            // deferred links into further particles: the wave visits those
+            // particles one at a time; a linked lane reads back the value it
+            // has just stored for each such link, adds C, stores it again and
+            // writes its cell of that particle's records. The force then uses
+            // the stored (rounded) f*_i.
+            uint32_t mine = OWN_FLUID;
+#pragma unroll
+            for (int i = 1; i < Q; i++)
+                mine = (((rare >> i) & 1u) && mine == OWN_FLUID) ? s_own[LBE_LS(i)] : mine;
+            while (true) {
+                const unsigned long long m = __ballot(rare != 0u);
+                if (m == 0ull) break;
+                const int lead = __ffsll(m) - 1;
+                const uint32_t q = __builtin_amdgcn_readfirstlane(__shfl(mine, lead, 64));
+                uint32_t sel = 0u, nxt = OWN_FLUID;
+#pragma unroll
+                for (int i = 1; i < Q; i++) {
+                    if ((rare >> i) & 1u) {
+                        const uint32_t o = s_own[LBE_LS(i)];
+                        if (o == q)
+                            sel |= 1u << i;
+                        else if (nxt == OWN_FLUID)
+                            nxt = o;
+                    }
+                }
+                if (!sel) continue;
+                rare &= ~sel;
+                mine = nxt;
+                const double* po = pfast + (size_t)q * kPF;
+                const double X[3] = {po[PF_X], po[PF_X + 1], po[PF_X + 2]};
+                const double rx = minimg((double)x - X[0], nx);
+                const double ry = minimg((double)y - X[1], ny);
+                const double rz = minimg((double)z - X[2], nz);
+                const double wx = po[PF_W], wy = po[PF_W + 1], wz = po[PF_W + 2];
+                const L Ux = L(po[PF_V] + (wy * rz - wz * ry));
+                const L Uy = L(po[PF_V + 1] + (wz * rx - wx * rz));
+                const L Uz = L(po[PF_V + 2] + (wx * ry - wy * rx));
+                L F[3] = {L(0), L(0), L(0)};
+#pragma unroll
+                for (int i = 1; i < Q; i++) {
+                    if ((sel >> i) & 1u) {
+                        const L cu = Ux * L(cx(i)) + Uy * L(cy(i)) + Uz * L(cz(i));
+                        const R C0 = R(L(-6.0 * wq(i)) * cu) * r0;
+                        const R C1 = R(L(-6.0 * wq(i)) * cu) * r1;
+                        const uint32_t mb = LBE_NB(i) * (uint32_t)sizeof(S);
+                        S* a0 = atw(fd + (size_t)i * N, mb);
+                        S* a1 = atw(fd + (size_t)(Q + i) * N, mb);
+                        const R v0 = P::raw(*a0), v1 = P::raw(*a1);
+                        *a0 = P::mk(v0 + C0);
+                        *a1 = P::mk(v1 + C1);
+                        const L fsum = L(v0) + L(v1) + L(P::dev ? wq(i) * (bx.rref[0] + bx.rref[1]) : 0.0);
+                        const L mag = L(2) * fsum + (L(C0) + L(C1));
+                        F[0] += mag * L(cx(i));
+                        F[1] += mag * L(cy(i));
+                        F[2] += mag * L(cz(i));
+                    }
+                }
+                int lo[3], sz[3];
+                const int cb = box_of(bx, X, po[PF_RB], lo, sz) ? rec_cell(xyz, lo, sz, Ls) : -1;
+                if (cb >= 0) {
+                    double* r = rec + ((size_t)q * rstride + cb) * kRec;
+                    r[0] = F[0];
+                    r[1] = F[1];
+                    r[2] = F[2];
+                }
+            }
+        }
     }
 #undef LBE_NB
 #undef LBE_SEL
 #undef LBE_LS
 }
 template <class P, bool SOLID, int BX, int BY>
-__global__ __launch_bounds__(256, sizeof(typename P::R) == 8 ? 2 : 3) void k_fused(
+__global__ __launch_bounds__(256, sizeof(typename P::R) == 8 ? 2 : (sizeof(typename P::S) == 2 ? 4 : 3)) void k_fused(
     Box bx, const typename P::S* __restrict__ fs, typename P::S* __restrict__ fd, const typename P::R* __restrict__ psi,
     const uint32_t* __restrict__ owner, const uint32_t* __restrict__ bm_in, uint32_t* __restrict__ bm_out,
     const double* __restrict__ pfast, double* __restrict__ rec, int rstride, int tiles_x, int tiles_y, int zrun) {
@@ -504,7 +593,7 @@ __global__ __launch_bounds__(256, sizeof(typename P::R) == 8 ? 2 : 3) void k_fus
 // Items of one system are contiguous, so the XCD remap keeps neighbouring
 // tiles together.
 template <class P, bool SOLID, int BX, int BY>
-__global__ __launch_bounds__(256, sizeof(typename P::R) == 8 ? 2 : 3) void k_fused_batch(
+__global__ __launch_bounds__(256, sizeof(typename P::R) == 8 ? 2 : (sizeof(typename P::S) == 2 ? 4 : 3)) void k_fused_batch(
     const SysDev* __restrict__ sd, const WorkItem* __restrict__ items, int c, int o) {
     const WorkItem w = items[xcd_remap(blockIdx.x, gridDim.x)];
     const SysDev& d = sd[w.sys];
