@@ -41,7 +41,7 @@ def _same(a, b):
     return all(np.array_equal(pa[k], pb[k]) for k in pa)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16_dev"])
 def test_batch_equals_lone_handles_bitwise(prec):
     """Each system of a batch ends bit for bit where a lone handle ends; the
     two-step graph is replayed several times with reads (eager work and

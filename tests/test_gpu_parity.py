@@ -267,8 +267,9 @@ def test_particles_added_mid_run_fp64():
 
 
 def test_node_touching_three_particles_fp64():
-    """A fluid node whose links end in three different particles (the most
-    the kernel sums per node), the particles carrying different colours."""
+    """A fluid node whose links end in three different particles (one more
+    than the fused kernel keeps in registers), the particles carrying
+    different colours."""
     import oracle
     from paper_1109_3277_amd.workloads import System, uniform_fields
 
@@ -286,10 +287,9 @@ def test_node_touching_three_particles_fp64():
     _check_fp64(res)
 
 
-def test_node_touching_five_particles_fp64():
-    """Particles crowding so that one fluid node links to five of them: the
-    fourth and fifth are handled link by link through the overflow
-    accumulators and must still match the oracle."""
+def _five_particles():
+    """Five small spheres around the node (12, 12, 12), which links to all
+    five of them."""
     import oracle
     from paper_1109_3277_amd.workloads import System, uniform_fields
 
@@ -305,8 +305,30 @@ def test_node_touching_five_particles_fp64():
     own = o0.owner().reshape(24, 24, 24)
     assert own[12, 12, 12] == -1
     assert [own[12, 12, 11], own[12, 12, 13], own[12, 13, 12], own[12, 11, 12], own[13, 12, 12]] == [0, 1, 2, 3, 4]
-    _, _, res = _run(s, 20)
+    return s
+
+
+def test_node_touching_five_particles_fp64():
+    """Particles crowding so that one fluid node links to five of them: the
+    third to fifth are handled link by link outside the two register slots
+    and must still match the oracle."""
+    _, _, res = _run(_five_particles(), 20)
     _check_fp64(res)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16_dev", "bf16_dev"])
+def test_node_touching_five_particles_reduced(prec):
+    """The same crowded node in the float forms: FP32 takes the per-lane path
+    for the third to fifth particles, the 2-byte forms the deferred one
+    (pushed without C, completed after the pushes)."""
+    _, _, res = _run(_five_particles(), 20, prec)
+    log(f"  {prec} {res}")
+    if prec == "fp32":
+        check(res, FP32_GATE)
+    else:
+        assert res["e_rho"] <= RED_GATE and res["owner_equal"], res
+        assert res["e_pos"] <= 1e-4 and res["e_quat"] <= 1e-4, res
+        assert res["e_vel"] <= 1e-2 and res["e_omega"] <= 1e-2, res
 
 
 @pytest.mark.parametrize("nx", [64, 128, 256, 512])
