@@ -154,10 +154,10 @@ def roofline_of(s, prec, res, traffic):
             "launches_timed": launches}
 
 
-def measured_traffic(workload: str, prec: str):
+def measured_traffic(workload: str, prec: str, kind: str = "fused"):
     """HBM bytes per fused launch from the committed rocprofv3 PMC summary, if
     it was taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", f"fused_{prec}_{workload}_pmc.json")
+    path = os.path.join(ROOT, "profiles", f"{kind}_{prec}_{workload}_pmc.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -263,7 +263,8 @@ def run_batch(steps, warmup, lone_steps):
             "precision": "fp32 fluid, fp64 particles",
             "roofline": {"bound": "hbm", "kernel": "k_fused_batch (all systems, one launch)",
                          "achieved": round(per / (fused_ms / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(per / (fused_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                         "frac": round(per / (fused_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "traffic": measured_traffic("ensemble", "fp32", "fused_batch"),
                          "algorithmic_bytes_per_launch": per, "avg_launch_ms": round(fused_ms, 5)}}
 
 

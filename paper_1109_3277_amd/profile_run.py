@@ -22,7 +22,7 @@ if ROOT not in sys.path:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="bijel", choices=["bijel", "spinodal", "interface", "mixed"])
+    ap.add_argument("--workload", default="bijel", choices=["bijel", "spinodal", "interface", "mixed", "ensemble"])
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
@@ -34,15 +34,30 @@ def main():
     from paper_1109_3277_amd import workloads as W
     from paper_1109_3277_amd.binding import Lattice
 
-    s = {"bijel": W.bijel_system, "spinodal": W.spinodal_system, "interface": W.interface_system,
-         "mixed": W.mixed_system}[a.workload]()
-    g = Lattice(s.dims, s.tau, s.g_br, s.psi_kind, a.precision, max_particles=s.n_particles, max_radius=s.max_radius)
-    g.init_fields(s.rho_a, s.rho_b)
-    if s.n_particles:
-        g.add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
+    if a.workload == "ensemble":
+        # the 64-system interface ensemble as one batch (tuned, then stepped)
+        from paper_1109_3277_amd.binding import Batch
+
+        systems = W.ensemble_systems()
+        g = Batch([{"dims": s.dims, "tau": s.tau, "g_br": s.g_br, "psi_kind": s.psi_kind,
+                    "max_particles": s.n_particles, "max_radius": s.max_radius} for s in systems], a.precision)
+        for k, s in enumerate(systems):
+            g[k].init_fields(s.rho_a, s.rho_b)
+            g[k].add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
+        print(f"tile {g.tune_report()['tile']}", flush=True)
+        N = sum(s.N for s in systems)
+    else:
+        s = {"bijel": W.bijel_system, "spinodal": W.spinodal_system, "interface": W.interface_system,
+             "mixed": W.mixed_system}[a.workload]()
+        g = Lattice(s.dims, s.tau, s.g_br, s.psi_kind, a.precision, max_particles=s.n_particles,
+                    max_radius=s.max_radius)
+        g.init_fields(s.rho_a, s.rho_b)
+        if s.n_particles:
+            g.add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
+        N = s.N
     g.step(a.warmup)
     g.step(a.steps)
-    print(f"ran {a.workload} {a.precision}: {a.warmup} + {a.steps} steps, N = {s.N}", flush=True)
+    print(f"ran {a.workload} {a.precision}: {a.warmup} + {a.steps} steps, N = {N}", flush=True)
     for _ in range(a.domain_size):
         print(f"domain size {g.domain_size()[:4].tolist()}", flush=True)
     if a.copy_mib:
