@@ -354,12 +354,13 @@ def main():
         log(f"  forms {forms}")
         del main_fields
         other = {}
-        for wl, st in (("bijel", 200), ("spinodal", 200)):
+        for wl, st in (("bijel", 200), ("spinodal", 200), ("interface", 500)):
             if wl == args.workload:
                 continue
             w, wdesc = make_workload(wl)
             blk = {"workload": wdesc, "dims": list(w.dims), "n_particles": w.n_particles, "steps": st}
-            for prec in (("fp64", "fp32", "fp16_dev") if wl == "bijel" else ("fp64", "fp32")):
+            for prec in {"bijel": ("fp64", "fp32", "fp16_dev"), "spinodal": ("fp64", "fp32"),
+                         "interface": ("fp64",)}[wl]:
                 log(f"timing {wl} {prec}")
                 r, _ = run_gpu(w, prec, st, 10)
                 blk[prec] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
@@ -382,6 +383,9 @@ def main():
         log(f"  oracle {cpu}")
 
     value = main_res["mlups"]
+    if cpu is not None:  # the GPU's rate over the oracle's, per thread count
+        cpu["gpu_over_oracle_all_threads"] = round(value / cpu["value"], 1)
+        cpu["gpu_over_oracle_one_thread"] = round(value / cpu["single_thread_mlups"], 1)
     rec = {
         "metric": METRIC, "value": round(value, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(main_res["ms_per_step"], 4), "higher_is_better": True,
