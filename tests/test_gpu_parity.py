@@ -87,6 +87,30 @@ def test_spinodal_full_size_fp64():
     _check_fp64(res)
 
 
+@pytest.mark.parametrize("prec,gate", [("fp64", 1e-13), ("fp32", FP32_GATE), ("fp16_dev", RED_GATE),
+                                       ("bf16_dev", RED_GATE)])
+def test_spinodal_mass_over_1000_steps(prec, gate):
+    """The 128^3 spinodal for 1000 steps: without particles BGK and streaming
+    conserve each component's mass exactly, so the relative change of the
+    FP64 mass sums measures only the arithmetic of the form (the deviation
+    forms store populations relative to w_i rho_ref and sum them in their
+    own precision); the total momentum stays at its initial zero."""
+    from paper_1109_3277_amd.binding import Lattice
+
+    s = W.spinodal_system()
+    log(f"case spinodal 128^3 {prec}: mass over 1000 steps")
+    g = Lattice(s.dims, s.tau, s.g_br, s.psi_kind, prec)
+    g.init_fields(s.rho_a, s.rho_b)
+    m0 = g.stats()
+    g.step(1000)
+    m1 = g.stats()
+    drift = np.abs((m1[:2] - m0[:2]) / m0[:2]).max()
+    mom = np.abs(m1[2:5]).max() / (m1[0] + m1[1])
+    log(f"  relative mass change {drift:.3e}, momentum / mass {mom:.3e}, domain size {g.domain_size()[3]:.2f}")
+    assert drift <= gate and mom <= gate
+    g.close()
+
+
 def test_bijel_scaled_fp64():
     """64^3 with the bijel recipe (volume fraction 0.15 of (8,4) ellipsoids)."""
     s = W.bijel_system(dims=(64, 64, 64), seed=14)
