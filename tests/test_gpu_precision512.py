@@ -1,6 +1,7 @@
 """The 512^3 mixed-precision domain (41,802 ellipsoids): FP32 and the FP16 /
 BF16 deviation-storage forms against the GPU FP64 run on the same seed (the
-oracle would need ~90 GB of host memory at this size).
+oracle takes ~90 GB of host memory and ~15 s per step at this size; the FP64
+run itself is checked against it in test_gpu_full_size512).
 
 Two runs per form:
 
