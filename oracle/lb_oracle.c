@@ -68,7 +68,9 @@
  *   3  angular impulse of a kill / fill taken about the centre before the
  *      body update instead of the moved centre
  *   4  Shan-Chen force with the neighbour sum of the component itself
- *      instead of the other one (Eq. (3)) */
+ *      instead of the other one (Eq. (3))
+ *   5  a fill averaging the densities of every neighbour fluid after the
+ *      step, including those the particle has just uncovered */
 #ifndef ORC_PLANT
 #define ORC_PLANT 0
 #endif
@@ -910,7 +912,11 @@ void orc_stage_raster_killfill(orc_t *s) {
             int cnt = 0;
             for (int i = 1; i < NQ; i++) {
                 long m = nbr(s, n, i);
+#if ORC_PLANT == 5
+                if (s->owner_new[m] != OWN_FLUID) continue;
+#else
                 if (s->owner[m] != OWN_FLUID || s->owner_new[m] != OWN_FLUID) continue;
+#endif
                 for (int c = 0; c < 2; c++) {
                     double r = 0.0;
                     for (int q = 0; q < NQ; q++) r += s->fn[c][q * N + m];

@@ -320,3 +320,64 @@ def test_rotating_and_translating_sphere_drag_fluid(oracle_mod):
     u = u.reshape(24, 24, 24, 3)  # [z][y][x]
     assert u[12, 12, 17, 1] > 0 and u[12, 12, 7, 1] < 0  # +x side moves +y, -x side moves -y
     assert u[12, 12, 17, 0] > 0 and u[12, 12, 7, 0] > 0  # fluid dragged along +x
+
+
+@pytest.mark.parametrize("plant", [0, 5])
+def test_fill_rule_hand_computed(oracle_mod, plant):
+    """The fill rule, computed in the test from its statement: a node that a
+    moving sphere uncovers gets f_i = f^eq_i(rho_bar^c, u_b) for each
+    component, with rho_bar^c the mean of rho^c(t+1) over the node's 18
+    neighbours that are fluid both before and after the step, and u_b =
+    V + W x r the surface velocity of the particle that owned it, with the
+    velocities and centre after the body update (r the minimum-image offset
+    from that centre). f^eq and the lattice are pinned by the fluid tests.
+    The copy of the oracle with planted mistake 5 (a fill that also averages
+    the just-uncovered neighbours) must fail it."""
+    dims = (16, 16, 16)
+    nx, ny, nz = dims
+    N = nx * ny * nz
+    rng = np.random.default_rng(31)
+    ra = 0.6 + 0.05 * rng.uniform(-1, 1, N)
+    rb = 0.5 + 0.05 * rng.uniform(-1, 1, N)
+    if plant:
+        oracle_mod.build(force=False, plant=plant)
+    o = oracle_mod.Oracle(dims, 1.0, 0.0, plant=plant)
+    o.init_fields(ra, rb)
+    R = 3.2
+    o.add_ellipsoids(np.array([[R, R]]), np.array([[8.1, 7.9, 8.2]]), np.array([[1.0, 0.0, 0.0, 0.0]]),
+                     np.zeros(1), np.array([1e6]))
+    M = o.particle_extra(0)["M"]
+    W0 = np.array([0.0, 0.02, 0.06])
+    o.set_particle_motion(0, V=[0.45, -0.2, 0.1], L=0.4 * M * R * R * W0, W=W0)
+    own0 = o.owner().copy()
+    o.step(1)
+    own1 = o.owner()
+    filled = np.where((own0 == 0) & (own1 == -1))[0]
+    assert len(filled) >= 5
+    ra1, rb1, _, _ = o.read_fields()
+    p = o.read_particles()
+    X, V, W = p["pos"][0], p["vel"][0], p["omega"][0]
+    c, w = oracle_mod.lattice()
+    fa, fb = o.get_pops(0), o.get_pops(1)
+
+    def feq(rho, u):
+        cu = c @ u
+        return w * rho * (1 + 3 * cu + 4.5 * cu * cu - 1.5 * (u @ u))
+
+    L = np.array(dims, float)
+    worst = 0.0
+    for n in filled:
+        xyz = np.array([n % nx, (n // nx) % ny, n // (nx * ny)], float)
+        nbrs = [int(((xyz[0] + ci[0]) % nx) + nx * (((xyz[1] + ci[1]) % ny) + ny * ((xyz[2] + ci[2]) % nz)))
+                for ci in c[1:]]
+        keep = [m for m in nbrs if own0[m] == -1 and own1[m] == -1]
+        assert keep, n
+        r = xyz - X
+        r -= np.round(r / L) * L
+        ub = V + np.cross(W, r)
+        worst = max(worst, np.abs(fa[:, n] - feq(np.mean(ra1[keep]), ub)).max(),
+                    np.abs(fb[:, n] - feq(np.mean(rb1[keep]), ub)).max())
+    if plant == 0:
+        assert worst <= 1e-14, worst
+    else:
+        assert worst > 1e-6, worst
