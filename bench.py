@@ -75,13 +75,14 @@ def make_workload(name: str):
     return s, desc
 
 
-def _lattice(s, prec):
+def _lattice(s, prec, density=None):
     from paper_1109_3277_amd.binding import Lattice
 
     g = Lattice(s.dims, s.tau, s.g_br, s.psi_kind, prec, max_particles=s.n_particles, max_radius=s.max_radius)
     g.init_fields(s.rho_a, s.rho_b)
     if s.n_particles:
-        g.add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
+        dens = s.density if density is None else np.full(s.n_particles, float(density))
+        g.add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, dens)
     return g
 
 
@@ -180,6 +181,45 @@ def form_errors(ref, fields, s):
             "owner_diff": int((own != OWN).sum())}
 
 
+def heavy_form_errors(s, steps=100):
+    """Each reduced form against FP64 after `steps` steps with the particles
+    made heavy (density 1e6), so that no owner code differs between the runs:
+    element-wise density and velocity errors on the device (densities over
+    max |rho|, velocities over max(|u|, 1e-3))."""
+    import torch
+
+    def fields(prec):
+        g = _lattice(s, prec, density=1e6)
+        g.step(steps)
+        N = s.N
+        f = {"ra": torch.empty(N, dtype=torch.float64, device="cuda"),
+             "rb": torch.empty(N, dtype=torch.float64, device="cuda"),
+             "u": torch.empty(3 * N, dtype=torch.float64, device="cuda"),
+             "own": torch.empty(N, dtype=torch.int32, device="cuda")}
+        g.read_fields_dev(f["ra"], f["rb"], f["u"], f["own"])
+        torch.cuda.synchronize()
+        g.close()
+        torch.cuda.empty_cache()
+        return f
+
+    ref = fields("fp64")
+    out = {}
+    for prec in ("fp32", "fp16_dev", "bf16_dev"):
+        log(f"heavy-particle comparison {prec}")
+        f = fields(prec)
+        both = (ref["own"] == -1) & (f["own"] == -1)
+        sc = torch.maximum(ref["ra"].abs().max(), ref["rb"].abs().max())
+        e_rho = torch.maximum((f["ra"] - ref["ra"])[both].abs().max(), (f["rb"] - ref["rb"])[both].abs().max()) / sc
+        b3 = both.repeat_interleave(3)
+        umax = max(float(ref["u"][b3].abs().max()), 1e-3)
+        out[prec] = {"heavy_steps": steps, "heavy_rho_linf": float(e_rho),
+                     "heavy_u_linf": float((f["u"] - ref["u"])[b3].abs().max()) / umax,
+                     "heavy_owner_diff": int((f["own"] != ref["own"]).sum())}
+        del f
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_forms(s, workload, steps, warmup, main_prec, main_res, main_fields):
     forms = {}
     for prec in ("fp64", "fp32", "fp16_dev", "bf16_dev"):
@@ -199,6 +239,9 @@ def run_forms(s, workload, steps, warmup, main_prec, main_res, main_fields):
         del fields
     for prec in forms:
         forms[prec]["speedup_vs_fp64"] = round(forms[prec]["mlups"] / forms["fp64"]["mlups"], 3)
+    if main_prec == "fp64":
+        for prec, e in heavy_form_errors(s).items():
+            forms[prec].update(e)
     return forms
 
 
