@@ -297,8 +297,11 @@ int lb_batch_last_graph(const lb_handle* batch, int32_t* steps, int64_t* kernel_
  * systems is rejected (LB_EINVAL). Each call rewrites every partial before it
  * reads it; calls that overlap on one GPU race on that array. Values equal
  * lb_stats's to rounding (the partial sums are grouped differently); the
- * fluid count, health flag and removed mass match exactly. LB_ESTATE on a
- * system handle of a batch (call it on the batch) or before lb_init_fields. */
+ * fluid count, health flag and removed mass match exactly. The call does no
+ * host-device copy and no synchronisation. LB_ESTATE on a system handle of a
+ * batch (call it on the batch), before lb_init_fields, or on a batch whose
+ * systems changed (fields, particles, walls) since its last lb_step or
+ * lb_batch_tune, which upload the batch's tables. */
 #define LB_NOALLOC_MAX_SYSTEMS 256
 int lb_stats_noalloc(lb_handle* h, double* dev_out);
 

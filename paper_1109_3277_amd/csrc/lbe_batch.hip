@@ -248,8 +248,11 @@ int check_ready(lb_handle* h) {
 // n steps of every system as one graph launch on the caller's stream. The
 // graph of the last step count is kept per starting parity and replayed
 // while the count and the systems stay the same.
-int batch_sys(lb_handle* h, const SysDev** d_sys, int* nsys, int* parity) {
+int batch_sys(lb_handle* h, const SysDev** d_sys, int* nsys, int* parity, bool refresh_ok) {
     BatchState* B = h->batch;
+    if (!refresh_ok && B->dirty)
+        return fail(h, LB_ESTATE, "the batch changed since its tables were last uploaded: step it (or call "
+                                  "lb_batch_tune) first");
     const int rc = check_ready(h);
     if (rc != LB_OK) return rc;
     *d_sys = B->d_sys;

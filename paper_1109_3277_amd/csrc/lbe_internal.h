@@ -104,8 +104,10 @@ int setup_handle(lb_handle* h, const lb_params* prm, char* ws, size_t ws_bytes, 
 
 // Descriptor of one system as the batched kernels see it (lbe_batch.hip).
 SysDev sys_dev(const lb_handle* q);
-// Device descriptors and systems of a batch (refreshed when stale).
-int batch_sys(lb_handle* h, const SysDev** d_sys, int* nsys, int* parity);
+// Device descriptors and systems of a batch. Stale tables are uploaded again
+// (host work, a copy and a stream synchronisation) unless refresh_ok is false;
+// then a stale batch is refused with LB_ESTATE.
+int batch_sys(lb_handle* h, const SysDev** d_sys, int* nsys, int* parity, bool refresh_ok = true);
 
 // Batches (lbe_batch.hip).
 int batch_step_async(lb_handle* h, int nsteps);

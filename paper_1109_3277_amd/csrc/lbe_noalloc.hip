@@ -157,14 +157,17 @@ extern "C" int lb_stats_noalloc(lb_handle* h, double* dev_out) {
     double* sc = nullptr;
     LBE_HIP_OR_FAIL(h, scratch_of(h->device, &sc));
     if (h->batch) {
+        const int n = lb_batch_size(h);
+        if (n > LB_NOALLOC_MAX_SYSTEMS)
+            return fail(h, LB_EINVAL,
+                        "batch of " + std::to_string(n) + " systems exceeds the allocation-free scratch (" +
+                            std::to_string(LB_NOALLOC_MAX_SYSTEMS) + " systems)");
+        // no table upload here (it would synchronise the stream): a batch
+        // changed since its last step is refused
         const SysDev* d_sys = nullptr;
         int nsys = 0, parity = 0;
-        const int rc = batch_sys(h, &d_sys, &nsys, &parity);
+        const int rc = batch_sys(h, &d_sys, &nsys, &parity, false);
         if (rc != LB_OK) return rc;
-        if (nsys > LB_NOALLOC_MAX_SYSTEMS)
-            return fail(h, LB_EINVAL,
-                        "batch of " + std::to_string(nsys) + " systems exceeds the allocation-free scratch (" +
-                            std::to_string(LB_NOALLOC_MAX_SYSTEMS) + " systems)");
         LBE_NA_DISPATCH(h->prm.precision, hipLaunchKernelGGL(k_stats_nb_batch<P>, dim3(kNB, nsys), dim3(256), 0,
                                                               h->stream, d_sys, parity, sc));
         LBE_HIP_OR_FAIL(h, hipGetLastError());

@@ -62,6 +62,31 @@ def test_stats_noalloc_batch_then_lone():
     g.close()
 
 
+def test_stats_noalloc_refuses_a_changed_batch_until_stepped():
+    """The call uploads nothing: a batch whose systems changed since its last
+    step (here: fresh fields) is refused, and accepted after a step."""
+    import torch
+
+    from paper_1109_3277_amd.binding import LB_ESTATE, Batch, load_library
+
+    L = load_library()
+    ens = sorted(W.ensemble_systems(), key=lambda s: s.N)[:2]
+    b = Batch([{"dims": s.dims, "tau": s.tau, "g_br": s.g_br, "psi_kind": s.psi_kind,
+                "max_particles": s.n_particles, "max_radius": s.max_radius} for s in ens], "fp32")
+    for k, s in enumerate(ens):
+        b[k].init_fields(s.rho_a, s.rho_b)
+    out = torch.zeros((len(ens), 8), dtype=torch.float64, device="cuda")
+    assert L.lb_stats_noalloc(b._h, C.c_void_p(out.data_ptr())) == LB_ESTATE
+    assert b"changed" in L.lb_last_error(b._h)
+    b.step(2)
+    assert L.lb_stats_noalloc(b._h, C.c_void_p(out.data_ptr())) == 0
+    torch.cuda.synchronize()
+    for k in range(len(ens)):
+        host = b[k].stats()
+        _agree(out[k].cpu().numpy(), host, f"system {k}")
+    b.close()
+
+
 def test_stats_noalloc_rejects_too_many_systems():
     import torch
 
