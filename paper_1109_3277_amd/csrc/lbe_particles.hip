@@ -38,6 +38,30 @@ __device__ inline void qrot(double w, double x, double y, double z, double R[3][
     R[2][2] = 1.0 - 2.0 * (x * x + y * y);
 }
 
+// Axis-aligned box of particle p's ellipsoid: along axis k its half extent is
+// sqrt(R_perp^2 (1 - o_k^2) + R_par^2 o_k^2), o the body axis (the support of
+// the ellipsoid in direction k), grown by a relative 1e-9 plus 1e-9 nodes, far
+// beyond the rounding of the inside test, and capped at the bounding radius.
+// It holds every node the inside test accepts, and for an elongated body it is
+// much smaller than the bounding cube. False if the state is not usable.
+__device__ inline bool ellipsoid_box(const Box& bx, const double* part, int cap, int p, int lo[3], int sz[3]) {
+    const int Ls[3] = {bx.nx, bx.ny, bx.nz};
+    const double X[3] = {part[PX * cap + p], part[PY * cap + p], part[PZ * cap + p]};
+    const double rpar = part[RPAR * cap + p], rperp = part[RPERP * cap + p];
+    const double rb = rpar > rperp ? rpar : rperp;
+    double R[3][3];
+    qrot(part[QW * cap + p], part[QX * cap + p], part[QY * cap + p], part[QZ * cap + p], R);
+    for (int d = 0; d < 3; d++) {
+        if (!isfinite(X[d]) || !(rb < 0.5 * Ls[d])) return false;
+        const double o = R[d][2];
+        const double e2 = rperp * rperp * fmax(0.0, 1.0 - o * o) + rpar * rpar * (o * o);
+        const double e = fmin(sqrt(e2) * (1.0 + 1e-9) + 1e-9, rb);
+        lo[d] = (int)ceil(X[d] - e);
+        sz[d] = max(0, min((int)floor(X[d] + e) - lo[d] + 1, Ls[d]));
+    }
+    return true;
+}
+
 // Closed inside test: body-frame offset b = R^T d of the minimum-image offset
 // d, inside when (b_x^2 + b_y^2)/R_perp^2 + b_z^2/R_par^2 <= 1. Evaluated in a
 // fixed order with FMA contraction off so the owner map is a function of the
@@ -68,11 +92,11 @@ __device__ inline int64_t node_index(const Box& bx, int x, int y, int z) {
 
 // ---------------------------------------------------------------- raster
 // Rasterise particle p into owner with atomicMin (the smallest index owns a
-// node covered by several particles): one block loops over p's box.
+// node covered by several particles): one block loops over p's ellipsoid box.
 __device__ inline void raster_body(const Box& bx, const double* __restrict__ part, int cap,
                                    uint32_t* __restrict__ owner, int p) {
     int lo[3], sz[3];
-    if (!particle_box(bx, part, cap, p, lo, sz)) return;  // invalid state: touch nothing
+    if (!ellipsoid_box(bx, part, cap, p, lo, sz)) return;  // invalid state: touch nothing
     const double X[3] = {part[PX * cap + p], part[PY * cap + p], part[PZ * cap + p]};
     double R[3][3];
     qrot(part[QW * cap + p], part[QX * cap + p], part[QY * cap + p], part[QZ * cap + p], R);
@@ -128,7 +152,7 @@ __device__ inline void shell_body(const Box& bx, R* __restrict__ psi, const R* _
     const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
     const int64_t N = bx.N;
     int lo[3] = {0, 0, 0}, sz[3] = {0, 0, 0};
-    const int total = particle_box(bx, part, cap, p, lo, sz) ? sz[0] * sz[1] * sz[2] : 0;
+    const int total = ellipsoid_box(bx, part, cap, p, lo, sz) ? sz[0] * sz[1] * sz[2] : 0;
     // densities of fluid nodes: the stored rho (Psi itself when Psi = rho)
     const R* dens = bx.psi_kind == 0 ? psi : rho;
     const double dr = part[DRHO * cap + p];
