@@ -98,6 +98,7 @@ __global__ __launch_bounds__(kDsThreads) void k_ds_mean(double* __restrict__ red
 // order and writes one partial.
 template <int AX>
 __global__ __launch_bounds__(kDsThreads) void k_line_moments(Box bx, const double* __restrict__ phi,
+                                                             const double* __restrict__ mean_of_phi,
                                                              double* __restrict__ red, int np, int fft_bits) {
     extern __shared__ double2 lds[];
     const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
@@ -108,7 +109,7 @@ __global__ __launch_bounds__(kDsThreads) void k_line_moments(Box bx, const doubl
     double2* data = lds;                      // np lines of La complex values
     double2* tw = lds + (size_t)np * La;      // exp(-2 pi i m / La)
     double* datad = (double*)data;
-    const double mean = red[(size_t)gridDim.x * 8];
+    const double mean = *mean_of_phi;
     for (int m = threadIdx.x; m < ntw; m += kDsThreads) {
         double s, c;
         sincospi(-2.0 * (double)m / (double)La, &s, &c);
@@ -254,8 +255,8 @@ hipError_t launch_lines(lb_handle* h, const double* phi) {
     line_shape(La, &np, &bits);
     const int ntw = bits >= 0 ? La / 2 : La;
     const size_t lds = ((size_t)np * La + (size_t)ntw) * sizeof(double2);
-    hipLaunchKernelGGL(k_line_moments<AX>, dim3(kRedBlocks), dim3(kDsThreads), lds, h->stream, h->box, phi, h->b.red,
-                       np, bits);
+    hipLaunchKernelGGL(k_line_moments<AX>, dim3(kRedBlocks), dim3(kDsThreads), lds, h->stream, h->box, phi,
+                       h->b.red + (size_t)kRedBlocks * 8, h->b.red, np, bits);
     return hipGetLastError();
 }
 
