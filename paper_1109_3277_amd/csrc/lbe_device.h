@@ -47,6 +47,7 @@ enum PField : int {
     JX, JY, JZ, HX, HY, HZ,    // pending kill/fill impulses
     LFX, LFY, LFZ, LTX, LTY, LTZ,  // totals applied in the last body update
     OX, OY, OZ,                // centre before the last body update
+    OQW, OQX, OQY, OQZ,        // orientation before the last body update
     KMASS, FMASS,              // fluid mass killed / filled by this particle (cumulative)
     PFX, PFY, PFZ, PTX, PTY, PTZ,  // particle-particle force / torque of the current step
     NPFIELD

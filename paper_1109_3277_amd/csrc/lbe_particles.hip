@@ -38,26 +38,36 @@ __device__ inline void qrot(double w, double x, double y, double z, double R[3][
     R[2][2] = 1.0 - 2.0 * (x * x + y * y);
 }
 
-// Axis-aligned box of particle p's ellipsoid: along axis k its half extent is
-// sqrt(R_perp^2 (1 - o_k^2) + R_par^2 o_k^2), o the body axis (the support of
-// the ellipsoid in direction k), grown by a relative 1e-9 plus 1e-9 nodes, far
-// beyond the rounding of the inside test, and capped at the bounding radius.
-// It holds every node the inside test accepts, and for an elongated body it is
-// much smaller than the bounding cube. False if the state is not usable.
+// Half extents of the axis-aligned box of an ellipsoid with semi-axes R_par
+// (body axis) and R_perp, orientation R (body -> space), scaled by sc: along
+// axis k, sc sqrt(R_perp^2 (1 - o_k^2) + R_par^2 o_k^2), o the body axis (the
+// support of the ellipsoid in direction k), grown by a relative 1e-9 plus 1e-9
+// nodes, far beyond the rounding of the inside tests, and capped at cap_r.
+__device__ inline void ellipsoid_extent(const double R[3][3], double rpar, double rperp, double sc, double cap_r,
+                                        double e[3]) {
+    for (int d = 0; d < 3; d++) {
+        const double o = R[d][2];
+        const double e2 = rperp * rperp * fmax(0.0, 1.0 - o * o) + rpar * rpar * (o * o);
+        e[d] = fmin(sc * sqrt(e2) * (1.0 + 1e-9) + 1e-9, cap_r);
+    }
+}
+
+// Axis-aligned box of particle p's ellipsoid (extents above, capped at the
+// bounding radius). It holds every node the inside test accepts, and for an
+// elongated body it is much smaller than the bounding cube. False if the state
+// is not usable.
 __device__ inline bool ellipsoid_box(const Box& bx, const double* part, int cap, int p, int lo[3], int sz[3]) {
     const int Ls[3] = {bx.nx, bx.ny, bx.nz};
     const double X[3] = {part[PX * cap + p], part[PY * cap + p], part[PZ * cap + p]};
     const double rpar = part[RPAR * cap + p], rperp = part[RPERP * cap + p];
     const double rb = rpar > rperp ? rpar : rperp;
-    double R[3][3];
+    double R[3][3], e[3];
     qrot(part[QW * cap + p], part[QX * cap + p], part[QY * cap + p], part[QZ * cap + p], R);
+    ellipsoid_extent(R, rpar, rperp, 1.0, rb, e);
     for (int d = 0; d < 3; d++) {
         if (!isfinite(X[d]) || !(rb < 0.5 * Ls[d])) return false;
-        const double o = R[d][2];
-        const double e2 = rperp * rperp * fmax(0.0, 1.0 - o * o) + rpar * rpar * (o * o);
-        const double e = fmin(sqrt(e2) * (1.0 + 1e-9) + 1e-9, rb);
-        lo[d] = (int)ceil(X[d] - e);
-        sz[d] = max(0, min((int)floor(X[d] + e) - lo[d] + 1, Ls[d]));
+        lo[d] = (int)ceil(X[d] - e[d]);
+        sz[d] = max(0, min((int)floor(X[d] + e[d]) - lo[d] + 1, Ls[d]));
     }
     return true;
 }
@@ -241,14 +251,16 @@ __global__ __launch_bounds__(kPB) void k_shell_batch(const SysDev* __restrict__ 
 // for every fluid node n linked to p, the node's force F_n = sum over its
 // links into p of (2 f*_i + C) c_i (both components) in p's record cell of n.
 // The force is the sum of the F_n and the torque the sum of r_n x F_n. One
-// block per particle walks the record box: cell c goes to thread c mod kPB,
-// each thread's cells in increasing order, then a fixed block sum, so the
-// result is reproducible bit for bit. Records read are cleared for the next
-// step. A linked fluid node lies within sqrt(2) of a node of p. In
-// coordinates scaled by the semi-axes that is a step of at most
-// sqrt(2) / min(R_par, R_perp), so the node lies inside p's ellipsoid scaled
-// about its centre by 1 + 1.5 / min(R_par, R_perp): cells outside that are
-// never written and are not read.
+// block per particle walks the record cells that can hold a link: cell t of
+// the walk goes to thread t mod kPB, each thread's cells in increasing order,
+// then a fixed block sum, so the result is reproducible bit for bit. Records
+// read are cleared for the next step. A linked fluid node lies within sqrt(2)
+// of a node of p. In coordinates scaled by the semi-axes that is a step of at
+// most sqrt(2) / min(R_par, R_perp), so the node lies inside p's ellipsoid
+// scaled about its centre by 1 + 1.5 / min(R_par, R_perp): the walk covers the
+// record cells inside that ellipsoid's axis-aligned box (on an axis where the
+// record box spans the whole lattice, all of them), and loads only the cells
+// inside the scaled ellipsoid itself; other cells are never written.
 __device__ inline void linkforce_body(const Box& bx, double* __restrict__ rec, int rstride,
                                       double* __restrict__ part, int cap, int p) {
     const int Ls[3] = {bx.nx, bx.ny, bx.nz};
@@ -256,7 +268,6 @@ __device__ inline void linkforce_body(const Box& bx, double* __restrict__ rec, i
     int lo[3] = {0, 0, 0}, sz[3] = {0, 0, 0}, esz[3];
     const bool ok = particle_box(bx, part, cap, p, lo, sz);
     for (int d = 0; d < 3; d++) esz[d] = min(sz[d] + 2, Ls[d]);
-    const int cells = ok ? esz[0] * esz[1] * esz[2] : 0;
     double Rm[3][3];
     qrot(part[QW * cap + p], part[QX * cap + p], part[QY * cap + p], part[QZ * cap + p], Rm);
     const double rpar = part[RPAR * cap + p], rperp = part[RPERP * cap + p];
@@ -265,23 +276,44 @@ __device__ inline void linkforce_body(const Box& bx, double* __restrict__ rec, i
     // a filter only: linked nodes lie strictly inside the scaled ellipsoid,
     // by far more than rounding, so the division-free form serves
     const double ia2 = 1.0 / (ga * ga), ic2 = 1.0 / (gc * gc);
+    // the walked box [slo, slo + ssz) inside the record box, whose cells are
+    // numbered from its corner lo - 1 (the numbering the fused kernel writes)
+    double es[3];
+    ellipsoid_extent(Rm, rpar, rperp, sc, (double)(Ls[0] + Ls[1] + Ls[2]), es);
+    int slo[3], ssz[3], off[3];
+    for (int d = 0; d < 3; d++) {
+        const int elo = lo[d] - 1;
+        if (!ok || esz[d] >= Ls[d]) {
+            slo[d] = elo;
+            ssz[d] = esz[d];
+        } else {
+            const int a = max((int)ceil(X[d] - es[d]), elo);
+            const int b = min((int)floor(X[d] + es[d]), elo + esz[d] - 1);
+            slo[d] = a;
+            ssz[d] = max(0, b - a + 1);
+        }
+        off[d] = slo[d] - elo;
+    }
+    const int cells = ok ? ssz[0] * ssz[1] * ssz[2] : 0;
     double* rp = rec + (size_t)p * rstride * kRec;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     constexpr int U = 4;  // cells per thread in flight
-    const int elo[3] = {lo[0] - 1, lo[1] - 1, lo[2] - 1};
-    BoxWalk w(elo, esz, Ls, threadIdx.x, kPB);
+    BoxWalk w(slo, ssz, Ls, threadIdx.x, kPB);
     for (int base = 0; base < cells; base += U * kPB) {
         double F[U][3], r[U][3];
+        int cell[U];
 #pragma unroll
         for (int k = 0; k < U; k++, w.next()) {
-            const int c = base + k * kPB + (int)threadIdx.x;
+            const int t = base + k * kPB + (int)threadIdx.x;
             F[k][0] = F[k][1] = F[k][2] = 0.0;
             r[k][0] = r[k][1] = r[k][2] = 0.0;
-            if (c < cells) {
+            cell[k] = ((off[2] + w.iz) * esz[1] + off[1] + w.iy) * esz[0] + off[0] + w.ix;
+            if (t < cells) {
                 r[k][0] = minimg((double)w.x() - X[0], Ls[0]);
                 r[k][1] = minimg((double)w.y() - X[1], Ls[1]);
                 r[k][2] = minimg((double)w.z() - X[2], Ls[2]);
                 if (q_fast(Rm, r[k][0], r[k][1], r[k][2], ia2, ic2) <= 1.0) {
+                    const int c = cell[k];
                     F[k][0] = rp[(size_t)c * kRec];
                     F[k][1] = rp[(size_t)c * kRec + 1];
                     F[k][2] = rp[(size_t)c * kRec + 2];
@@ -291,7 +323,7 @@ __device__ inline void linkforce_body(const Box& bx, double* __restrict__ rec, i
 #pragma unroll
         for (int k = 0; k < U; k++) {
             if (F[k][0] == 0.0 && F[k][1] == 0.0 && F[k][2] == 0.0) continue;
-            const int c = base + k * kPB + (int)threadIdx.x;
+            const int c = cell[k];
             rp[(size_t)c * kRec] = 0.0;
             rp[(size_t)c * kRec + 1] = 0.0;
             rp[(size_t)c * kRec + 2] = 0.0;
@@ -311,12 +343,12 @@ __device__ inline void linkforce_body(const Box& bx, double* __restrict__ rec, i
         for (int k = 0; k < 6; k++) part[fld[k] * cap + p] = tot[k];
     }
 }
-__global__ __launch_bounds__(kPB) void k_linkforce(Box bx, double* __restrict__ rec, int rstride,
+__global__ __launch_bounds__(kPB, 4) void k_linkforce(Box bx, double* __restrict__ rec, int rstride,
                                                    double* __restrict__ part, int cap) {
     linkforce_body(bx, rec, rstride, part, cap, blockIdx.x);
 }
 // Batched: item = (system, particle).
-__global__ __launch_bounds__(kPB) void k_linkforce_batch(const SysDev* __restrict__ sd,
+__global__ __launch_bounds__(kPB, 4) void k_linkforce_batch(const SysDev* __restrict__ sd,
                                                          const WorkItem* __restrict__ items) {
     const WorkItem w = items[blockIdx.x];
     const SysDev& d = sd[w.sys];
@@ -383,6 +415,10 @@ __device__ inline void bodies_body(const Box& bx, double* __restrict__ part, int
         F_(lk[d]) = F_(lk[d]) + T[d];
     }
     const double qw = F_(QW), qx = F_(QX), qy = F_(QY), qz = F_(QZ);
+    F_(OQW) = qw;
+    F_(OQX) = qx;
+    F_(OQY) = qy;
+    F_(OQZ) = qz;
     double R[3][3];
     qrot(qw, qx, qy, qz, R);
     const double Lv[3] = {F_(LX), F_(LY), F_(LZ)};
@@ -463,8 +499,9 @@ __device__ inline R feq_p(int i, R rho, R ux, R uy, R uz) {
     return R(wq(i)) * rho * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
 }
 
-// Kill / fill over the union of the particle's bounding boxes before and after
-// the move; runs after the density pass of the next step (populations after
+// Kill / fill over the smallest box holding the particle's axis-aligned
+// ellipsoid boxes before and after the move (the boxes the raster walked, so
+// every node it gave to p in either owner map); runs after the density pass of the next step (populations after
 // streaming, nodes fluid in both owner maps). Node n with old owner o and new
 // owner o2:
 //   o fluid, o2 == p : kill  -> J_p += sum_c j^c(n), H_p += r x that (the node's
@@ -474,10 +511,10 @@ __device__ inline R feq_p(int i, R rho, R ux, R uy, R uz) {
 //                      f = f^eq(rho_new^c, u), J_p -= sum_c rho_new^c u, H_p -= r x that;
 //                      the node's Psi (and rho) follow from the stored f.
 // Each changing node is handled by exactly one thread (of its owner's block).
-// One block loops over the union box, four nodes per thread in flight; the
+// One block loops over that box, eight nodes per thread in flight; the
 // block's fixed-order sum is the particle's impulse (and killed / filled
-// mass) of this step. A union box
-// wider than kext (a move of more than two spacings) raises health bit 2.
+// mass) of this step. A box wider than kext (a move of more than two
+// spacings) raises health bit 2.
 template <class P>
 __device__ inline void killfill_node(const Box& bx, typename P::S* __restrict__ f,
                                      const uint32_t* __restrict__ own_old, const uint32_t* __restrict__ own_new,
@@ -614,14 +651,22 @@ __device__ inline void killfill_body(const Box& bx, typename P::S* __restrict__ 
     const double Xo[3] = {part[OX * cap + p], part[OY * cap + p], part[OZ * cap + p]};
     const double rpar = part[RPAR * cap + p], rperp = part[RPERP * cap + p];
     const double rb = rpar > rperp ? rpar : rperp;
+    // the boxes the raster walked before and after the move (same extents,
+    // from the same centres and orientations), the new one lifted next to the
+    // old centre
+    double Ro[3][3], Rn[3][3], eo[3], en[3];
+    qrot(part[OQW * cap + p], part[OQX * cap + p], part[OQY * cap + p], part[OQZ * cap + p], Ro);
+    qrot(part[QW * cap + p], part[QX * cap + p], part[QY * cap + p], part[QZ * cap + p], Rn);
+    ellipsoid_extent(Ro, rpar, rperp, 1.0, rb, eo);
+    ellipsoid_extent(Rn, rpar, rperp, 1.0, rb, en);
     for (int d = 0; d < 3; d++) {
         if (!isfinite(Xn[d]) || !isfinite(Xo[d]) || !(rb < 0.5 * Ls[d])) {
             ok = false;
             break;
         }
         const double xn = Xo[d] + minimg(Xn[d] - Xo[d], Ls[d]);  // unwrapped new centre
-        const int a = min((int)ceil(Xo[d] - rb), (int)ceil(xn - rb));
-        const int b = max((int)floor(Xo[d] + rb), (int)floor(xn + rb));
+        const int a = min((int)ceil(Xo[d] - eo[d]), (int)ceil(xn - en[d]));
+        const int b = max((int)floor(Xo[d] + eo[d]), (int)floor(xn + en[d]));
         lo[d] = a;
         sz[d] = max(0, min(b - a + 1, Ls[d]));
         if (sz[d] > kext && threadIdx.x == 0) atomicOr(health, 2);

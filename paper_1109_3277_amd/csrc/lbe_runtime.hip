@@ -347,6 +347,7 @@ int lb_add_ellipsoids(lb_handle* h, int32_t n, const double* radii, const double
             F(QX, k) = q[1] / qn;
             F(QY, k) = q[2] / qn;
             F(QZ, k) = q[3] / qn;
+            for (int d = 0; d < 4; d++) F(OQW + d, k) = F(QW + d, k);
         }
         const double rpar = radii[2 * k], rperp = radii[2 * k + 1];
         const double dens = density ? density[k] : 1.0;

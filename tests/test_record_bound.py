@@ -107,3 +107,34 @@ def test_reciprocal_form_stays_within_the_raster_band():
         inn = fast < 1.0 - 1e-9
         assert (exact[out] > 1.0).all() and (exact[inn] <= 1.0).all()
     assert worst < 1e-13
+
+
+def test_axis_aligned_box_holds_the_ellipsoid_and_is_tight():
+    """The raster, shell and kill/fill passes walk the axis-aligned box of the
+    rotated ellipsoid, with half extent sqrt(R_perp^2 (1 - o_k^2) + R_par^2 o_k^2)
+    on axis k (o the body axis), and the force pass the same box of the
+    ellipsoid scaled by 1 + 1.5 / min(R). Every lattice point inside the
+    ellipsoid lies in the box, every linked node in the scaled box, and the box
+    is attained: the surface point X + M e_k / sqrt(M_kk), M = R diag(R_perp^2,
+    R_perp^2, R_par^2) R^T, lies on the ellipsoid at offset sqrt(M_kk) along k."""
+    rng = np.random.default_rng(11)
+    for _ in range(80):
+        rpar, rperp = rng.uniform(0.5, 9.0), rng.uniform(0.5, 9.0)
+        q = rng.normal(size=4)
+        R = _rot(q / np.linalg.norm(q))
+        X = rng.uniform(0.0, 1.0, 3)
+        o = R[:, 2]
+        e = np.sqrt(rperp ** 2 * (1.0 - o ** 2) + rpar ** 2 * o ** 2)
+        L = int(2 * max(rpar, rperp)) + 4
+        g = np.stack(np.meshgrid(*[np.arange(-L, L + 1)] * 3, indexing="ij"), -1).reshape(-1, 3).astype(float)
+        inside = g[_form(g, X, R, rperp, rpar) <= 1.0]
+        assert (np.abs(inside - X) <= e * (1.0 + 1e-9) + 1e-9).all()
+        s = 1.0 + 1.5 / min(rpar, rperp)
+        for c in LINKS:
+            n = inside - np.array(c, dtype=float)
+            assert (np.abs(n - X) <= s * e * (1.0 + 1e-9) + 1e-9).all()
+        M = R @ np.diag([rperp ** 2, rperp ** 2, rpar ** 2]) @ R.T
+        for k in range(3):
+            p = X + M[:, k] / np.sqrt(M[k, k])
+            assert abs(_form(p[None, :], X, R, rperp, rpar)[0] - 1.0) < 1e-12
+            assert abs((p[k] - X[k]) - e[k]) < 1e-12 * max(rpar, rperp)
