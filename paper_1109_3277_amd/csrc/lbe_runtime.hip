@@ -28,7 +28,8 @@ int fail(lb_handle* h, int code, const std::string& msg) {
 bool params_ok(const lb_params* p, std::string* why) {
     if (!p) { *why = "params is NULL"; return false; }
     if (p->nx < 3 || p->ny < 3 || p->nz < 3) { *why = "each dimension must be >= 3"; return false; }
-    if ((int64_t)p->nx * p->ny * p->nz * 8 >= ((int64_t)1 << 32)) {
+    // in double: exact near the bound, and no overflow for any int32 extents
+    if ((double)p->nx * (double)p->ny * (double)p->nz * 8.0 >= 4294967296.0) {
         *why = "too many nodes (one population plane must stay below 4 GiB: N < 2^29)";
         return false;
     }

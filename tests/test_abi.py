@@ -53,6 +53,11 @@ def test_workspace_bytes_validates(lib):
                 B.make_params((8, 8, 8), 1.0, 0.08, max_particles=2),
                 B.make_params((8, 8, 8), 1.0, 0.08, max_particles=2, max_radius=4.0)):
         assert lib.lb_workspace_bytes(C.byref(bad)) == 0
+    # the largest boxes: one population plane (N values of 8 bytes) must stay below 4 GiB
+    big = lib.lb_workspace_bytes(C.byref(B.make_params((1024, 1024, 511), 1.0, 0.08)))
+    assert big >= 2 * 2 * 19 * 1024 * 1024 * 511 * 8
+    for dims in ((1024, 1024, 512), (2 ** 31 - 1, 2 ** 31 - 1, 2 ** 31 - 1), (2 ** 20, 2 ** 20, 3)):
+        assert lib.lb_workspace_bytes(C.byref(B.make_params(dims, 1.0, 0.08))) == 0
     # reduced storage needs less memory
     n16 = lib.lb_workspace_bytes(C.byref(B.make_params((32, 32, 64), 1.0, 0.08, precision="fp16_dev")))
     assert n16 < n / 2
