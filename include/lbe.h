@@ -132,6 +132,16 @@ int lb_read_fields_dev(lb_handle* h, double* dev_rho_a, double* dev_rho_b, doubl
 /* Number of particles on the handle (or a negative error code). */
 int lb_num_particles(const lb_handle* h);
 
+/* Set the motion of particle k (0 <= k < lb_num_particles): velocity V,
+ * angular velocity omega and angular momentum L, all in the space frame (the
+ * rigid-body state of Sec. 2 that the bounce-back of Eq. (4) and the next
+ * body update read). Any of the three may be NULL (left as it is). The body
+ * update recomputes omega from L with the current orientation, so a
+ * consistent state has omega = R I^-1 R^T L. Host arrays of 3 doubles, the
+ * caller's. LB_EINVAL for a bad index or a non-finite value (nothing is
+ * changed then). Synchronises the stream. */
+int lb_set_particle_motion(lb_handle* h, int32_t k, const double* vel, const double* omega, const double* angmom);
+
 /* Particle state, n x 3 (quat n x 4); force / torque are the totals applied in
  * the last rigid-body update (bounce-back sums of Eq. (5) plus kill/fill
  * impulses). Any output may be NULL. Synchronises the stream. */

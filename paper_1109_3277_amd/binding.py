@@ -18,7 +18,7 @@ LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_EUNSTABLE, LB_ESTATE, LB_EGEOM = 0, -1,
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp16_dev": 2, "bf16_dev": 3}
 EXPORTED = [
     "lb_workspace_bytes", "lb_create", "lb_destroy", "lb_init_fields", "lb_add_ellipsoids", "lb_step",
-    "lb_step_async", "lb_read_fields", "lb_read_fields_dev", "lb_num_particles", "lb_read_particles", "lb_stats",
+    "lb_step_async", "lb_read_fields", "lb_read_fields_dev", "lb_num_particles", "lb_read_particles", "lb_set_particle_motion", "lb_stats",
     "lb_set_body_accel", "lb_set_static_solid", "lb_set_pair_interactions", "lb_state_bytes", "lb_save_state", "lb_load_state", "lb_last_error",
     "lb_profile_enable", "lb_profile_read", "lb_batch_workspace_bytes", "lb_create_batch", "lb_init_fields_sys",
     "lb_add_ellipsoids_sys", "lb_read_fields_sys", "lb_read_particles_sys", "lb_stats_sys", "lb_batch_size",
@@ -73,6 +73,7 @@ def load_library():
     L.lb_read_fields_dev.argtypes = [vp, vp, vp, vp, vp]
     L.lb_num_particles.argtypes = [vp]
     L.lb_read_particles.argtypes = [vp, dp, dp, dp, dp, dp, dp]
+    L.lb_set_particle_motion.argtypes = [vp, C.c_int32, dp, dp, dp]
     L.lb_stats.argtypes = [vp, dp]
     L.lb_set_body_accel.argtypes = [vp, dp]
     L.lb_set_static_solid.argtypes = [vp, C.POINTER(C.c_uint8), dp]
@@ -251,6 +252,12 @@ class Lattice:
         self._check(load_library().lb_read_particles(self._h, _dp(out["pos"]), _dp(out["quat"]), _dp(out["vel"]),
                                                      _dp(out["omega"]), _dp(out["force"]), _dp(out["torque"])))
         return out
+
+    def set_particle_motion(self, k, vel=None, omega=None, angmom=None):
+        """Velocity, angular velocity and angular momentum (space frame) of
+        particle k; None leaves that quantity as it is."""
+        args = [None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(3) for a in (vel, omega, angmom)]
+        self._check(load_library().lb_set_particle_motion(self._h, int(k), *[_dp(a) for a in args]))
 
     def stats(self):
         o = np.zeros(8)

@@ -458,6 +458,28 @@ int lb_read_fields_dev(lb_handle* h, double* dev_rho_a, double* dev_rho_b, doubl
 
 int lb_num_particles(const lb_handle* h) { return h ? h->np : LB_EINVAL; }
 
+int lb_set_particle_motion(lb_handle* h, int32_t k, const double* vel, const double* omega, const double* angmom) {
+    if (!h) return LB_EINVAL;
+    LBE_NOT_BATCH(h);
+    if (k < 0 || k >= h->np) return fail(h, LB_EINVAL, "particle index out of range");
+    const double* src[3] = {vel, omega, angmom};
+    const int fld[3] = {VX, WX, LX};
+    double v[9];
+    for (int a = 0; a < 3; a++)
+        for (int d = 0; d < 3; d++) {
+            if (src[a] && !isfinite(src[a][d])) return fail(h, LB_EINVAL, "non-finite particle motion");
+            v[3 * a + d] = src[a] ? src[a][d] : 0.0;
+        }
+    for (int a = 0; a < 3; a++)
+        if (src[a])
+            for (int d = 0; d < 3; d++)
+                LBE_HIP(h, hipMemcpyAsync(h->b.part + (size_t)(fld[a] + d) * h->cap + k, &v[3 * a + d], sizeof(double),
+                                          hipMemcpyHostToDevice, h->stream));
+    LBE_HIP(h, launch_pack_fast(h));
+    LBE_HIP(h, hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
 int lb_read_particles(lb_handle* h, double* pos, double* quat, double* vel, double* omega, double* force,
                       double* torque) {
     if (!h) return LB_EINVAL;

@@ -82,6 +82,7 @@ def test_null_handle_calls_are_rejected(lib):
     from paper_1109_3277_amd import binding as B
     assert lib.lb_step(None, 1) == B.LB_EINVAL
     assert lib.lb_init_fields(None, None, None, None) == B.LB_EINVAL
+    assert lib.lb_set_particle_motion(None, 0, None, None, None) == B.LB_EINVAL
     assert lib.lb_num_particles(None) == B.LB_EINVAL
     lib.lb_destroy(None)
 
