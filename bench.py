@@ -230,6 +230,7 @@ def run_forms(s, workload, steps, warmup, main_prec, main_res, main_fields):
             r, fields = run_gpu(s, prec, steps, warmup, keep_fields=main_fields is not None)
         f = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
              "fused_roofline_frac": roofline_of(s, prec, r, None)["frac"],
+             "fused_traffic_per_launch": measured_traffic(workload, prec),
              "step_alg_gbs": round(r["mlups"] * 1e6 * step_bytes_per_node(prec) / 1e9, 1)}
         if main_fields is not None and prec != "fp64" and main_prec == "fp64":
             f["vs_fp64_after_steps"] = warmup + steps
