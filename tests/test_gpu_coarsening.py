@@ -11,6 +11,7 @@ import pytest
 
 from paper_1109_3277_amd import workloads as W
 from paper_1109_3277_amd.adsorption import fit_line
+from paper_1109_3277_amd.coarsening import history
 from tests.parity_util import log
 
 pytestmark = pytest.mark.gpu
@@ -19,20 +20,7 @@ STEPS, EVERY = 15000, 1500
 
 
 def _history(s, pairs):
-    from paper_1109_3277_amd.binding import Lattice
-
-    g = Lattice(s.dims, s.tau, s.g_br, s.psi_kind, "fp64", max_particles=max(s.n_particles, 2),
-                max_radius=max(s.max_radius, 1.0))
-    g.init_fields(s.rho_a, s.rho_b)
-    if s.n_particles:
-        g.add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, np.full(s.n_particles, 8.0))
-        g.set_pair_interactions(pairs)
-    out = []
-    for t in range(EVERY, STEPS + 1, EVERY):
-        g.step(EVERY)
-        out.append((t, g.domain_size()[3]))
-    g.close()
-    return np.array(out)
+    return history(s, pairs, STEPS, EVERY)[:, [0, 4]]
 
 
 def test_particles_arrest_coarsening_and_size_falls_with_concentration():
