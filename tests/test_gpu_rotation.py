@@ -85,3 +85,27 @@ def test_set_particle_motion_validates():
     p = g.read_particles()
     assert np.array_equal(p["vel"][0], [0.0, 0.0, 0.02]) and np.array_equal(p["omega"], before["omega"])
     g.close()
+
+
+def test_add_ellipsoids_rejects_bad_geometry():
+    """lb_add_ellipsoids refuses, with LB_EGEOM and nothing placed, a radius
+    that is not positive, a bounding radius of half the box or more, and one
+    above the handle's max_radius; a zero quaternion is LB_EINVAL."""
+    from paper_1109_3277_amd.binding import LB_EGEOM, LB_EINVAL, LBError, Lattice
+
+    dims = (16, 16, 20)
+    ra, rb = W.uniform_fields(dims, 5, 0.7, 0.7, 0.01)
+    g = Lattice(dims, 1.0, 0.08, 1, "fp64", max_particles=4, max_radius=7.5)
+    g.init_fields(ra, rb)
+    pos, q = np.array([[8.0, 8.0, 10.0]]), np.array([[1.0, 0.0, 0.0, 0.0]])
+    for radii, quat, code in (([[0.0, 2.0]], q, LB_EGEOM), ([[3.0, -1.0]], q, LB_EGEOM),
+                              ([[8.0, 2.0]], q, LB_EGEOM), ([[2.0, 7.8]], q, LB_EGEOM),
+                              ([[3.0, 2.0]], np.zeros((1, 4)), LB_EINVAL)):
+        with pytest.raises(LBError) as e:
+            g.add_ellipsoids(np.array(radii), pos, quat)
+        assert e.value.code == code, (radii, e.value)
+    assert g.num_particles() == 0
+    g.add_ellipsoids(np.array([[3.0, 2.0]]), pos, q)
+    assert g.num_particles() == 1
+    g.step(2)
+    g.close()
