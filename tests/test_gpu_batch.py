@@ -297,3 +297,37 @@ def test_batch_with_walled_systems_equals_lone_handles():
     for k, g in enumerate(lone):
         assert _same(b[k], g), f"system {k} differs"
     assert np.abs(lone[1].read_particles()["pos"] - part[1]).max() > 0
+
+
+def test_batch_systems_with_set_motion_and_domain_size_equal_lone_handles():
+    """A particle set spinning and moving through lb_set_particle_motion on a
+    system handle of a batch, and lb_domain_size called on the systems between
+    steps: every system ends bit for bit where a lone handle given the same
+    calls ends, and its domain size is bitwise the lone handle's."""
+    from paper_1109_3277_amd.binding import Lattice
+
+    systems = _small_ensemble(3)
+    b = _batch(systems, "fp64")
+    lone = []
+    for s in systems:
+        g = Lattice(s.dims, s.tau, s.g_br, s.psi_kind, "fp64", max_particles=s.n_particles, max_radius=s.max_radius)
+        g.init_fields(s.rho_a, s.rho_b)
+        g.add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
+        lone.append(g)
+    motion = dict(vel=np.array([0.004, -0.002, 0.003]), omega=np.array([0.002, 0.004, -0.003]),
+                  angmom=np.array([5.0, 9.0, -7.0]))
+    for h in [b[k] for k in range(len(systems))] + lone:
+        h.set_particle_motion(0, **motion)
+    b.step(20)
+    for g in lone:
+        g.step(20)
+    for k, g in enumerate(lone):
+        assert np.array_equal(b[k].domain_size(), g.domain_size()), k
+    b.step(15)
+    for g in lone:
+        g.step(15)
+    for k, g in enumerate(lone):
+        assert _same(b[k], g), k
+        log(f"  system {k} {systems[k].dims}: bitwise equal, L = {g.domain_size()[3]:.4f}")
+        g.close()
+    b.close()
