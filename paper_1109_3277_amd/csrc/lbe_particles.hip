@@ -735,9 +735,9 @@ __global__ __launch_bounds__(kPB, 3) void k_killfill_batch(const SysDev* __restr
 
 // ---------------------------------------------------------------- launchers
 
-// Extent of the raster box for bounding radius rb: floor(2 rb) + 1, at most
-// the longest side; the kill/fill union box of a move below two spacings has
-// two more nodes.
+// Largest extent of a raster box for bounding radius rb: floor(2 rb) + 1, at
+// most the longest side; the kill/fill box of a move below two spacings has
+// at most two more nodes (this also sizes the record boxes).
 int raster_extent(int nx, int ny, int nz, double rb) {
     const int L = std::max(nx, std::max(ny, nz));
     return std::min((int)floor(2.0 * rb) + 1, L);
