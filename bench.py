@@ -107,14 +107,17 @@ def run_domain_size(g, s, prec, calls=5):
             "hbm_frac_alg": round(per / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
-def run_gpu(s, prec, steps, warmup, profile_steps=PROFILE_STEPS, keep_fields=False, analysis=False):
+def run_gpu(s, prec, steps, warmup, profile_steps=PROFILE_STEPS, keep_fields=False, analysis=False, pairs=False):
     """Warm-up, then `steps` timed steps with per-kernel profiling off, then
     `profile_steps` steps with HIP events around every launch (per-kernel
     average durations for the roofline); with `analysis`, the domain size of
-    Eq. (12) timed on the final state."""
+    Eq. (12) timed on the final state; with `pairs`, the particle-particle
+    terms of Eqs. (6)-(9) switched on."""
     import torch
 
     g = _lattice(s, prec)
+    if pairs:
+        g.set_pair_interactions(True)
     m0 = g.stats()[:2].copy()
     g.step(warmup)
     torch.cuda.synchronize()
@@ -392,7 +395,7 @@ def main():
     traffic = measured_traffic(args.workload, args.precision)
     roof = roofline_of(s, args.precision, main_res, traffic)
 
-    forms = other = None
+    forms = other = pairs_on = None
     if not args.no_forms:
         forms = run_forms(s, args.workload, args.steps, args.warmup, args.precision, main_res, main_fields)
         log(f"  forms {forms}")
@@ -413,6 +416,13 @@ def main():
                              "phases_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in r["prof"].items()}}
             other[wl] = blk
             log(f"  {wl} {blk}")
+        # the same workload with the particle-particle terms on (the pair
+        # kernels are timed with the link forces, in the "forces" phase)
+        log(f"timing {args.workload} {args.precision} with the pair terms on")
+        r, _ = run_gpu(s, args.precision, 100, args.warmup, pairs=True)
+        pairs_on = {"steps": 100, "mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                    "phases_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in r["prof"].items()}}
+        log(f"  pair terms on {pairs_on}")
 
     batch = None
     if not args.no_batch:
@@ -443,6 +453,7 @@ def main():
         "cpu_baseline": cpu,
         "forms": forms,
         "other_workloads": other,
+        "pair_terms_on": pairs_on,
         "batch": batch,
     }
     print(json.dumps(rec), flush=True)
