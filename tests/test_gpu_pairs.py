@@ -35,7 +35,7 @@ def _dense_contacts(seed=31):
                   rng.uniform(-0.1, 0.1, n), np.full(n, 10.0))
 
 
-def _run(s, steps, u_amp=0.02, seed=7):
+def _run(s, steps, u_amp=0.02, seed=7, precision="fp64"):
     import oracle
     from paper_1109_3277_amd.binding import Lattice
 
@@ -44,7 +44,7 @@ def _run(s, steps, u_amp=0.02, seed=7):
     o.init_fields(s.rho_a, s.rho_b, u)
     o.add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
     o.set_pairs(True, 100.0, 2.0 / 3.0)
-    g = Lattice(s.dims, s.tau, s.g_br, s.psi_kind, "fp64", max_particles=s.n_particles, max_radius=s.max_radius)
+    g = Lattice(s.dims, s.tau, s.g_br, s.psi_kind, precision, max_particles=s.n_particles, max_radius=s.max_radius)
     g.init_fields(s.rho_a, s.rho_b, u)
     g.add_ellipsoids(s.radii, s.pos, s.quat, s.delta_rho, s.density)
     g.set_pair_interactions(True, 100.0, 2.0 / 3.0)
@@ -64,6 +64,14 @@ def test_pairs_dense_contacts_fp64():
     check(res, 1e-12, vel_gate=1e-10)
     # the pair terms moved the particles: the force totals carry them
     assert np.abs(o.read_particles()["vel"]).max() > 1e-4
+
+
+def test_pairs_dense_contacts_fp32():
+    """The same dense contacts with FP32 fluid storage (particle state and
+    the pair terms in FP64), at the FP32 gates."""
+    s = _dense_contacts()
+    o, g, contacts = _run(s, 60, precision="fp32")
+    check(compare(o, g, s.dims, s.radii), 1e-5)
 
 
 def test_pairs_small_box_few_cells_fp64():
